@@ -1,0 +1,337 @@
+"""Seeded synthetic inputs for the periodic RPA hot path.
+
+This module is the one place that both the HIP path (through its tests and the
+benchmark) and the CPU oracle draw their inputs from.  It contains no step of the
+RPA method itself: it only produces the data the method consumes, i.e. band
+energies, the k (+) q index map, the integration weights, the square root of the
+Coulomb matrix V(q), the imaginary-frequency grid and the density-fitted
+transition coefficients B^P_ia(k,q).
+
+Input recipe (the paper's physical systems need DFT data that is not available,
+so slab-shaped synthetic systems of the paper's sizes stand in for them):
+
+* k-grids are regular n1 x n2 x n3 grids in reduced coordinates kappa_d = n_d/N_d,
+  and Q_G equals K_G (regular grids, Sec. "Dual grids", the regular-grid case);
+  k (+) q is index addition modulo the grid in every direction.
+* Band energies: eps0_i ~ U[-1.0,-0.3] Ha (occupied), eps0_a ~ U[0.05,3.0] Ha
+  (virtual), plus a band-independent dispersion 0.1*cos(2 pi (k1+k2+k3)) for
+  periodic systems, so every transition energy is >= 0.15 Ha (insulator, as the
+  polarizability section of the paper assumes).
+* V(q) = Q Lambda Q^H with Q Haar-distributed (QR of a Gaussian matrix with the
+  diagonal phase of R moved into Q) and Lambda = 10^U[-2,1] * f(q); f(q) = 1 for a
+  Gamma-only system, else f(q) = 1 + 1/|q|^2 with |q|^2 = (2 pi)^2 sum kappa_d^2
+  (kappa folded into [-1/2,1/2)), and f(0) = 1 + 1/|q_min|^2 (regularised head).
+  Only V^(1/2) = Q Lambda^(1/2) Q^H is handed over.
+* B^P_ia(k,q) is drawn from Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11)
+  followed by a Box-Muller transform; CN(0, sigma^2) for complex systems
+  (real and imaginary parts each N(0, sigma^2/2)), N(0, sigma^2) for real ones.
+  Stream layout: key = (seed mod 2^32, (seed >> 32) + q*N_k + k mod 2^32),
+  counter = (e mod 2^32, e >> 32, 0, 0) with e = (i*N_virt + a)*N_aux + P.
+  The four output words w0..w3 give two uniforms
+  u = ((w_even >> 6) * 2^26 + (w_odd >> 6) + 1/2) * 2^-52 in (0,1), exactly
+  representable in binary64; r = sqrt(-2 ln u1), theta = 2 pi u2 and
+  B = sigma/sqrt(2) * r * (cos theta + i sin theta) (complex) or
+  B = sigma * r * cos theta (real).  The device generator follows the same
+  definition; the 32-bit words agree bit for bit, the transcendental functions
+  may differ in the last ulp.
+* Frequencies: n-point Gauss-Legendre on x in [0,1], mapped by omega = x/(1-x);
+  the weight carries the Jacobian d omega/dx = 1/(1-x)^2.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+# Philox4x32 constants from the published definition (SC'11): round multipliers
+# and the Weyl key increments.
+PHILOX_M0 = 0xD2511F53
+PHILOX_M1 = 0xCD9E8D57
+PHILOX_W0 = 0x9E3779B9
+PHILOX_W1 = 0xBB67AE85
+_MASK32 = np.uint64(0xFFFFFFFF)
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32 with 10 rounds on arrays.
+
+    ctr: tuple of four uint64 arrays holding 32-bit counter words.
+    key: tuple of two uint64 arrays (or scalars) holding 32-bit key words.
+    Returns four uint64 arrays holding the 32-bit output words.
+    """
+    c0, c1, c2, c3 = (np.asarray(c, dtype=np.uint64) for c in ctr)
+    k0 = np.asarray(key[0], dtype=np.uint64) & _MASK32
+    k1 = np.asarray(key[1], dtype=np.uint64) & _MASK32
+    m0 = np.uint64(PHILOX_M0)
+    m1 = np.uint64(PHILOX_M1)
+    w0 = np.uint64(PHILOX_W0)
+    w1 = np.uint64(PHILOX_W1)
+    s32 = np.uint64(32)
+    for r in range(10):
+        if r:
+            k0 = (k0 + w0) & _MASK32
+            k1 = (k1 + w1) & _MASK32
+        p0 = m0 * c0
+        p1 = m1 * c2
+        hi0, lo0 = p0 >> s32, p0 & _MASK32
+        hi1, lo1 = p1 >> s32, p1 & _MASK32
+        c0, c1, c2, c3 = hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0
+    return c0, c1, c2, c3
+
+
+def philox_key(seed: int, nk: int, iq: int, ik: int):
+    """Key words of the B stream of block (q, k)."""
+    k0 = seed & 0xFFFFFFFF
+    k1 = ((seed >> 32) + iq * nk + ik) & 0xFFFFFFFF
+    return k0, k1
+
+
+def _uniform_pair(wa, wb):
+    x = ((wa >> np.uint64(6)) << np.uint64(26)) | (wb >> np.uint64(6))
+    return (x.astype(np.float64) + 0.5) * 2.0 ** -52
+
+
+def philox_words(seed: int, nk: int, iq: int, ik: int, e0: int, count: int):
+    """Raw Philox words for elements e0..e0+count-1 of block (q, k); shape [count, 4]."""
+    e = np.arange(e0, e0 + count, dtype=np.uint64)
+    k0, k1 = philox_key(seed, nk, iq, ik)
+    zero = np.zeros_like(e)
+    w = philox4x32_10((e & _MASK32, e >> np.uint64(32), zero, zero),
+                      (np.uint64(k0), np.uint64(k1)))
+    return np.stack(w, axis=-1).astype(np.uint32)
+
+
+def philox_B_rows(seed: int, sigma: float, nk: int, iq: int, ik: int,
+                  nvirt: int, naux: int, is_complex: bool, i0: int, i1: int):
+    """B^P_ia(k,q) for occupied rows i0 <= i < i1 of block (q, k).
+
+    Returns an array of shape [i1-i0, nvirt, naux], complex128 or float64.
+    """
+    per_i = nvirt * naux
+    e = np.arange(i0 * per_i, i1 * per_i, dtype=np.uint64)
+    k0, k1 = philox_key(seed, nk, iq, ik)
+    zero = np.zeros_like(e)
+    w0, w1, w2, w3 = philox4x32_10((e & _MASK32, e >> np.uint64(32), zero, zero),
+                                   (np.uint64(k0), np.uint64(k1)))
+    del e, zero
+    u1 = _uniform_pair(w0, w1)
+    u2 = _uniform_pair(w2, w3)
+    del w0, w1, w2, w3
+    r = np.sqrt(-2.0 * np.log(u1))
+    theta = 2.0 * np.pi * u2
+    if is_complex:
+        s = sigma / math.sqrt(2.0)
+        out = np.empty(r.shape, dtype=np.complex128)
+        out.real = s * r * np.cos(theta)
+        out.imag = s * r * np.sin(theta)
+    else:
+        out = sigma * r * np.cos(theta)
+    return out.reshape(i1 - i0, nvirt, naux)
+
+
+def philox_B_block(seed, sigma, nk, iq, ik, nocc, nvirt, naux, is_complex):
+    """Whole block B[k][i][a][P] of one (q, k) pair."""
+    return philox_B_rows(seed, sigma, nk, iq, ik, nvirt, naux, is_complex, 0, nocc)
+
+
+# ----------------------------------------------------------------------------
+# grids, band energies, Coulomb square roots, frequencies
+
+
+def kgrid(grid):
+    """Reduced coordinates [N_k, 3] of a regular grid and the k (+) q map [N_q, N_k]."""
+    n1, n2, n3 = grid
+    idx = np.array([(a, b, c) for a in range(n1) for b in range(n2) for c in range(n3)],
+                   dtype=np.int64)
+    dims = np.array([n1, n2, n3], dtype=np.int64)
+    kappa = idx / dims
+    nk = len(idx)
+    kq = np.empty((nk, nk), dtype=np.int32)
+    for q in range(nk):
+        s = (idx + idx[q]) % dims
+        kq[q] = s[:, 0] * n2 * n3 + s[:, 1] * n3 + s[:, 2]
+    return kappa, kq
+
+
+def qnorm2(kappa):
+    """|q|^2 with the reduced coordinates folded into [-1/2, 1/2) (lattice constant 1)."""
+    f = (kappa + 0.5) % 1.0 - 0.5
+    return (2.0 * np.pi) ** 2 * np.sum(f * f, axis=-1)
+
+
+def haar_unitary(rng, n, is_complex):
+    """Haar-distributed orthogonal / unitary matrix (Mezzadri's QR recipe)."""
+    if is_complex:
+        z = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / math.sqrt(2.0)
+    else:
+        z = rng.standard_normal((n, n))
+    q, r = np.linalg.qr(z)
+    d = np.diagonal(r)
+    ph = d / np.abs(d)
+    return q * ph[None, :]
+
+
+def coulomb_sqrt(rng, naux, kappa, is_complex, periodic):
+    """V^(1/2)(q) for every q of the grid: [N_q, naux, naux]."""
+    nq = len(kappa)
+    if periodic:
+        q2 = qnorm2(kappa)
+        nz = q2[q2 > 0]
+        q2min = nz.min() if len(nz) else 1.0
+        q2 = np.where(q2 > 0, q2, q2min)
+        f = 1.0 + 1.0 / q2
+    else:
+        f = np.ones(nq)
+    dt = np.complex128 if is_complex else np.float64
+    out = np.empty((nq, naux, naux), dtype=dt)
+    for iq in range(nq):
+        Q = haar_unitary(rng, naux, is_complex)
+        lam = 10.0 ** rng.uniform(-2.0, 1.0, size=naux) * f[iq]
+        vh = (Q * np.sqrt(lam)[None, :]) @ Q.conj().T
+        out[iq] = 0.5 * (vh + vh.conj().T)
+    return out
+
+
+def frequency_grid(nw):
+    """Gauss-Legendre nodes on [0,1] mapped to omega = x/(1-x); weights include d omega/dx."""
+    t, g = np.polynomial.legendre.leggauss(nw)
+    x = 0.5 * (1.0 + t)
+    omega = x / (1.0 - x)
+    weight = 0.5 * g / (1.0 - x) ** 2
+    return omega.astype(np.float64), weight.astype(np.float64)
+
+
+@dataclasses.dataclass
+class System:
+    """One synthetic periodic system plus its frequency grid."""
+    name: str
+    grid: tuple
+    nk: int
+    nq: int
+    nocc: int
+    nvirt: int
+    naux: int
+    is_complex: bool
+    kq: np.ndarray          # int32 [nq][nk]
+    eps_occ: np.ndarray     # f64 [nk][nocc]
+    eps_virt: np.ndarray    # f64 [nk][nvirt]
+    zeta_k: np.ndarray      # f64 [nk]
+    zeta_q: np.ndarray      # f64 [nq]
+    vhalf: np.ndarray       # [nq][naux][naux]
+    omega: np.ndarray       # f64 [nw]
+    weight: np.ndarray      # f64 [nw]
+    seed: int
+    sigma: float
+    B: Optional[np.ndarray] = None   # explicit [nq][nk][nocc][nvirt][naux] or None (Philox)
+
+    @property
+    def nw(self):
+        return len(self.omega)
+
+    @property
+    def M(self):
+        return self.nk * self.nocc * self.nvirt
+
+    def B_rows(self, iq, ik, i0, i1):
+        """B[q][k][i0:i1] from the explicit array or the Philox stream."""
+        if self.B is not None:
+            return self.B[iq, ik, i0:i1]
+        return philox_B_rows(self.seed, self.sigma, self.nk, iq, ik, self.nvirt,
+                             self.naux, self.is_complex, i0, i1)
+
+    def B_block(self, iq, ik):
+        return self.B_rows(iq, ik, 0, self.nocc)
+
+    def materialize_B(self):
+        """Attach the explicit B array (small systems only)."""
+        dt = np.complex128 if self.is_complex else np.float64
+        B = np.empty((self.nq, self.nk, self.nocc, self.nvirt, self.naux), dtype=dt)
+        for iq in range(self.nq):
+            for ik in range(self.nk):
+                B[iq, ik] = philox_B_block(self.seed, self.sigma, self.nk, iq, ik,
+                                           self.nocc, self.nvirt, self.naux, self.is_complex)
+        self.B = B
+        return self
+
+
+def make_system(name, grid, nocc, nvirt, naux, nw, seed, is_complex=True, sigma=None,
+                periodic=None, vhalf_seed=None):
+    """Build a seeded synthetic system.
+
+    sigma defaults to sqrt(1.61/(nocc*nvirt)), which keeps sigma^2*nocc*nvirt at the value
+    of the 3x3x1, N_aux = 384 system (0.03^2 * 16 * 112) for every size.
+    """
+    kappa, kq = kgrid(grid)
+    nk = len(kappa)
+    if periodic is None:
+        periodic = nk > 1
+    if sigma is None:
+        sigma = math.sqrt(1.61 / (nocc * nvirt))
+    rng = np.random.default_rng(seed)
+    e0_occ = rng.uniform(-1.0, -0.3, size=nocc)
+    e0_virt = rng.uniform(0.05, 3.0, size=nvirt)
+    if periodic:
+        disp = 0.1 * np.cos(2.0 * np.pi * kappa.sum(axis=1))
+    else:
+        disp = np.zeros(nk)
+    eps_occ = e0_occ[None, :] + disp[:, None]
+    eps_virt = e0_virt[None, :] + disp[:, None]
+    vrng = np.random.default_rng(seed + 7919 if vhalf_seed is None else vhalf_seed)
+    vhalf = coulomb_sqrt(vrng, naux, kappa, is_complex, periodic)
+    omega, weight = frequency_grid(nw)
+    return System(name=name, grid=tuple(grid), nk=nk, nq=nk, nocc=nocc, nvirt=nvirt,
+                  naux=naux, is_complex=bool(is_complex), kq=kq,
+                  eps_occ=np.ascontiguousarray(eps_occ), eps_virt=np.ascontiguousarray(eps_virt),
+                  zeta_k=np.full(nk, 1.0 / nk), zeta_q=np.full(nk, 1.0 / nk),
+                  vhalf=vhalf, omega=omega, weight=weight, seed=int(seed), sigma=float(sigma))
+
+
+# The five workloads of the benchmark plan, by what they are.
+def gamma_real_128(seed=1234):
+    """Gamma-only real system: N_occ 8, N_virt 56, N_aux 128, 8 frequencies, B ~ N(0, 0.05^2)."""
+    return make_system("gamma_real_naux128", (1, 1, 1), 8, 56, 128, 8, seed,
+                       is_complex=False, sigma=0.05, periodic=False)
+
+
+def slab_3x3_384(seed=2025):
+    """3x3x1 slab, N_occ 16, N_virt 112, N_aux 384, 12 frequencies, B ~ CN(0, 0.03^2)."""
+    return make_system("slab3x3_naux384", (3, 3, 1), 16, 112, 384, 12, seed,
+                       is_complex=True, sigma=0.03)
+
+
+def slab_6x6_1200(seed=4242):
+    """6x6x1 slab, N_occ 48, N_virt 400, N_aux 1200, 16 frequencies (B streamed)."""
+    return make_system("slab6x6_naux1200", (6, 6, 1), 48, 400, 1200, 16, seed)
+
+
+def slab_3x3_2400(seed=9001):
+    """3x3x1 slab, N_occ 96, N_virt 900, N_aux 2400, 16 frequencies (B streamed)."""
+    return make_system("slab3x3_naux2400", (3, 3, 1), 96, 900, 2400, 16, seed)
+
+
+def serving_jobs(njobs=256, rate=4.0, seed=77, naux_range=(200, 1500)):
+    """Job stream of the serving workload: Poisson arrivals, log-uniform N_aux.
+
+    Returns a list of dicts with arrival time (s) and the job's sizes and seed;
+    call make_job_system(job) to build its inputs.
+    """
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    jobs = []
+    grids = [(1, 1, 1), (2, 2, 1), (3, 3, 1)]
+    for j in range(njobs):
+        t += rng.exponential(1.0 / rate)
+        naux = int(round(math.exp(rng.uniform(math.log(naux_range[0]), math.log(naux_range[1])))))
+        g = grids[int(rng.integers(0, 3))]
+        nw = int(rng.integers(8, 17))
+        jobs.append(dict(id=j, arrival=t, naux=naux, nocc=max(1, round(naux / 12)),
+                         nvirt=max(1, round(naux / 1.5)), grid=g, nw=nw,
+                         seed=int(rng.integers(1, 2 ** 31))))
+    return jobs
+
+
+def make_job_system(job):
+    return make_system(f"job{job['id']}", job["grid"], job["nocc"], job["nvirt"], job["naux"],
+                       job["nw"], job["seed"], is_complex=True)
