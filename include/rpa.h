@@ -1,0 +1,197 @@
+/*
+ * rpa.h -- C-ABI of the MI355X periodic RPA hot path (librpa.so, gfx950).
+ *
+ * The library evaluates the RPA correlation energy per unit cell of a periodic
+ * insulator in a density-fitting (auxiliary) basis, following arXiv:2505.06021
+ * (Spadetto, Philipsen, Foerster, Visscher):
+ *
+ *   chi0_PQ(q, i w) = sum_k zeta_k sum_ia conj(B^P_ia(k,q)) w_ia(w) B^Q_ia(k,q)
+ *       with w_ia(w) = -4 Delta / (Delta^2 + w^2), Delta = eps_a(k) - eps_i(k (+) q)
+ *       (Sec. 2.2, the fit-basis polarizability equation; the -2 is the closed-shell
+ *        occupation factor and the complex-conjugate term doubles the real part)
+ *   Pi  = V^(1/2) chi0 V^(1/2)                 (working equation; Algorithm 1)
+ *   eps(q, w) = ln det(1 - Pi) + Re Tr Pi      (Eq. 1 summed as -ln(1 - Z) - Z)
+ *   E   = sum_q zeta_q sum_j W_j eps(q, w_j) / (2 pi)
+ *                                               (Eq. 1 with the main-loop quadrature)
+ *
+ * Conventions for every entry point:
+ *  - Return value: RPA_OK (0) on success, RPA_PENDING (1) from rpa_poll while a job runs,
+ *    a negative rpa_status otherwise.  Nothing aborts or throws across the ABI;
+ *    rpa_last_error() gives a message for the calling thread's last failure.
+ *  - Complex arrays are interleaved (re, im) binary64 pairs, row-major.
+ *    Real systems (is_complex = 0) use plain binary64 arrays of the same shape.
+ *  - memspace says where the caller's array pointers live: RPA_MEM_HOST (pageable or
+ *    pinned host memory) or RPA_MEM_DEVICE (device memory of the context's GPU).
+ *    Device-side work runs on the context's stream (rpa_set_stream); synchronous
+ *    entry points return after that stream has finished the call's work.
+ *  - Inputs are borrowed for the duration of a synchronous call; the library keeps
+ *    no pointer to them afterwards.  Outputs are written to caller buffers.
+ *  - A context is safe to use from several threads; calls are serialised inside.
+ */
+#ifndef RPA_H
+#define RPA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum rpa_status {
+  RPA_OK = 0,
+  RPA_PENDING = 1,
+  RPA_E_ARG = -1,          /* invalid argument, shape or null pointer                  */
+  RPA_E_NOMEM = -2,        /* request exceeds the context's HBM limit                  */
+  RPA_E_DEVICE = -3,       /* HIP runtime or launch error                              */
+  RPA_E_NOTSPD = -4,       /* 1 - Pi is not Hermitian positive definite (Cholesky fails) */
+  RPA_E_UNKNOWN_JOB = -5,  /* job id never issued or already consumed                  */
+  RPA_E_INTERNAL = -6,
+  RPA_E_CANCELLED = -7     /* job cancelled by rpa_finalize                            */
+};
+
+/* Arithmetic of the chi0 contraction; Pi, the Cholesky/log-det and the sums are FP64. */
+typedef enum {
+  RPA_FP64 = 0,      /* FP64 MFMA                                                      */
+  RPA_FP32 = 1,      /* FP32 MFMA, FP64 flush of partial sums, exact FP64 diagonal     */
+  RPA_BF16X3 = 2     /* split-BF16 (hi*hi + hi*lo + lo*hi) on MFMA, FP32 accumulate,
+                        FP64 flush of partial sums, exact FP64 diagonal                */
+} rpa_precision;
+
+typedef enum { RPA_MEM_HOST = 0, RPA_MEM_DEVICE = 1 } rpa_memspace;
+
+typedef struct rpa_ctx rpa_ctx;
+
+/*
+ * One periodic system (Algorithm 1, "Require: C, eps_n"): regular grids with N_q = N_k.
+ *  kq        [nq][nk]  int32: index of k (+) q in the k list.
+ *  eps_occ   [nk][nocc], eps_virt [nk][nvirt]: Kohn-Sham band energies (Hartree).
+ *  zeta_k    [nk], zeta_q [nq]: integration weights; NULL means 1/nk and 1/nq.
+ *  B         [nq][nk][nocc][nvirt][naux]: fit coefficients B^P_ia(k,q), P fastest
+ *            (the MO-basis PADF coefficients of Sec. 2.2).  NULL means: generate them
+ *            on the device from Philox4x32-10 with philox_seed and sigma (the stream
+ *            definition is that of rpa_philox_B).
+ *  vhalf     [nq][naux][naux]: V^(1/2)(q), Hermitian (symmetric if real).
+ * All arrays live in `memspace`.
+ */
+typedef struct {
+  int32_t nk, nq, nocc, nvirt, naux, is_complex;
+  int32_t memspace;
+  const int32_t *kq;
+  const double *eps_occ;
+  const double *eps_virt;
+  const double *zeta_k;
+  const double *zeta_q;
+  const void *B;
+  uint64_t philox_seed;
+  double sigma;
+  const void *vhalf;
+} rpa_system;
+
+/* Imaginary-frequency quadrature (host memory): nodes omega_j and weights W_j that
+ * already include d omega / dx of the node map.  The 1/(2 pi) of Eq. 1 is applied
+ * by the library. */
+typedef struct {
+  int32_t nw;
+  const double *omega;
+  const double *weight;
+} rpa_freq;
+
+/* Final record of a submitted job (times in seconds on the library's monotonic clock). */
+typedef struct {
+  double E;
+  int32_t status;
+  int32_t npoints;
+  double t_submit, t_start, t_done;
+  int64_t hbm_bytes;     /* device bytes the job held while running */
+} rpa_result;
+
+typedef struct {
+  int64_t hbm_limit, hbm_in_use, hbm_high_water;
+  int64_t jobs_submitted, jobs_done, jobs_running, jobs_queued;
+} rpa_stats;
+
+/* Create a context on HIP device `device`.  hbm_limit_bytes caps the device memory the
+ * context may hold (0 = 90% of the device memory free at creation).  Errors: RPA_E_ARG
+ * (ctx NULL, bad device), RPA_E_DEVICE. */
+int rpa_init(rpa_ctx **ctx, int device, uint64_t hbm_limit_bytes);
+
+/* Cancel queued jobs, wait for running ones, free all device memory, destroy ctx. */
+int rpa_finalize(rpa_ctx *ctx);
+
+/* Message of the calling thread's last error ("" if none).  ctx may be NULL. */
+const char *rpa_last_error(const rpa_ctx *ctx);
+
+/* Use `hip_stream` (a hipStream_t, NULL = the context's own stream) for the context's
+ * synchronous device work, e.g. torch.cuda.current_stream().cuda_stream. */
+int rpa_set_stream(rpa_ctx *ctx, void *hip_stream);
+
+/* chi0(q = iq, i omega) of Sec. 2.2 into chi0 [naux][naux] (complex, or real if
+ * is_complex = 0), in sys->memspace.  The full Hermitian matrix is written.
+ * Errors: RPA_E_ARG, RPA_E_NOMEM, RPA_E_DEVICE. */
+int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega,
+             rpa_precision prec, void *chi0);
+
+/* Pi = V^(1/2) chi0 V^(1/2) (Algorithm 1, "Z = V^0.5 P V^0.5") for one n x n pair, all
+ * arrays [n][n] in `memspace`; Pi is written in full.  Errors: RPA_E_ARG, RPA_E_NOMEM,
+ * RPA_E_DEVICE. */
+int rpa_pi(rpa_ctx *ctx, int32_t n, int32_t is_complex, int32_t memspace,
+           const void *vhalf, const void *chi0, void *pi);
+
+/* eps_b = ln det(1 - Pi_b) + Re Tr Pi_b for `batch` matrices Pi [batch][n][n] (only the
+ * lower triangle is read), through a Cholesky factor of 1 - Pi (the log-det step of
+ * Algorithm 1 with the sign of Eq. 1).  out [batch] doubles; all in `memspace`.
+ * Errors: RPA_E_NOTSPD if some 1 - Pi_b is not positive definite (the message names b
+ * and the failing column), RPA_E_ARG, RPA_E_NOMEM, RPA_E_DEVICE. */
+int rpa_trln(rpa_ctx *ctx, int32_t n, int32_t batch, int32_t is_complex, int32_t memspace,
+             const void *pi, double *out);
+
+/* RPA correlation energy per cell: E (host double) and, if eps_qw != NULL, the integrand
+ * eps(q, omega_j) [nq][nw] (host memory).  All steps run on the GPU; the q/omega sum is
+ * taken on the device in a fixed order (q outer, omega inner).
+ * Errors: RPA_E_ARG, RPA_E_NOMEM, RPA_E_NOTSPD, RPA_E_DEVICE. */
+int rpa_energy(rpa_ctx *ctx, const rpa_system *sys, const rpa_freq *freq,
+               rpa_precision prec, double *E, double *eps_qw);
+
+/* Same as rpa_energy for a subset of points only: eps[p] = eps(q = iq[p], omega = w[p]).
+ * iq, w and eps are host arrays of npts entries.  Errors as rpa_energy. */
+int rpa_points(rpa_ctx *ctx, const rpa_system *sys, int32_t npts, const int32_t *iq,
+               const double *w, rpa_precision prec, double *eps);
+
+/* Device Philox generator of the fit coefficients of block (q = iq, k = ik):
+ * out [nocc][nvirt][naux] in `memspace`.  Stream: Philox4x32-10 (Salmon et al., SC'11)
+ * with key (seed mod 2^32, (seed >> 32) + iq*nk + ik mod 2^32) and counter
+ * (e mod 2^32, e >> 32, 0, 0), e = (i*nvirt + a)*naux + P; the words w0..w3 give
+ * u = ((w_even >> 6) * 2^26 + (w_odd >> 6) + 1/2) * 2^-52 and Box-Muller in FP64:
+ * B = sigma/sqrt(2) * sqrt(-2 ln u1) * (cos 2 pi u2 + i sin 2 pi u2), or
+ * sigma * sqrt(-2 ln u1) * cos 2 pi u2 for real systems.  Errors: RPA_E_ARG, RPA_E_DEVICE. */
+int rpa_philox_B(rpa_ctx *ctx, uint64_t seed, double sigma, int32_t nk, int32_t iq,
+                 int32_t ik, int32_t nocc, int32_t nvirt, int32_t naux, int32_t is_complex,
+                 int32_t memspace, void *out);
+
+/* The raw 32-bit Philox words of elements e0 .. e0+count-1 of block (iq, ik):
+ * out [count][4] uint32 in `memspace`. */
+int rpa_philox_words(rpa_ctx *ctx, uint64_t seed, int32_t nk, int32_t iq, int32_t ik,
+                     uint64_t e0, int64_t count, int32_t memspace, uint32_t *out);
+
+/* Serving (continuous batching).  rpa_submit copies every input it needs (B must be
+ * NULL, i.e. Philox-generated, or host memory) and returns at once with a job id.
+ * A scheduler thread admits queued jobs while their projected device memory fits
+ * under the HBM limit, and runs the (q, omega) points of all admitted jobs through
+ * shared kernel launches.  A job that can never fit fails at submit with RPA_E_NOMEM.
+ * rpa_poll waits up to timeout_ms (0 = do not wait, < 0 = forever) and returns
+ * RPA_PENDING, or the job's final status with *out filled and, if eps_qw != NULL,
+ * its [nq][nw] integrand; a finished job is consumed by the successful poll.
+ * Errors: RPA_E_ARG, RPA_E_NOMEM, RPA_E_UNKNOWN_JOB, or the job's own error. */
+int rpa_submit(rpa_ctx *ctx, const rpa_system *sys, const rpa_freq *freq,
+               rpa_precision prec, uint64_t *job_id);
+int rpa_poll(rpa_ctx *ctx, uint64_t job_id, int32_t timeout_ms, rpa_result *out,
+             double *eps_qw);
+
+/* Counters of the context (device memory, jobs). */
+int rpa_get_stats(rpa_ctx *ctx, rpa_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPA_H */

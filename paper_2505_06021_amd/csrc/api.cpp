@@ -1,0 +1,373 @@
+// extern "C" entry points of librpa (declared in include/rpa.h).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "runtime.hpp"
+#include "scheduler.hpp"
+
+using namespace rpa;
+
+namespace {
+
+int check_ctx(rpa_ctx *ctx) {
+  if (!ctx) return fail(RPA_E_ARG, "ctx is NULL");
+  return RPA_OK;
+}
+
+int set_device(Ctx &c) {
+  RPA_HIP(hipSetDevice(c.device));
+  return RPA_OK;
+}
+
+int64_t budget_of(Ctx &c) {
+  std::lock_guard<std::mutex> g(c.mem_mu);
+  // the synchronous path may reuse its own cached workspaces, so count them as available
+  int64_t cached = 0;
+  for (auto &kv : c.cache) cached += kv.second.bytes;
+  return c.hbm_limit - c.in_use + cached;
+}
+
+// Copy `bytes` between a caller array in `memspace` and a device buffer.
+int to_device(void *dst, const void *src, size_t bytes, int memspace, hipStream_t s) {
+  RPA_HIP(hipMemcpyAsync(dst, src, bytes,
+                         memspace == RPA_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
+  return RPA_OK;
+}
+int from_device(void *dst, const void *src, size_t bytes, int memspace, hipStream_t s) {
+  RPA_HIP(hipMemcpyAsync(dst, src, bytes,
+                         memspace == RPA_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
+  return RPA_OK;
+}
+
+// Stage n*n real or complex caller data as complex on the device (widening real input).
+int stage_complex(Ctx &c, const char *name, const void *src, int64_t count, int is_complex,
+                  int memspace, double2 **out) {
+  void *buf;
+  RPA_TRY(c.workspace(name, count * 16, &buf));
+  if (is_complex) {
+    RPA_TRY(to_device(buf, src, (size_t)count * 16, memspace, c.stream));
+  } else {
+    void *tmp;
+    std::string tname = std::string(name) + "_real";
+    RPA_TRY(c.workspace(tname.c_str(), count * 8, &tmp));
+    RPA_TRY(to_device(tmp, src, (size_t)count * 8, memspace, c.stream));
+    RPA_HIP(launch_widen(c.stream, (const double *)tmp, (double2 *)buf, count));
+  }
+  *out = (double2 *)buf;
+  return RPA_OK;
+}
+
+// Write a complex device result to the caller (narrowing to real if needed).
+int deliver_complex(Ctx &c, void *dst, const double2 *src, int64_t count, int is_complex, int memspace) {
+  if (is_complex) {
+    RPA_TRY(from_device(dst, src, (size_t)count * 16, memspace, c.stream));
+  } else {
+    void *tmp;
+    RPA_TRY(c.workspace("deliver_real", count * 8, &tmp));
+    RPA_HIP(launch_narrow(c.stream, src, (double *)tmp, count));
+    RPA_TRY(from_device(dst, tmp, (size_t)count * 8, memspace, c.stream));
+  }
+  return RPA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rpa_init(rpa_ctx **out, int device, uint64_t hbm_limit_bytes) {
+  if (!out) return fail(RPA_E_ARG, "ctx pointer is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  RPA_HIP(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(RPA_E_ARG, "device %d not in [0, %d)", device, ndev);
+  RPA_HIP(hipSetDevice(device));
+  size_t free_b = 0, total_b = 0;
+  RPA_HIP(hipMemGetInfo(&free_b, &total_b));
+  rpa_ctx *ctx = new (std::nothrow) rpa_ctx();
+  if (!ctx) return fail(RPA_E_NOMEM, "host allocation of the context failed");
+  Ctx &c = ctx->c;
+  c.device = device;
+  c.hbm_limit = hbm_limit_bytes ? (int64_t)hbm_limit_bytes : (int64_t)(0.9 * (double)free_b);
+  hipError_t e = hipStreamCreateWithFlags(&c.own_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete ctx;
+    return fail(RPA_E_DEVICE, "hipStreamCreate failed: %s", hipGetErrorString(e));
+  }
+  c.stream = c.own_stream;
+  c.sched.reset(new Scheduler(c));
+  *out = ctx;
+  return RPA_OK;
+}
+
+int rpa_finalize(rpa_ctx *ctx) {
+  RPA_TRY(check_ctx(ctx));
+  Ctx &c = ctx->c;
+  (void)hipSetDevice(c.device);
+  if (c.sched) c.sched->shutdown();
+  c.sched.reset();
+  {
+    std::lock_guard<std::mutex> g(c.mu);
+    (void)hipStreamSynchronize(c.stream);
+    c.free_cache();
+  }
+  if (c.own_stream) (void)hipStreamDestroy(c.own_stream);
+  delete ctx;
+  return RPA_OK;
+}
+
+const char *rpa_last_error(const rpa_ctx *) { return last_error(); }
+
+int rpa_set_stream(rpa_ctx *ctx, void *hip_stream) {
+  RPA_TRY(check_ctx(ctx));
+  std::lock_guard<std::mutex> g(ctx->c.mu);
+  ctx->c.stream = hip_stream ? (hipStream_t)hip_stream : ctx->c.own_stream;
+  return RPA_OK;
+}
+
+int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega, rpa_precision prec,
+             void *chi0) {
+  RPA_TRY(check_ctx(ctx));
+  Ctx &c = ctx->c;
+  std::lock_guard<std::mutex> g(c.mu);
+  RPA_TRY(set_device(c));
+  HostSmall hs;
+  RPA_TRY(validate_system(sys, hs));
+  if (!chi0) return fail(RPA_E_ARG, "chi0 output is NULL");
+  if (iq < 0 || iq >= hs.nq) return fail(RPA_E_ARG, "iq = %d outside [0, nq)", iq);
+  if (!std::isfinite(omega) || omega < 0.0) return fail(RPA_E_ARG, "omega must be finite and >= 0");
+  if (prec != RPA_FP64 && prec != RPA_FP32 && prec != RPA_BF16X3)
+    return fail(RPA_E_ARG, "unknown precision %d", (int)prec);
+  const int N = hs.naux;
+  const int64_t M = (int64_t)hs.nk * hs.nocc * hs.nvirt;
+  const bool cplx = hs.is_complex != 0;
+  const int64_t belem = cplx ? 16 : 8;
+  const void *B = sys->B;
+  if (!B || sys->memspace == RPA_MEM_HOST) {
+    void *buf;
+    RPA_TRY(c.workspace("B", M * N * belem, &buf));
+    if (!B) {
+      RPA_HIP(launch_philox_B(c.stream, sys->philox_seed, sys->sigma, hs.nk, iq, 0, hs.nk, hs.nocc,
+                              hs.nvirt, N, cplx, buf));
+    } else {
+      RPA_HIP(hipMemcpyAsync(buf, (const char *)B + (int64_t)iq * M * N * belem, (size_t)(M * N * belem),
+                             hipMemcpyHostToDevice, c.stream));
+    }
+    B = buf;
+  } else {
+    B = (const char *)B + (int64_t)iq * M * N * belem;
+  }
+  // eps_occ | eps_virt | zeta_k | kq | (pad to 16) | PointDesc, one upload
+  const int64_t nsmall = (int64_t)(hs.eps_occ.size() + hs.eps_virt.size() + hs.zeta_k.size());
+  const int64_t pd_off = ((nsmall * 8 + (int64_t)hs.kq.size() * 4) + 15) / 16 * 16;
+  std::vector<char> hsm((size_t)(pd_off + (int64_t)sizeof(PointDesc)));
+  char *hp = hsm.data();
+  memcpy(hp, hs.eps_occ.data(), hs.eps_occ.size() * 8);
+  memcpy(hp + hs.eps_occ.size() * 8, hs.eps_virt.data(), hs.eps_virt.size() * 8);
+  memcpy(hp + (hs.eps_occ.size() + hs.eps_virt.size()) * 8, hs.zeta_k.data(), hs.zeta_k.size() * 8);
+  memcpy(hp + nsmall * 8, hs.kq.data(), hs.kq.size() * 4);
+  PointDesc pd{iq, 0, omega};
+  memcpy(hp + pd_off, &pd, sizeof(pd));
+  void *d_all;
+  RPA_TRY(c.workspace("chi0_args", (int64_t)hsm.size() + 64, &d_all));
+  RPA_HIP(hipMemcpyAsync(d_all, hsm.data(), hsm.size(), hipMemcpyHostToDevice, c.stream));
+  char *da = (char *)d_all;
+  double2 *out;
+  const bool direct = cplx && sys->memspace == RPA_MEM_DEVICE;
+  if (direct) out = (double2 *)chi0;
+  else RPA_TRY(c.workspace("chi0_out", (int64_t)N * N * 16, (void **)&out));
+  Chi0Args a{};
+  a.B = B;
+  a.b_slot_stride = 0;
+  a.eps_occ = (const double *)da;
+  a.eps_virt = (const double *)(da + hs.eps_occ.size() * 8);
+  a.zeta_k = (const double *)(da + (hs.eps_occ.size() + hs.eps_virt.size()) * 8);
+  a.kq = (const int32_t *)(da + nsmall * 8);
+  a.pts = (const PointDesc *)(da + pd_off);
+  a.out = out;
+  a.out_stride = 0;
+  a.nk = hs.nk; a.nocc = hs.nocc; a.nvirt = hs.nvirt; a.N = N; a.M = M;
+  if (prec != RPA_FP64) return fail(RPA_E_ARG, "precision %d not available in this path", (int)prec);
+  RPA_HIP(launch_chi0_f64(c.stream, a, 1, cplx));
+  if (!direct) RPA_TRY(deliver_complex(c, chi0, out, (int64_t)N * N, hs.is_complex, sys->memspace));
+  RPA_HIP(hipStreamSynchronize(c.stream));
+  return RPA_OK;
+}
+
+int rpa_pi(rpa_ctx *ctx, int32_t n, int32_t is_complex, int32_t memspace, const void *vhalf,
+           const void *chi0, void *pi) {
+  RPA_TRY(check_ctx(ctx));
+  Ctx &c = ctx->c;
+  std::lock_guard<std::mutex> g(c.mu);
+  RPA_TRY(set_device(c));
+  if (n < 1 || n > 16384) return fail(RPA_E_ARG, "n = %d out of range", n);
+  if (is_complex != 0 && is_complex != 1) return fail(RPA_E_ARG, "is_complex must be 0 or 1");
+  if (memspace != RPA_MEM_HOST && memspace != RPA_MEM_DEVICE) return fail(RPA_E_ARG, "bad memspace");
+  if (!vhalf || !chi0 || !pi) return fail(RPA_E_ARG, "NULL array");
+  const int64_t nn = (int64_t)n * n;
+  double2 *dv, *dc, *dt, *dp;
+  RPA_TRY(stage_complex(c, "pi_v", vhalf, nn, is_complex, memspace, &dv));
+  RPA_TRY(stage_complex(c, "pi_c", chi0, nn, is_complex, memspace, &dc));
+  RPA_TRY(c.workspace("pi_t", nn * 16, (void **)&dt));
+  RPA_TRY(c.workspace("pi_p", nn * 16, (void **)&dp));
+  GemmArgs g1{};
+  g1.A = dc; g1.a_div = 1; g1.B = dv; g1.b_div = 1; g1.C = dt; g1.N = n;
+  RPA_HIP(launch_zgemm_f64(c.stream, g1, 1));
+  GemmArgs g2{};
+  g2.A = dv; g2.a_div = 1; g2.B = dt; g2.b_div = 1; g2.C = dp; g2.N = n;
+  RPA_HIP(launch_zgemm_f64(c.stream, g2, 1));
+  RPA_TRY(deliver_complex(c, pi, dp, nn, is_complex, memspace));
+  RPA_HIP(hipStreamSynchronize(c.stream));
+  return RPA_OK;
+}
+
+int rpa_trln(rpa_ctx *ctx, int32_t n, int32_t batch, int32_t is_complex, int32_t memspace,
+             const void *pi, double *out) {
+  RPA_TRY(check_ctx(ctx));
+  Ctx &c = ctx->c;
+  std::lock_guard<std::mutex> g(c.mu);
+  RPA_TRY(set_device(c));
+  if (n < 1 || n > 16384) return fail(RPA_E_ARG, "n = %d out of range", n);
+  if (batch < 0 || batch > (1 << 20)) return fail(RPA_E_ARG, "batch = %d out of range", batch);
+  if (is_complex != 0 && is_complex != 1) return fail(RPA_E_ARG, "is_complex must be 0 or 1");
+  if (memspace != RPA_MEM_HOST && memspace != RPA_MEM_DEVICE) return fail(RPA_E_ARG, "bad memspace");
+  if (batch == 0) return RPA_OK;
+  if (!pi || !out) return fail(RPA_E_ARG, "NULL array");
+  const int64_t nn = (int64_t)n * n;
+  double2 *dp;
+  RPA_TRY(stage_complex(c, "trln_pi", pi, nn * batch, is_complex, memspace, &dp));
+  double *de;
+  int32_t *di;
+  RPA_TRY(c.workspace("trln_eps", (int64_t)batch * 8, (void **)&de));
+  RPA_TRY(c.workspace("trln_info", (int64_t)batch * 4, (void **)&di));
+  RPA_HIP(launch_trln_f64(c.stream, dp, nn, n, batch, de, di, nullptr));
+  std::vector<int32_t> info((size_t)batch);
+  RPA_HIP(hipMemcpyAsync(info.data(), di, (size_t)batch * 4, hipMemcpyDeviceToHost, c.stream));
+  RPA_TRY(from_device(out, de, (size_t)batch * 8, memspace, c.stream));
+  RPA_HIP(hipStreamSynchronize(c.stream));
+  for (int b = 0; b < batch; ++b)
+    if (info[b] >= 0)
+      return fail(RPA_E_NOTSPD, "1 - Pi is not positive definite for matrix %d (column %d)", b, info[b]);
+  return RPA_OK;
+}
+
+int rpa_energy(rpa_ctx *ctx, const rpa_system *sys, const rpa_freq *freq, rpa_precision prec,
+               double *E, double *eps_qw) {
+  RPA_TRY(check_ctx(ctx));
+  Ctx &c = ctx->c;
+  std::lock_guard<std::mutex> g(c.mu);
+  RPA_TRY(set_device(c));
+  HostSmall hs;
+  RPA_TRY(validate_system(sys, hs));
+  RPA_TRY(validate_freq(freq));
+  if (!E) return fail(RPA_E_ARG, "E is NULL");
+  if (prec != RPA_FP64 && prec != RPA_FP32 && prec != RPA_BF16X3)
+    return fail(RPA_E_ARG, "unknown precision %d", (int)prec);
+  PointJob job;
+  job.sys = sys;
+  job.hs = &hs;
+  job.prec = prec;
+  for (int q = 0; q < hs.nq; ++q)
+    for (int j = 0; j < freq->nw; ++j) {
+      job.pq.push_back(q);
+      job.pw.push_back(freq->omega[j]);
+    }
+  job.quadrature = true;
+  job.weight.assign(freq->weight, freq->weight + freq->nw);
+  RPA_TRY(run_points(c, c.stream, job, budget_of(c), true));
+  *E = job.E;
+  if (eps_qw) memcpy(eps_qw, job.eps.data(), job.eps.size() * 8);
+  return RPA_OK;
+}
+
+int rpa_points(rpa_ctx *ctx, const rpa_system *sys, int32_t npts, const int32_t *iq, const double *w,
+               rpa_precision prec, double *eps) {
+  RPA_TRY(check_ctx(ctx));
+  Ctx &c = ctx->c;
+  std::lock_guard<std::mutex> g(c.mu);
+  RPA_TRY(set_device(c));
+  HostSmall hs;
+  RPA_TRY(validate_system(sys, hs));
+  if (npts < 0) return fail(RPA_E_ARG, "npts < 0");
+  if (npts == 0) return RPA_OK;
+  if (!iq || !w || !eps) return fail(RPA_E_ARG, "NULL array");
+  if (prec != RPA_FP64 && prec != RPA_FP32 && prec != RPA_BF16X3)
+    return fail(RPA_E_ARG, "unknown precision %d", (int)prec);
+  PointJob job;
+  job.sys = sys;
+  job.hs = &hs;
+  job.prec = prec;
+  job.pq.assign(iq, iq + npts);
+  job.pw.assign(w, w + npts);
+  RPA_TRY(run_points(c, c.stream, job, budget_of(c), true));
+  memcpy(eps, job.eps.data(), (size_t)npts * 8);
+  return RPA_OK;
+}
+
+int rpa_philox_B(rpa_ctx *ctx, uint64_t seed, double sigma, int32_t nk, int32_t iq, int32_t ik,
+                 int32_t nocc, int32_t nvirt, int32_t naux, int32_t is_complex, int32_t memspace,
+                 void *out) {
+  RPA_TRY(check_ctx(ctx));
+  Ctx &c = ctx->c;
+  std::lock_guard<std::mutex> g(c.mu);
+  RPA_TRY(set_device(c));
+  if (nk < 1 || iq < 0 || ik < 0 || ik >= nk || nocc < 1 || nvirt < 1 || naux < 1)
+    return fail(RPA_E_ARG, "bad block indices or sizes");
+  if (memspace != RPA_MEM_HOST && memspace != RPA_MEM_DEVICE) return fail(RPA_E_ARG, "bad memspace");
+  if (!out) return fail(RPA_E_ARG, "out is NULL");
+  const int64_t count = (int64_t)nocc * nvirt * naux;
+  const int64_t bytes = count * (is_complex ? 16 : 8);
+  void *dst = out;
+  if (memspace == RPA_MEM_HOST) RPA_TRY(c.workspace("philox_out", bytes, &dst));
+  RPA_HIP(launch_philox_B(c.stream, seed, sigma, nk, iq, ik, ik + 1, nocc, nvirt, naux, is_complex != 0, dst));
+  if (memspace == RPA_MEM_HOST) RPA_HIP(hipMemcpyAsync(out, dst, (size_t)bytes, hipMemcpyDeviceToHost, c.stream));
+  RPA_HIP(hipStreamSynchronize(c.stream));
+  return RPA_OK;
+}
+
+int rpa_philox_words(rpa_ctx *ctx, uint64_t seed, int32_t nk, int32_t iq, int32_t ik, uint64_t e0,
+                     int64_t count, int32_t memspace, uint32_t *out) {
+  RPA_TRY(check_ctx(ctx));
+  Ctx &c = ctx->c;
+  std::lock_guard<std::mutex> g(c.mu);
+  RPA_TRY(set_device(c));
+  if (nk < 1 || iq < 0 || ik < 0 || ik >= nk || count < 0) return fail(RPA_E_ARG, "bad block or count");
+  if (memspace != RPA_MEM_HOST && memspace != RPA_MEM_DEVICE) return fail(RPA_E_ARG, "bad memspace");
+  if (count == 0) return RPA_OK;
+  if (!out) return fail(RPA_E_ARG, "out is NULL");
+  void *dst = out;
+  if (memspace == RPA_MEM_HOST) RPA_TRY(c.workspace("philox_words", count * 16, &dst));
+  RPA_HIP(launch_philox_words(c.stream, seed, nk, iq, ik, e0, count, (uint32_t *)dst));
+  if (memspace == RPA_MEM_HOST) RPA_HIP(hipMemcpyAsync(out, dst, (size_t)count * 16, hipMemcpyDeviceToHost, c.stream));
+  RPA_HIP(hipStreamSynchronize(c.stream));
+  return RPA_OK;
+}
+
+int rpa_submit(rpa_ctx *ctx, const rpa_system *sys, const rpa_freq *freq, rpa_precision prec,
+               uint64_t *job_id) {
+  RPA_TRY(check_ctx(ctx));
+  return ctx->c.sched->submit(sys, freq, prec, job_id);
+}
+
+int rpa_poll(rpa_ctx *ctx, uint64_t job_id, int32_t timeout_ms, rpa_result *out, double *eps_qw) {
+  RPA_TRY(check_ctx(ctx));
+  return ctx->c.sched->poll(job_id, timeout_ms, out, eps_qw);
+}
+
+int rpa_get_stats(rpa_ctx *ctx, rpa_stats *out) {
+  RPA_TRY(check_ctx(ctx));
+  if (!out) return fail(RPA_E_ARG, "out is NULL");
+  Ctx &c = ctx->c;
+  {
+    std::lock_guard<std::mutex> g(c.mem_mu);
+    out->hbm_limit = c.hbm_limit;
+    out->hbm_in_use = c.in_use;
+    out->hbm_high_water = c.high_water;
+  }
+  c.sched->fill_stats(out);
+  return RPA_OK;
+}
+
+}  // extern "C"

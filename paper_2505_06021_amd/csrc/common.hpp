@@ -1,0 +1,71 @@
+// Internal declarations shared by the HIP kernels and the host runtime of librpa.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rpa {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+// One (q, omega) point of a chi0 launch.
+struct PointDesc {
+  int32_t q;        // q index (selects the kq row and the Delta pairing)
+  int32_t bslot;    // which B(q) slab of the launch holds this q's coefficients
+  double omega;
+};
+
+// Arguments of the chi0 contraction kernels.
+struct Chi0Args {
+  const void *B;            // bslot-major slabs of [M][N] coefficients (complex or real)
+  int64_t b_slot_stride;    // elements (complex or real) between slabs
+  const double *eps_occ;    // [nk][nocc]
+  const double *eps_virt;   // [nk][nvirt]
+  const int32_t *kq;        // [nq][nk]
+  const double *zeta_k;     // [nk]
+  const PointDesc *pts;     // [npts]
+  double2 *out;             // [npts][N][N] complex
+  int64_t out_stride;       // complex elements between outputs
+  int32_t nk, nocc, nvirt, N;
+  int64_t M;                // nk * nocc * nvirt
+};
+
+// Batched complex GEMM C_b = A_{a(b)} * B_{b(b)}, all N x N row-major.
+struct GemmArgs {
+  const double2 *A; int64_t a_stride; int32_t a_div;   // A index = b / a_div
+  const double2 *B; int64_t b_stride; int32_t b_div;   // B index = b / b_div
+  double2 *C; int64_t c_stride;
+  const int32_t *a_map;   // optional: A index = a_map[b]   (overrides a_div)
+  const int32_t *b_map;   // optional: B index = b_map[b]
+  int32_t N;
+  int32_t lower_only;     // compute only the tiles on or below the diagonal
+};
+
+// ---- launchers (each returns the launch's hipError_t) -----------------------
+
+hipError_t launch_philox_B(hipStream_t s, uint64_t seed, double sigma, int32_t nk, int32_t iq,
+                           int32_t k0, int32_t k1, int32_t nocc, int32_t nvirt, int32_t naux,
+                           bool cplx, void *out);
+hipError_t launch_philox_words(hipStream_t s, uint64_t seed, int32_t nk, int32_t iq, int32_t ik,
+                               uint64_t e0, int64_t count, uint32_t *out);
+
+hipError_t launch_chi0_f64(hipStream_t s, const Chi0Args &a, int32_t npts, bool cplx_b);
+
+hipError_t launch_zgemm_f64(hipStream_t s, const GemmArgs &a, int32_t batch);
+
+// eps_b = ln det(1 - Pi_b) + Re Tr Pi_b; Pi is overwritten by its factor.  info[b] = -1 on
+// success, else the failing column.  Results of batch entry b go to index out_map[b]
+// (or b if out_map is NULL).
+hipError_t launch_trln_f64(hipStream_t s, double2 *pi, int64_t stride, int32_t n, int32_t batch,
+                           double *eps, int32_t *info, const int32_t *out_map);
+
+// E = sum_q zeta_q sum_j W_j eps[q][j] / (2 pi) in a fixed order.
+hipError_t launch_quadrature(hipStream_t s, const double *eps, const double *zeta_q,
+                             const double *weight, int32_t nq, int32_t nw, double *E);
+
+// Real [n] -> complex [n] with zero imaginary parts, and back (real part).
+hipError_t launch_widen(hipStream_t s, const double *in, double2 *out, int64_t n);
+hipError_t launch_narrow(hipStream_t s, const double2 *in, double *out, int64_t n);
+
+}  // namespace rpa

@@ -1,0 +1,383 @@
+// Host runtime of librpa: errors, device-memory accounting, validation and the
+// (q, w) point pipeline (B generation or staging -> chi0 -> Pi -> Tr ln).
+#include "runtime.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+
+namespace rpa {
+
+// ---- errors ---------------------------------------------------------------------
+namespace {
+thread_local char g_err[1024] = {0};
+}
+
+void set_error(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+const char *last_error() { return g_err; }
+
+int fail(int code, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+double now_seconds() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ---- device memory ----------------------------------------------------------------
+int Ctx::alloc(DevBuf &b, int64_t bytes, const char *what) {
+  if (bytes <= 0) bytes = 256;
+  {
+    std::lock_guard<std::mutex> g(mem_mu);
+    if (in_use + bytes > hbm_limit)
+      return fail(RPA_E_NOMEM, "%s: %lld bytes requested, %lld of %lld in use", what,
+                  (long long)bytes, (long long)in_use, (long long)hbm_limit);
+    in_use += bytes;
+    high_water = std::max(high_water, in_use);
+  }
+  hipError_t e = hipMalloc(&b.p, (size_t)bytes);
+  if (e != hipSuccess) {
+    std::lock_guard<std::mutex> g(mem_mu);
+    in_use -= bytes;
+    b.p = nullptr;
+    (void)hipGetLastError();
+    return fail(e == hipErrorOutOfMemory ? RPA_E_NOMEM : RPA_E_DEVICE, "%s: hipMalloc(%lld) failed: %s",
+                what, (long long)bytes, hipGetErrorString(e));
+  }
+  b.bytes = bytes;
+  return RPA_OK;
+}
+
+void Ctx::release(DevBuf &b) {
+  if (!b.p) return;
+  (void)hipFree(b.p);
+  std::lock_guard<std::mutex> g(mem_mu);
+  in_use -= b.bytes;
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+int Ctx::workspace(const char *name, int64_t bytes, void **out) {
+  DevBuf &b = cache[name];
+  if (b.p && b.bytes >= bytes) {
+    *out = b.p;
+    return RPA_OK;
+  }
+  if (b.p) {
+    RPA_HIP(hipStreamSynchronize(stream));
+    release(b);
+  }
+  RPA_TRY(alloc(b, bytes, name));
+  *out = b.p;
+  return RPA_OK;
+}
+
+void Ctx::free_cache() {
+  for (auto &kv : cache) release(kv.second);
+  cache.clear();
+}
+
+bool Ctx::would_fit(int64_t extra) {
+  std::lock_guard<std::mutex> g(mem_mu);
+  return in_use + extra <= hbm_limit;
+}
+
+// ---- validation -----------------------------------------------------------------
+namespace {
+int copy_in(void *dst, const void *src, size_t bytes, int memspace) {
+  if (memspace == RPA_MEM_HOST) {
+    memcpy(dst, src, bytes);
+    return RPA_OK;
+  }
+  RPA_HIP(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+  return RPA_OK;
+}
+}  // namespace
+
+int validate_freq(const rpa_freq *f) {
+  if (!f) return fail(RPA_E_ARG, "freq is NULL");
+  if (f->nw < 1 || f->nw > 4096) return fail(RPA_E_ARG, "nw = %d out of range [1, 4096]", f->nw);
+  if (!f->omega || !f->weight) return fail(RPA_E_ARG, "freq arrays are NULL");
+  for (int j = 0; j < f->nw; ++j)
+    if (!std::isfinite(f->omega[j]) || !std::isfinite(f->weight[j]) || f->omega[j] < 0.0)
+      return fail(RPA_E_ARG, "frequency node %d is not a finite non-negative value", j);
+  return RPA_OK;
+}
+
+int validate_system(const rpa_system *sys, HostSmall &hs) {
+  if (!sys) return fail(RPA_E_ARG, "system is NULL");
+  if (sys->memspace != RPA_MEM_HOST && sys->memspace != RPA_MEM_DEVICE)
+    return fail(RPA_E_ARG, "memspace %d is neither host nor device", sys->memspace);
+  if (sys->nk < 1 || sys->nq < 1 || sys->nocc < 1 || sys->nvirt < 1 || sys->naux < 1)
+    return fail(RPA_E_ARG, "sizes must be >= 1 (nk %d nq %d nocc %d nvirt %d naux %d)", sys->nk,
+                sys->nq, sys->nocc, sys->nvirt, sys->naux);
+  if (sys->naux > 16384) return fail(RPA_E_ARG, "naux %d above the supported 16384", sys->naux);
+  const int64_t M = (int64_t)sys->nk * sys->nocc * sys->nvirt;
+  if (M > ((int64_t)1 << 31) - 64) return fail(RPA_E_ARG, "nk*nocc*nvirt = %lld too large", (long long)M);
+  if (sys->is_complex != 0 && sys->is_complex != 1) return fail(RPA_E_ARG, "is_complex must be 0 or 1");
+  if (!sys->kq || !sys->eps_occ || !sys->eps_virt || !sys->vhalf)
+    return fail(RPA_E_ARG, "kq, eps_occ, eps_virt and vhalf must be non-NULL");
+  if (!sys->B && !(sys->sigma > 0.0 && std::isfinite(sys->sigma)))
+    return fail(RPA_E_ARG, "B is NULL (Philox) but sigma = %g is not positive", sys->sigma);
+  hs.nk = sys->nk; hs.nq = sys->nq; hs.nocc = sys->nocc; hs.nvirt = sys->nvirt; hs.naux = sys->naux;
+  hs.is_complex = sys->is_complex;
+  hs.kq.resize((size_t)sys->nq * sys->nk);
+  hs.eps_occ.resize((size_t)sys->nk * sys->nocc);
+  hs.eps_virt.resize((size_t)sys->nk * sys->nvirt);
+  RPA_TRY(copy_in(hs.kq.data(), sys->kq, hs.kq.size() * 4, sys->memspace));
+  RPA_TRY(copy_in(hs.eps_occ.data(), sys->eps_occ, hs.eps_occ.size() * 8, sys->memspace));
+  RPA_TRY(copy_in(hs.eps_virt.data(), sys->eps_virt, hs.eps_virt.size() * 8, sys->memspace));
+  hs.zeta_k.assign(sys->nk, 1.0 / sys->nk);
+  hs.zeta_q.assign(sys->nq, 1.0 / sys->nq);
+  if (sys->zeta_k) RPA_TRY(copy_in(hs.zeta_k.data(), sys->zeta_k, (size_t)sys->nk * 8, sys->memspace));
+  if (sys->zeta_q) RPA_TRY(copy_in(hs.zeta_q.data(), sys->zeta_q, (size_t)sys->nq * 8, sys->memspace));
+  for (size_t i = 0; i < hs.kq.size(); ++i)
+    if (hs.kq[i] < 0 || hs.kq[i] >= sys->nk)
+      return fail(RPA_E_ARG, "kq[%zu] = %d outside [0, nk)", i, hs.kq[i]);
+  for (double v : hs.eps_occ) if (!std::isfinite(v)) return fail(RPA_E_ARG, "eps_occ not finite");
+  for (double v : hs.eps_virt) if (!std::isfinite(v)) return fail(RPA_E_ARG, "eps_virt not finite");
+  for (double v : hs.zeta_k) if (!std::isfinite(v)) return fail(RPA_E_ARG, "zeta_k not finite");
+  for (double v : hs.zeta_q) if (!std::isfinite(v)) return fail(RPA_E_ARG, "zeta_q not finite");
+  // insulators only (closed-shell occupations 2/0): every transition energy positive
+  double min_occ_gap = INFINITY;
+  for (int q = 0; q < sys->nq; ++q)
+    for (int k = 0; k < sys->nk; ++k) {
+      const int kq = hs.kq[(size_t)q * sys->nk + k];
+      double emax_occ = -INFINITY, emin_virt = INFINITY;
+      for (int i = 0; i < sys->nocc; ++i) emax_occ = std::max(emax_occ, hs.eps_occ[(size_t)kq * sys->nocc + i]);
+      for (int a = 0; a < sys->nvirt; ++a) emin_virt = std::min(emin_virt, hs.eps_virt[(size_t)k * sys->nvirt + a]);
+      min_occ_gap = std::min(min_occ_gap, emin_virt - emax_occ);
+    }
+  if (!(min_occ_gap > 0.0))
+    return fail(RPA_E_ARG, "smallest transition energy %g <= 0: only insulators are supported", min_occ_gap);
+  return RPA_OK;
+}
+
+// ---- the point pipeline -------------------------------------------------------------
+namespace {
+
+struct Arena {
+  Ctx &ctx;
+  bool use_cache;
+  std::vector<DevBuf> owned;
+  Arena(Ctx &c, bool cache) : ctx(c), use_cache(cache) {}
+  ~Arena() {
+    for (auto &b : owned) ctx.release(b);
+  }
+  int get(const char *name, int64_t bytes, void **out) {
+    if (use_cache) return ctx.workspace(name, bytes, out);
+    owned.emplace_back();
+    RPA_TRY(ctx.alloc(owned.back(), bytes, name));
+    *out = owned.back().p;
+    return RPA_OK;
+  }
+};
+
+}  // namespace
+
+int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use_cache) {
+  const rpa_system *sys = job.sys;
+  const HostSmall &hs = *job.hs;
+  const int N = hs.naux;
+  const int64_t M = (int64_t)hs.nk * hs.nocc * hs.nvirt;
+  const bool cplx = hs.is_complex != 0;
+  const int64_t npts = (int64_t)job.pq.size();
+  job.eps.assign((size_t)npts, 0.0);
+  if (npts == 0) return RPA_OK;
+  if (job.prec != RPA_FP64) return fail(RPA_E_ARG, "precision %d not available in this path", (int)job.prec);
+
+  const int64_t nn = (int64_t)N * N;
+  const int64_t belem = cplx ? 16 : 8;
+  const bool b_direct = sys->B && sys->memspace == RPA_MEM_DEVICE;
+  const bool vh_direct = sys->memspace == RPA_MEM_DEVICE && cplx;
+  const int64_t b_slot = b_direct ? 0 : M * N * belem;
+  const int64_t vh_slot = vh_direct ? 0 : nn * 16;
+  const int64_t per_pt = 2 * nn * 16 + 64;
+  const int64_t small = (int64_t)(hs.eps_occ.size() + hs.eps_virt.size() + hs.zeta_k.size()) * 8 +
+                        (int64_t)hs.kq.size() * 4 + npts * 32 + 4096;
+
+  // distinct q's in order of first appearance; points grouped by q
+  std::vector<int32_t> qs;
+  std::vector<std::vector<int64_t>> by_q(hs.nq);
+  for (int64_t p = 0; p < npts; ++p) {
+    const int q = job.pq[(size_t)p];
+    if (q < 0 || q >= hs.nq) return fail(RPA_E_ARG, "point %lld: q = %d outside [0, nq)", (long long)p, q);
+    if (!std::isfinite(job.pw[(size_t)p]) || job.pw[(size_t)p] < 0.0)
+      return fail(RPA_E_ARG, "point %lld: omega is not finite and non-negative", (long long)p);
+    if (by_q[q].empty()) qs.push_back(q);
+    by_q[q].push_back(p);
+  }
+
+  // q-group size and point batch under the budget
+  int64_t avail = budget - small;
+  int gq = (int)qs.size();
+  if (job.max_q_group > 0) gq = std::min(gq, job.max_q_group);
+  auto pts_of = [&](int g0, int g) {
+    int64_t c = 0;
+    for (int i = g0; i < g0 + g && i < (int)qs.size(); ++i) c += (int64_t)by_q[qs[i]].size();
+    return c;
+  };
+  while (gq > 1 && gq * (b_slot + vh_slot) + std::min<int64_t>(pts_of(0, gq), 256) * per_pt > avail) --gq;
+  const int64_t rest = avail - gq * (b_slot + vh_slot);
+  if (rest < per_pt)
+    return fail(RPA_E_NOMEM, "one q of this system needs %lld bytes, budget is %lld",
+                (long long)(b_slot + vh_slot + per_pt + small), (long long)budget);
+  int64_t pb_cap = rest / per_pt;
+  int64_t max_group_pts = 0;
+  for (size_t g0 = 0; g0 < qs.size(); g0 += gq) max_group_pts = std::max(max_group_pts, pts_of((int)g0, gq));
+  const int64_t pbatch = std::min<int64_t>(pb_cap, max_group_pts);
+
+  Arena ar(ctx, use_cache);
+  double *d_eo, *d_ev, *d_zk, *d_eps;
+  int32_t *d_kq, *d_info, *d_amap;
+  PointDesc *d_pts;
+  void *d_B = nullptr, *d_vh = nullptr, *d_chi = nullptr, *d_T = nullptr, *d_vstage = nullptr;
+  RPA_TRY(ar.get("eps_occ", (int64_t)hs.eps_occ.size() * 8, (void **)&d_eo));
+  RPA_TRY(ar.get("eps_virt", (int64_t)hs.eps_virt.size() * 8, (void **)&d_ev));
+  RPA_TRY(ar.get("zeta_k", (int64_t)hs.zeta_k.size() * 8, (void **)&d_zk));
+  RPA_TRY(ar.get("kq", (int64_t)hs.kq.size() * 4, (void **)&d_kq));
+  RPA_TRY(ar.get("eps_out", npts * 8, (void **)&d_eps));
+  RPA_TRY(ar.get("info", npts * 4, (void **)&d_info));
+  RPA_TRY(ar.get("pts", pbatch * (int64_t)sizeof(PointDesc), (void **)&d_pts));
+  RPA_TRY(ar.get("maps", 3 * pbatch * 4, (void **)&d_amap));
+  if (b_slot) RPA_TRY(ar.get("B", gq * b_slot, &d_B));
+  if (vh_slot) RPA_TRY(ar.get("vhalf", gq * vh_slot, &d_vh));
+  if (vh_slot && !cplx && sys->memspace == RPA_MEM_HOST) RPA_TRY(ar.get("vstage", nn * 8, &d_vstage));
+  RPA_TRY(ar.get("chi", pbatch * nn * 16, &d_chi));
+  RPA_TRY(ar.get("T", pbatch * nn * 16, &d_T));
+
+  RPA_HIP(hipMemcpyAsync(d_eo, hs.eps_occ.data(), hs.eps_occ.size() * 8, hipMemcpyHostToDevice, st));
+  RPA_HIP(hipMemcpyAsync(d_ev, hs.eps_virt.data(), hs.eps_virt.size() * 8, hipMemcpyHostToDevice, st));
+  RPA_HIP(hipMemcpyAsync(d_zk, hs.zeta_k.data(), hs.zeta_k.size() * 8, hipMemcpyHostToDevice, st));
+  RPA_HIP(hipMemcpyAsync(d_kq, hs.kq.data(), hs.kq.size() * 4, hipMemcpyHostToDevice, st));
+
+  // host copies of every batch's descriptors stay alive until the final synchronisation
+  std::deque<std::vector<PointDesc>> keep_pts;
+  std::deque<std::vector<int32_t>> keep_maps;
+  for (size_t g0 = 0; g0 < qs.size(); g0 += (size_t)gq) {
+    const int ng = (int)std::min<size_t>((size_t)gq, qs.size() - g0);
+    if (g0 > 0) RPA_HIP(hipStreamSynchronize(st));   // slots are reused by this group
+    // stage B and V^(1/2) of the group's q's into slots
+    for (int s = 0; s < ng; ++s) {
+      const int q = qs[g0 + s];
+      if (!b_direct) {
+        char *dst = (char *)d_B + (int64_t)s * b_slot;
+        if (!sys->B) {
+          RPA_HIP(launch_philox_B(st, sys->philox_seed, sys->sigma, hs.nk, q, 0, hs.nk, hs.nocc,
+                                  hs.nvirt, N, cplx, dst));
+        } else {
+          RPA_HIP(hipMemcpyAsync(dst, (const char *)sys->B + (int64_t)q * b_slot, (size_t)b_slot,
+                                 hipMemcpyHostToDevice, st));
+        }
+      }
+      if (vh_slot) {
+        double2 *dst = (double2 *)((char *)d_vh + (int64_t)s * vh_slot);
+        if (cplx) {
+          RPA_HIP(hipMemcpyAsync(dst, (const char *)sys->vhalf + (int64_t)q * nn * 16, (size_t)(nn * 16),
+                                 hipMemcpyHostToDevice, st));
+        } else if (sys->memspace == RPA_MEM_HOST) {
+          RPA_HIP(hipMemcpyAsync(d_vstage, (const char *)sys->vhalf + (int64_t)q * nn * 8, (size_t)(nn * 8),
+                                 hipMemcpyHostToDevice, st));
+          RPA_HIP(launch_widen(st, (const double *)d_vstage, dst, nn));
+        } else {
+          RPA_HIP(launch_widen(st, (const double *)sys->vhalf + (int64_t)q * nn, dst, nn));
+        }
+      }
+    }
+    // the group's points in batches
+    std::vector<int64_t> gp;
+    std::vector<int> gslot;
+    for (int s = 0; s < ng; ++s)
+      for (int64_t p : by_q[qs[g0 + s]]) {
+        gp.push_back(p);
+        gslot.push_back(s);
+      }
+    for (size_t b0 = 0; b0 < gp.size(); b0 += (size_t)pbatch) {
+      const int nb = (int)std::min<size_t>((size_t)pbatch, gp.size() - b0);
+      keep_pts.emplace_back(nb);
+      keep_maps.emplace_back(3 * (size_t)nb);
+      std::vector<PointDesc> &hp = keep_pts.back();
+      int32_t *vmap = keep_maps.back().data();      // V^(1/2) slot of each batch entry
+      int32_t *imap = vmap + nb;                     // identity (chi0 / T slot)
+      int32_t *emap = vmap + 2 * nb;                 // output position of each batch entry
+      for (int i = 0; i < nb; ++i) {
+        const int64_t p = gp[b0 + i];
+        const int s = gslot[b0 + i];
+        const int q = job.pq[(size_t)p];
+        hp[i].q = q;
+        hp[i].bslot = b_direct ? q : s;
+        hp[i].omega = job.pw[(size_t)p];
+        vmap[i] = vh_direct ? q : s;
+        imap[i] = i;
+        emap[i] = (int32_t)p;
+      }
+      RPA_HIP(hipMemcpyAsync(d_pts, hp.data(), nb * sizeof(PointDesc), hipMemcpyHostToDevice, st));
+      RPA_HIP(hipMemcpyAsync(d_amap, vmap, 3 * (size_t)nb * 4, hipMemcpyHostToDevice, st));
+      const int32_t *d_vmap = d_amap, *d_imap = d_amap + nb, *d_emap = d_amap + 2 * nb;
+
+      Chi0Args ca{};
+      ca.B = b_direct ? sys->B : d_B;
+      ca.b_slot_stride = M * N;
+      ca.eps_occ = d_eo;
+      ca.eps_virt = d_ev;
+      ca.kq = d_kq;
+      ca.zeta_k = d_zk;
+      ca.pts = d_pts;
+      ca.out = (double2 *)d_chi;
+      ca.out_stride = nn;
+      ca.nk = hs.nk; ca.nocc = hs.nocc; ca.nvirt = hs.nvirt; ca.N = N; ca.M = M;
+      RPA_HIP(launch_chi0_f64(st, ca, nb, cplx));
+
+      const double2 *vh = vh_direct ? (const double2 *)sys->vhalf : (const double2 *)d_vh;
+      GemmArgs g1{};   // T = chi0 V^(1/2)
+      g1.A = (const double2 *)d_chi; g1.a_stride = nn; g1.a_map = d_imap; g1.a_div = 1;
+      g1.B = vh; g1.b_stride = nn; g1.b_map = d_vmap; g1.b_div = 1;
+      g1.C = (double2 *)d_T; g1.c_stride = nn; g1.N = N; g1.lower_only = 0;
+      RPA_HIP(launch_zgemm_f64(st, g1, nb));
+      GemmArgs g2{};   // Pi = V^(1/2) T, lower triangle, into the chi0 buffer
+      g2.A = vh; g2.a_stride = nn; g2.a_map = d_vmap; g2.a_div = 1;
+      g2.B = (const double2 *)d_T; g2.b_stride = nn; g2.b_map = d_imap; g2.b_div = 1;
+      g2.C = (double2 *)d_chi; g2.c_stride = nn; g2.N = N; g2.lower_only = 1;
+      RPA_HIP(launch_zgemm_f64(st, g2, nb));
+      RPA_HIP(launch_trln_f64(st, (double2 *)d_chi, nn, N, nb, d_eps, d_info, d_emap));
+    }
+  }
+  if (job.quadrature) {
+    // E = sum_q zeta_q sum_j W_j eps(q, w_j) / (2 pi) over the full q-major grid, on the device
+    const int nq = hs.nq, nw = (int)job.weight.size();
+    if ((int64_t)nq * nw != npts) return fail(RPA_E_INTERNAL, "quadrature needs the full point grid");
+    double *d_qw;
+    RPA_TRY(ar.get("quad", (int64_t)(nq + nw + 1) * 8, (void **)&d_qw));
+    std::vector<double> &hq = job.qstage;
+    hq.assign(hs.zeta_q.begin(), hs.zeta_q.end());
+    hq.insert(hq.end(), job.weight.begin(), job.weight.end());
+    RPA_HIP(hipMemcpyAsync(d_qw, hq.data(), (size_t)(nq + nw) * 8, hipMemcpyHostToDevice, st));
+    RPA_HIP(launch_quadrature(st, d_eps, d_qw, d_qw + nq, nq, nw, d_qw + nq + nw));
+    RPA_HIP(hipMemcpyAsync(&job.E, d_qw + nq + nw, 8, hipMemcpyDeviceToHost, st));
+  }
+  std::vector<int32_t> info((size_t)npts);
+  RPA_HIP(hipMemcpyAsync(job.eps.data(), d_eps, (size_t)npts * 8, hipMemcpyDeviceToHost, st));
+  RPA_HIP(hipMemcpyAsync(info.data(), d_info, (size_t)npts * 4, hipMemcpyDeviceToHost, st));
+  RPA_HIP(hipStreamSynchronize(st));
+  for (int64_t p = 0; p < npts; ++p)
+    if (info[(size_t)p] >= 0)
+      return fail(RPA_E_NOTSPD, "1 - Pi is not positive definite at point %lld (q %d, omega %g), column %d",
+                  (long long)p, job.pq[(size_t)p], job.pw[(size_t)p], info[(size_t)p]);
+  return RPA_OK;
+}
+
+}  // namespace rpa

@@ -1,0 +1,115 @@
+// Host runtime of librpa: context, device-memory accounting, errors, staging of the
+// system description, and the (q, w) point pipeline shared by the synchronous entry
+// points and the serving scheduler.
+#pragma once
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/rpa.h"
+#include "common.hpp"
+
+namespace rpa {
+
+// ---- errors -------------------------------------------------------------------
+void set_error(const char *fmt, ...);
+const char *last_error();
+int fail(int code, const char *fmt, ...);
+
+#define RPA_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return ::rpa::fail(RPA_E_DEVICE, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                         __FILE__, __LINE__);                                           \
+  } while (0)
+
+#define RPA_TRY(expr)          \
+  do {                         \
+    int rc_ = (expr);          \
+    if (rc_ != RPA_OK) return rc_; \
+  } while (0)
+
+double now_seconds();
+
+class Scheduler;
+
+// ---- device memory -------------------------------------------------------------
+struct DevBuf {
+  void *p = nullptr;
+  int64_t bytes = 0;
+};
+
+struct Ctx {
+  int device = 0;
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;     // stream of synchronous calls
+  std::mutex mu;                    // serialises synchronous calls on this context
+  std::mutex mem_mu;
+  int64_t hbm_limit = 0;
+  int64_t in_use = 0;
+  int64_t high_water = 0;
+  std::map<std::string, DevBuf> cache;   // grow-only workspaces of synchronous calls
+  std::unique_ptr<Scheduler> sched;
+
+  int alloc(DevBuf &b, int64_t bytes, const char *what);
+  void release(DevBuf &b);
+  // Cached workspace of at least `bytes` (device), reused across synchronous calls.
+  int workspace(const char *name, int64_t bytes, void **out);
+  void free_cache();
+  bool would_fit(int64_t extra);
+};
+
+// ---- staged system ----------------------------------------------------------------
+// Host-side copy of the small arrays of a system (always made, for validation) plus
+// device copies; large arrays (B, V^(1/2)) are referenced or staged by the pipeline.
+struct HostSmall {
+  int32_t nk, nq, nocc, nvirt, naux, is_complex;
+  std::vector<int32_t> kq;
+  std::vector<double> eps_occ, eps_virt, zeta_k, zeta_q;
+};
+
+int validate_system(const rpa_system *sys, HostSmall &hs);
+int validate_freq(const rpa_freq *f);
+
+// Bytes of device memory the pipeline needs for a group of `gq` q-points of a system,
+// `npts` (q, w) points in flight, and whether B must be staged.
+struct PlanSizes {
+  int64_t small_bytes, vhalf_bytes, b_slot_bytes, point_bytes;
+};
+PlanSizes plan_sizes(const HostSmall &hs, bool b_on_device_complex, bool b_device_real);
+
+// One evaluation job over a list of (q, w) points of one system, used by rpa_energy,
+// rpa_points and the scheduler.  Device memory comes from the context's workspace cache
+// (use_cache, synchronous calls) or from buffers owned by the call.
+struct PointJob {
+  const rpa_system *sys;     // caller's description (pointers valid during run)
+  const HostSmall *hs;
+  rpa_precision prec;
+  std::vector<int32_t> pq;   // q of every point
+  std::vector<double> pw;    // omega of every point
+  std::vector<double> eps;   // output eps per point (host)
+  // rpa_energy: the points are the full q-major grid and the quadrature runs on the device
+  bool quadrature = false;
+  std::vector<double> weight;   // W_j
+  std::vector<double> qstage;   // host staging of zeta_q and W_j
+  double E = 0.0;
+  int max_q_group = 0;          // > 0: at most this many q's staged at once
+};
+
+int run_points(Ctx &ctx, hipStream_t stream, PointJob &job, int64_t mem_budget, bool use_cache);
+
+}  // namespace rpa
+
+struct rpa_ctx {
+  rpa::Ctx c;
+};

@@ -1,0 +1,61 @@
+"""Write the stored oracle values used by the GPU parity tests.
+
+Calls only the CPU oracle and the seeded input generators.  Each file records the
+workload recipe next to the values:
+
+    python tests/golden/make_golden.py small     # Gamma-only and 3x3x1 systems, all points
+    python tests/golden/make_golden.py sampled   # sampled points of the two large systems
+"""
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import rpa_oracle as orc          # noqa: E402
+from paper_2505_06021_amd import inputs        # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def write(name, payload):
+    with open(os.path.join(HERE, name + ".json"), "w") as f:
+        json.dump(payload, f, indent=1)
+
+
+def recipe(s):
+    return dict(name=s.name, grid=list(s.grid), nocc=s.nocc, nvirt=s.nvirt, naux=s.naux,
+                nw=s.nw, seed=s.seed, sigma=s.sigma, is_complex=s.is_complex)
+
+
+def full(make):
+    s = make()
+    t = time.time()
+    E, g = orc.energy(s)
+    return dict(recipe=recipe(s), E=E, eps=g.tolist(), oracle_seconds=time.time() - t)
+
+
+def sampled(make, pts):
+    s = make()
+    out = []
+    t = time.time()
+    for iq, j in pts:
+        out.append(dict(iq=iq, j=j, omega=float(s.omega[j]), eps=orc.point(s, iq, j)))
+        print(f"  point q={iq} j={j}: {out[-1]['eps']!r}  ({time.time() - t:.0f} s)", flush=True)
+    return dict(recipe=recipe(s), points=out, oracle_seconds=time.time() - t)
+
+
+if __name__ == "__main__":
+    what = sys.argv[1] if len(sys.argv) > 1 else "small"
+    if what == "small":
+        write("gamma_real_naux128", full(inputs.gamma_real_128))
+        write("slab3x3_naux384", full(inputs.slab_3x3_384))
+    elif what == "sampled6x6":
+        write("slab6x6_naux1200_sampled", sampled(inputs.slab_6x6_1200, [(0, 0), (0, 7), (17, 0), (17, 7)]))
+    elif what == "sampled2400":
+        write("slab3x3_naux2400_sampled", sampled(inputs.slab_3x3_2400, [(0, 0), (4, 7)]))

@@ -1,0 +1,264 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle.
+
+Tolerances (FP64 path):
+  chi0    ||chi0_gpu - chi0_oracle||_F <= 1e-12 ||chi0_oracle||_F
+  eps     |eps_gpu(q,w) - eps_oracle(q,w)| <= 1e-10 max_w' |eps_oracle(q,w')|  (scale-aware:
+          ln det(1 - Pi) and Tr Pi cancel at large w, so a point's own |eps| is no scale)
+  E       |E_gpu - E_oracle| <= 1e-10 |E_oracle|
+Philox words are compared bit for bit; B values to a few ulp (the device and host
+transcendental functions may differ in the last bit).
+"""
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import rpa_oracle as orc
+from paper_2505_06021_amd import inputs
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def say(msg):
+    print(f"[gpu-test] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2505_06021_amd import rpa
+    c = rpa.Context(0)
+    yield c
+    c.close()
+
+
+def rel_fro(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def ragged_system(seed=31, nw=5):
+    # N = 150 spans three 64-wide tiles with a ragged tail; M = 4*3*7 = 84 is not a
+    # multiple of the 16-row K step
+    return inputs.make_system("ragged", (2, 2, 1), 3, 7, 150, nw, seed, is_complex=True, sigma=0.15)
+
+
+# ---------------------------------------------------------------- Philox (a1)
+
+def test_philox_words_bitwise(ctx):
+    say("philox words")
+    for seed, nk, iq, ik, e0, n in [(7, 9, 0, 0, 0, 4096), (2 ** 40 + 5, 9, 8, 3, 12345, 1000),
+                                    (123, 36, 35, 35, 2 ** 32 - 100, 300)]:
+        dev = ctx.philox_words(seed, nk, iq, ik, e0, n)
+        host = inputs.philox_words(seed, nk, iq, ik, e0, n)
+        assert np.array_equal(dev, host), (seed, iq, ik, e0)
+
+
+@pytest.mark.parametrize("cplx", [True, False])
+def test_philox_B_matches_host(ctx, cplx):
+    say(f"philox B complex={cplx}")
+    dev = ctx.philox_B(99, 0.03, 9, 4, 7, 5, 112, 96, is_complex=cplx)
+    host = inputs.philox_B_block(99, 0.03, 9, 4, 7, 5, 112, 96, cplx)
+    assert np.max(np.abs(dev - host)) <= 1e-14 * 0.03 * 8
+
+
+# ---------------------------------------------------------------- chi0 (a2, a3)
+
+def test_chi0_gamma_real_explicit_B(ctx):
+    say("chi0 Gamma real 128")
+    s = inputs.gamma_real_128().materialize_B()
+    for j in (0, 3, 7):
+        ref = orc.chi0(s, 0, s.omega[j])
+        got = ctx.chi0(s, 0, s.omega[j])
+        assert got.dtype == np.float64
+        assert rel_fro(got, ref) <= 1e-12
+
+
+def test_chi0_ragged_tiles_philox(ctx):
+    say("chi0 ragged N=150 M=84")
+    s = ragged_system()
+    for iq in (0, 3):
+        for om in (0.0, 0.77, 40.0):
+            ref = orc.chi0(s, iq, om)
+            got = ctx.chi0(s, iq, om)
+            assert rel_fro(got, ref) <= 1e-12, (iq, om)
+            assert np.abs(got - got.conj().T).max() == 0.0
+
+
+def test_chi0_slab384_sampled(ctx):
+    say("chi0 slab 3x3 naux 384")
+    s = inputs.slab_3x3_384()
+    for iq, j in [(0, 0), (4, 11)]:
+        ref = orc.chi0(s, iq, s.omega[j])
+        got = ctx.chi0(s, iq, s.omega[j])
+        assert rel_fro(got, ref) <= 1e-12
+
+
+def test_chi0_device_memspace_equals_host(ctx):
+    say("chi0 device memspace")
+    s = ragged_system(nw=2)
+    a = ctx.chi0(s, 1, 0.5, device=False)
+    b = ctx.chi0(s, 1, 0.5, device=True)
+    assert np.array_equal(a, b)
+
+
+def test_chi0_single_aux_and_single_transition(ctx):
+    say("chi0 degenerate sizes")
+    s = inputs.make_system("deg", (1, 1, 1), 1, 1, 1, 3, 5, is_complex=True, sigma=0.4, periodic=False)
+    ref = orc.chi0(s, 0, 0.3)
+    got = ctx.chi0(s, 0, 0.3)
+    assert rel_fro(got, ref) <= 1e-14
+
+
+# ---------------------------------------------------------------- Pi (a4)
+
+@pytest.mark.parametrize("n,cplx", [(1, True), (100, True), (200, True), (130, False)])
+def test_pi_sandwich(ctx, n, cplx):
+    say(f"pi n={n} complex={cplx}")
+    rng = np.random.default_rng(n)
+    if cplx:
+        v = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        c = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    else:
+        v = rng.standard_normal((n, n))
+        c = rng.standard_normal((n, n))
+    v = v + v.conj().T
+    c = c + c.conj().T
+    ref = orc.pi_matrix(v, c)
+    got = ctx.pi(v, c)
+    assert rel_fro(got, ref) <= 1e-13
+
+
+# ---------------------------------------------------------------- Tr ln (a5)
+
+def pis_of(s, pts):
+    return [orc.pi_matrix(s.vhalf[iq], orc.chi0(s, iq, s.omega[j])) for iq, j in pts]
+
+
+@pytest.mark.parametrize("n", [1, 16, 17, 150, 384])
+def test_trln_matches_oracle(ctx, n):
+    say(f"trln n={n}")
+    s = inputs.make_system("t", (1, 1, 1), 4, 30, n, 6, 100 + n, is_complex=True, sigma=0.2,
+                           periodic=False)
+    pis = np.stack(pis_of(s, [(0, j) for j in range(s.nw)]))
+    ref = np.array([orc.trace_log(p) for p in pis])
+    got = ctx.trln(pis)
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(got - ref)) <= 1e-10 * scale
+
+
+def test_trln_real_input(ctx):
+    say("trln real")
+    s = inputs.gamma_real_128().materialize_B()
+    pis = np.stack(pis_of(s, [(0, 0), (0, 5)]))
+    ref = np.array([orc.trace_log(p) for p in pis])
+    assert np.max(np.abs(ctx.trln(pis) - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+def test_trln_not_positive_definite_is_an_error(ctx):
+    from paper_2505_06021_amd import rpa
+    say("trln not SPD")
+    n = 40
+    pi = np.zeros((n, n), dtype=np.complex128)
+    pi[17, 17] = 2.0          # 1 - Pi has a negative pivot at column 17
+    with pytest.raises(rpa.RpaError) as e:
+        ctx.trln(pi[None])
+    assert e.value.code == rpa.RPA_E_NOTSPD
+    assert "column 17" in str(e.value)
+
+
+# ---------------------------------------------------------------- energy (a1-a6)
+
+def check_grid(got, ref):
+    for q in range(ref.shape[0]):
+        scale = np.max(np.abs(ref[q]))
+        assert np.max(np.abs(got[q] - ref[q])) <= 1e-10 * scale, q
+
+
+def test_energy_gamma_real_golden(ctx):
+    say("energy Gamma real 128 (explicit B and Philox)")
+    g = json.load(open(os.path.join(GOLD, "gamma_real_naux128.json")))
+    s = inputs.gamma_real_128()
+    E, eps = ctx.energy(s)                       # B from the device Philox stream
+    assert abs(E - g["E"]) <= 1e-10 * abs(g["E"])
+    check_grid(eps, np.array(g["eps"]))
+    s.materialize_B()
+    E2, _ = ctx.energy(s)                        # explicit B from host memory
+    assert abs(E2 - g["E"]) <= 1e-10 * abs(g["E"])
+
+
+def test_energy_slab384_golden(ctx):
+    say("energy slab 3x3 naux 384")
+    g = json.load(open(os.path.join(GOLD, "slab3x3_naux384.json")))
+    s = inputs.slab_3x3_384()
+    E, eps = ctx.energy(s)
+    assert abs(E - g["E"]) <= 1e-10 * abs(g["E"])
+    check_grid(eps, np.array(g["eps"]))
+
+
+def test_energy_ragged_live_oracle(ctx):
+    say("energy ragged live oracle")
+    s = ragged_system(nw=6)
+    E_ref, g_ref = orc.energy(s)
+    E, eps = ctx.energy(s)
+    assert abs(E - E_ref) <= 1e-10 * abs(E_ref)
+    check_grid(eps, g_ref)
+
+
+def test_energy_device_inputs_bitwise_equal(ctx):
+    say("energy device inputs")
+    s = ragged_system(nw=4)
+    a = ctx.energy(s, device=False)
+    b = ctx.energy(s, device=True)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
+
+
+def test_points_subset_equals_energy_grid(ctx):
+    say("points subset")
+    s = ragged_system(nw=4)
+    E, eps = ctx.energy(s)
+    iq = [3, 0, 2, 3]
+    j = [1, 0, 3, 2]
+    got = ctx.points(s, iq, s.omega[j])
+    assert np.array_equal(got, eps[iq, j])
+
+
+def test_energy_repeatable_bitwise(ctx):
+    say("energy repeatable")
+    s = ragged_system(nw=3)
+    a = ctx.energy(s)
+    b = ctx.energy(s)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
+
+
+# ---------------------------------------------------------------- errors
+
+def test_argument_errors(ctx):
+    from paper_2505_06021_amd import rpa
+    say("argument errors")
+    s = ragged_system(nw=2)
+    s.kq = s.kq.copy()
+    s.kq[1, 2] = 99                      # out-of-range k (+) q index is refused on the host
+    with pytest.raises(rpa.RpaError) as e:
+        ctx.energy(s)
+    assert e.value.code == rpa.RPA_E_ARG
+    s = ragged_system(nw=2)
+    s.eps_occ = s.eps_occ + 5.0          # metallic: negative transition energies
+    with pytest.raises(rpa.RpaError) as e:
+        ctx.energy(s)
+    assert e.value.code == rpa.RPA_E_ARG
+    with pytest.raises(rpa.RpaError) as e:
+        ctx.chi0(ragged_system(nw=2), 7, 0.1)
+    assert e.value.code == rpa.RPA_E_ARG
+
+
+def test_hbm_limit_is_enforced():
+    from paper_2505_06021_amd import rpa
+    say("hbm limit")
+    with rpa.Context(0, hbm_limit=1 << 20) as c:
+        s = ragged_system(nw=2)
+        with pytest.raises(rpa.RpaError) as e:
+            c.energy(s)
+        assert e.value.code == rpa.RPA_E_NOMEM
