@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Throughput of the periodic RPA hot path on one MI355X.
+
+One step = one full RPA correlation energy of the workload: device Philox generation
+of B for every q, chi0 for every (q, w) point, Pi = V^(1/2) chi0 V^(1/2), the Cholesky
+log-det and the q/w quadrature, all in librpa's kernels, with the inputs (band
+energies, V^(1/2), weights, the Philox seed) resident in HBM before timing starts.
+
+Prints one JSON line: (q, w) points per second, the roofline position of the dominant
+kernel (chi0) from HIP events recorded on its stream, and the CPU oracle timed on a
+bounded sample of the same workload on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+PREC_CODE = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+WORKLOADS = {
+    "slab3x3_naux384": "slab_3x3_384",
+    "gamma_real_naux128": "gamma_real_128",
+    "slab6x6_naux1200": "slab_6x6_1200",
+    "slab3x3_naux2400": "slab_3x3_2400",
+}
+
+
+def chi0_flops_per_point(s):
+    """Algorithmic flops of chi0 for one (q, w) point: Hermitian half of B^H W B."""
+    M, N = s.M, s.naux
+    return (4.0 if s.is_complex else 1.0) * M * N * (N + 1)
+
+
+def kernel_source_hash(name):
+    p = os.path.join(ROOT, "paper_2505_06021_amd", "csrc", name)
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def traffic_from_profiles(workload, prec):
+    """HBM bytes per chi0 launch from committed counter runs, if the kernel is unchanged."""
+    src = {"fp64": "chi0_f64.hip"}.get(prec, "chi0_mixed.hip")
+    f = os.path.join(ROOT, "profiles", f"chi0_{prec}_{workload}_traffic.json")
+    if not os.path.exists(f) or not os.path.exists(os.path.join(ROOT, "paper_2505_06021_amd", "csrc", src)):
+        return None
+    d = json.load(open(f))
+    if d.get("kernel_source_sha256_16") != kernel_source_hash(src):
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(make, budget_s=12.0, max_points=24):
+    """The oracle as it stands, on the first points of the workload, on the host cores."""
+    from oracle import rpa_oracle as orc
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    s = make()
+    pts = [(q, j) for q in range(s.nq) for j in range(s.nw)]
+    t0 = time.perf_counter()
+    n = 0
+    for (q, j) in pts[:max_points]:
+        orc.point(s, q, j)
+        n += 1
+        if time.perf_counter() - t0 > budget_s and n >= 2:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "points/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"first {n} (q, w) points of the workload in q-major order, "
+                      f"{dt:.1f} s, NumPy FP64 with host Philox B"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="slab3x3_naux384", choices=sorted(WORKLOADS))
+    ap.add_argument("--prec", default="fp64", choices=sorted(PREC_CODE))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the (q, w) points shard by q across GPUs, which this build does not do).",
+              file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import torch
+    from paper_2505_06021_amd import inputs, rpa
+
+    make = getattr(inputs, WORKLOADS[args.workload])
+    s = make()
+    npts = s.nq * s.nw
+    ctx = rpa.Context(0)
+    m = rpa._Marshal(s, device=True)          # inputs resident in HBM before timing
+    prec = PREC_CODE[args.prec]
+    print(f"[bench] {args.workload} prec={args.prec} points/step={npts} warmup={args.warmup} "
+          f"steps={args.steps}", file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        E, _ = ctx.energy(s, prec=prec, marshal=m)
+        print(f"[bench] warmup {i} E={E:.12f}", file=sys.stderr, flush=True)
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        E, eps = ctx.energy(s, prec=prec, marshal=m)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = ctx.profile_read()
+    ctx.profile(False)
+    ctx.close()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    print(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
+
+    launches, ms = kt["chi0"]
+    pts_per_launch = args.steps * npts / max(launches, 1)
+    flops_launch = chi0_flops_per_point(s) * pts_per_launch
+    avg_s = ms * 1e-3 / max(launches, 1)
+    achieved = flops_launch / avg_s / 1e12 if avg_s > 0 else 0.0
+    peak = PEAK_TFLOPS[args.prec]
+    traffic = traffic_from_profiles(args.workload, args.prec)
+
+    check = None
+    gold = os.path.join(ROOT, "tests", "golden", f"{args.workload}.json")
+    if os.path.exists(gold):
+        g = json.load(open(gold))
+        check = {"E": E, "E_oracle": g["E"], "rel_err": abs(E - g["E"]) / abs(g["E"])}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(make)
+
+    line = {
+        "metric": "(q,w) RPA points/s",
+        "value": npts / (ms_step * 1e-3),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f64"}[args.prec],
+        "data": "synthetic (seeded Philox B, Haar-random V, GL frequencies)",
+        "config": {"workload": args.workload, "grid": list(s.grid), "nk": s.nk, "nq": s.nq,
+                   "nocc": s.nocc, "nvirt": s.nvirt, "naux": s.naux, "nw": s.nw,
+                   "is_complex": s.is_complex, "chi0_precision": args.prec,
+                   "B": "Philox4x32-10 on device", "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic,
+                     "kernel": "chi0", "flops_per_launch": flops_launch,
+                     "avg_launch_ms": avg_s * 1e3, "launches": launches},
+        "kernels_ms_per_step": {k: v[1] / args.steps for k, v in kt.items()},
+        "check": check,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -190,6 +190,25 @@ int rpa_poll(rpa_ctx *ctx, uint64_t job_id, int32_t timeout_ms, rpa_result *out,
 /* Counters of the context (device memory, jobs). */
 int rpa_get_stats(rpa_ctx *ctx, rpa_stats *out);
 
+/* Per-kernel device time of the synchronous entry points, measured with HIP events
+ * recorded on the stream each kernel is launched on.  Index by rpa_kernel_kind. */
+enum rpa_kernel_kind {
+  RPA_K_PHILOX = 0,   /* B generation                                 */
+  RPA_K_CHI0 = 1,     /* chi0 contraction                             */
+  RPA_K_PI = 2,       /* the two GEMMs of V^(1/2) chi0 V^(1/2)         */
+  RPA_K_TRLN = 3,     /* Cholesky log-det                             */
+  RPA_K_OTHER = 4,    /* quadrature, widening, copies                 */
+  RPA_K_COUNT = 8
+};
+typedef struct {
+  int64_t launches[RPA_K_COUNT];
+  double ms[RPA_K_COUNT];
+} rpa_kernel_times;
+
+/* enable != 0 turns event timing on and clears the totals; 0 turns it off. */
+int rpa_profile(rpa_ctx *ctx, int32_t enable);
+int rpa_profile_read(rpa_ctx *ctx, rpa_kernel_times *out);
+
 #ifdef __cplusplus
 }
 #endif

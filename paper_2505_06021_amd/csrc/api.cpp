@@ -370,4 +370,29 @@ int rpa_get_stats(rpa_ctx *ctx, rpa_stats *out) {
   return RPA_OK;
 }
 
+int rpa_profile(rpa_ctx *ctx, int32_t enable) {
+  RPA_TRY(check_ctx(ctx));
+  Ctx &c = ctx->c;
+  std::lock_guard<std::mutex> g(c.mu);
+  c.prof_collect();
+  c.profile = enable != 0;
+  for (int k = 0; k < RPA_K_COUNT; ++k) {
+    c.prof_launches[k] = 0;
+    c.prof_ms[k] = 0.0;
+  }
+  return RPA_OK;
+}
+
+int rpa_profile_read(rpa_ctx *ctx, rpa_kernel_times *out) {
+  RPA_TRY(check_ctx(ctx));
+  if (!out) return fail(RPA_E_ARG, "out is NULL");
+  Ctx &c = ctx->c;
+  std::lock_guard<std::mutex> g(c.mu);
+  for (int k = 0; k < RPA_K_COUNT; ++k) {
+    out->launches[k] = c.prof_launches[k];
+    out->ms[k] = c.prof_ms[k];
+  }
+  return RPA_OK;
+}
+
 }  // extern "C"

@@ -91,6 +91,37 @@ void Ctx::free_cache() {
   cache.clear();
 }
 
+int Ctx::prof_begin(hipStream_t s, int k) {
+  if (!profile) return RPA_OK;
+  hipEvent_t a, b;
+  RPA_HIP(hipEventCreate(&a));
+  RPA_HIP(hipEventCreate(&b));
+  RPA_HIP(hipEventRecord(a, s));
+  prof_pending.push_back({k, {a, b}});
+  return RPA_OK;
+}
+
+int Ctx::prof_end(hipStream_t s) {
+  if (!profile || prof_pending.empty()) return RPA_OK;
+  RPA_HIP(hipEventRecord(prof_pending.back().second.second, s));
+  return RPA_OK;
+}
+
+int Ctx::prof_collect() {
+  for (auto &p : prof_pending) {
+    float ms = 0.f;
+    hipError_t e = hipEventElapsedTime(&ms, p.second.first, p.second.second);
+    if (e == hipSuccess) {
+      prof_ms[p.first] += ms;
+      prof_launches[p.first] += 1;
+    }
+    (void)hipEventDestroy(p.second.first);
+    (void)hipEventDestroy(p.second.second);
+  }
+  prof_pending.clear();
+  return RPA_OK;
+}
+
 bool Ctx::would_fit(int64_t extra) {
   std::lock_guard<std::mutex> g(mem_mu);
   return in_use + extra <= hbm_limit;
@@ -242,6 +273,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   const int64_t pbatch = std::min<int64_t>(pb_cap, max_group_pts);
 
   Arena ar(ctx, use_cache);
+  const bool prof = use_cache && ctx.profile;   // timing only on the synchronous path
   double *d_eo, *d_ev, *d_zk, *d_eps;
   int32_t *d_kq, *d_info, *d_amap;
   PointDesc *d_pts;
@@ -277,8 +309,10 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
       if (!b_direct) {
         char *dst = (char *)d_B + (int64_t)s * b_slot;
         if (!sys->B) {
+          if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_PHILOX));
           RPA_HIP(launch_philox_B(st, sys->philox_seed, sys->sigma, hs.nk, q, 0, hs.nk, hs.nocc,
                                   hs.nvirt, N, cplx, dst));
+          if (prof) RPA_TRY(ctx.prof_end(st));
         } else {
           RPA_HIP(hipMemcpyAsync(dst, (const char *)sys->B + (int64_t)q * b_slot, (size_t)b_slot,
                                  hipMemcpyHostToDevice, st));
@@ -340,20 +374,26 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
       ca.out = (double2 *)d_chi;
       ca.out_stride = nn;
       ca.nk = hs.nk; ca.nocc = hs.nocc; ca.nvirt = hs.nvirt; ca.N = N; ca.M = M;
+      if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0));
       RPA_HIP(launch_chi0_f64(st, ca, nb, cplx));
+      if (prof) RPA_TRY(ctx.prof_end(st));
 
       const double2 *vh = vh_direct ? (const double2 *)sys->vhalf : (const double2 *)d_vh;
       GemmArgs g1{};   // T = chi0 V^(1/2)
       g1.A = (const double2 *)d_chi; g1.a_stride = nn; g1.a_map = d_imap; g1.a_div = 1;
       g1.B = vh; g1.b_stride = nn; g1.b_map = d_vmap; g1.b_div = 1;
       g1.C = (double2 *)d_T; g1.c_stride = nn; g1.N = N; g1.lower_only = 0;
+      if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_PI));
       RPA_HIP(launch_zgemm_f64(st, g1, nb));
       GemmArgs g2{};   // Pi = V^(1/2) T, lower triangle, into the chi0 buffer
       g2.A = vh; g2.a_stride = nn; g2.a_map = d_vmap; g2.a_div = 1;
       g2.B = (const double2 *)d_T; g2.b_stride = nn; g2.b_map = d_imap; g2.b_div = 1;
       g2.C = (double2 *)d_chi; g2.c_stride = nn; g2.N = N; g2.lower_only = 1;
       RPA_HIP(launch_zgemm_f64(st, g2, nb));
+      if (prof) RPA_TRY(ctx.prof_end(st));
+      if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_TRLN));
       RPA_HIP(launch_trln_f64(st, (double2 *)d_chi, nn, N, nb, d_eps, d_info, d_emap));
+      if (prof) RPA_TRY(ctx.prof_end(st));
     }
   }
   if (job.quadrature) {
@@ -366,13 +406,16 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
     hq.assign(hs.zeta_q.begin(), hs.zeta_q.end());
     hq.insert(hq.end(), job.weight.begin(), job.weight.end());
     RPA_HIP(hipMemcpyAsync(d_qw, hq.data(), (size_t)(nq + nw) * 8, hipMemcpyHostToDevice, st));
+    if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_OTHER));
     RPA_HIP(launch_quadrature(st, d_eps, d_qw, d_qw + nq, nq, nw, d_qw + nq + nw));
+    if (prof) RPA_TRY(ctx.prof_end(st));
     RPA_HIP(hipMemcpyAsync(&job.E, d_qw + nq + nw, 8, hipMemcpyDeviceToHost, st));
   }
   std::vector<int32_t> info((size_t)npts);
   RPA_HIP(hipMemcpyAsync(job.eps.data(), d_eps, (size_t)npts * 8, hipMemcpyDeviceToHost, st));
   RPA_HIP(hipMemcpyAsync(info.data(), d_info, (size_t)npts * 4, hipMemcpyDeviceToHost, st));
   RPA_HIP(hipStreamSynchronize(st));
+  if (prof) RPA_TRY(ctx.prof_collect());
   for (int64_t p = 0; p < npts; ++p)
     if (info[(size_t)p] >= 0)
       return fail(RPA_E_NOTSPD, "1 - Pi is not positive definite at point %lld (q %d, omega %g), column %d",

@@ -60,6 +60,16 @@ struct Ctx {
   int64_t high_water = 0;
   std::map<std::string, DevBuf> cache;   // grow-only workspaces of synchronous calls
   std::unique_ptr<Scheduler> sched;
+  // kernel timing of synchronous calls (rpa_profile)
+  bool profile = false;
+  int64_t prof_launches[RPA_K_COUNT] = {0};
+  double prof_ms[RPA_K_COUNT] = {0};
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_pending;
+  // Record the start / end of a kernel of kind k on stream s (no-op unless profiling).
+  int prof_begin(hipStream_t s, int k);
+  int prof_end(hipStream_t s);
+  // After the stream has been synchronised: fold pending event pairs into the totals.
+  int prof_collect();
 
   int alloc(DevBuf &b, int64_t bytes, const char *what);
   void release(DevBuf &b);

@@ -22,7 +22,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librpa.so")
 
 EXPORTS = ("rpa_init", "rpa_finalize", "rpa_last_error", "rpa_set_stream", "rpa_chi0", "rpa_pi",
            "rpa_trln", "rpa_energy", "rpa_points", "rpa_philox_B", "rpa_philox_words",
-           "rpa_submit", "rpa_poll", "rpa_get_stats")
+           "rpa_submit", "rpa_poll", "rpa_get_stats", "rpa_profile", "rpa_profile_read")
+KERNEL_KINDS = ("philox", "chi0", "pi", "trln", "other")
 
 
 class RpaError(RuntimeError):
@@ -84,6 +85,8 @@ def load():
         "rpa_submit": [P, C.POINTER(RpaSystemC), C.POINTER(RpaFreqC), C.c_int, C.POINTER(U64)],
         "rpa_poll": [P, U64, I32, C.POINTER(RpaResultC), P],
         "rpa_get_stats": [P, C.POINTER(RpaStatsC)],
+        "rpa_profile": [P, I32],
+        "rpa_profile_read": [P, C.POINTER(RpaKernelTimesC)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -105,6 +108,10 @@ def _ptr(a):
 
 def _host(a, dtype):
     return np.ascontiguousarray(a, dtype=dtype)
+
+
+class RpaKernelTimesC(C.Structure):
+    _fields_ = [("launches", C.c_int64 * 8), ("ms", C.c_double * 8)]
 
 
 class _Marshal:
@@ -278,3 +285,12 @@ class Context:
         s = RpaStatsC()
         self._check(self.lib.rpa_get_stats(self.h, C.byref(s)))
         return {n: getattr(s, n) for n, _ in RpaStatsC._fields_}
+
+    def profile(self, enable=True):
+        """Turn per-kernel HIP-event timing on (clearing totals) or off."""
+        self._check(self.lib.rpa_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        t = RpaKernelTimesC()
+        self._check(self.lib.rpa_profile_read(self.h, C.byref(t)))
+        return {k: (t.launches[i], t.ms[i]) for i, k in enumerate(KERNEL_KINDS)}
