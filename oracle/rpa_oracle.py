@@ -76,9 +76,9 @@ def trace_log(pi):
     return 2.0 * float(np.sum(np.log(np.real(np.diagonal(L))))) + float(np.real(np.trace(pi)))
 
 
-def point(system, iq, j):
+def point(system, iq, j, row_block=None):
     """eps(q, omega_j) of one (q, omega) point (steps 1-5)."""
-    c = chi0(system, iq, system.omega[j])
+    c = chi0(system, iq, system.omega[j], row_block)
     return trace_log(pi_matrix(system.vhalf[iq], c))
 
 

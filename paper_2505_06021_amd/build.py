@@ -19,6 +19,9 @@ ARCH = "gfx950"
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-mcode-object-version=5",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          # MFMA accumulators in ordinary VGPRs (gfx950 has a unified register file); the
+          # AGPR form made the allocator copy accumulators across every loop iteration
+          "-mllvm", "-amdgpu-mfma-vgpr-form",
           "-Wall", "-Wno-unused-result", f"-I{os.path.join(os.path.dirname(HERE), 'include')}"]
 
 

@@ -178,6 +178,8 @@ int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega, rpa_
   const bool direct = cplx && sys->memspace == RPA_MEM_DEVICE;
   if (direct) out = (double2 *)chi0;
   else RPA_TRY(c.workspace("chi0_out", (int64_t)N * N * 16, (void **)&out));
+  double *wt;
+  RPA_TRY(c.workspace("chi0_wtab", M * 8, (void **)&wt));
   Chi0Args a{};
   a.B = B;
   a.b_slot_stride = 0;
@@ -186,11 +188,13 @@ int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega, rpa_
   a.zeta_k = (const double *)(da + (hs.eps_occ.size() + hs.eps_virt.size()) * 8);
   a.kq = (const int32_t *)(da + nsmall * 8);
   a.pts = (const PointDesc *)(da + pd_off);
+  a.wtab = wt;
   a.out = out;
   a.out_stride = 0;
   a.nk = hs.nk; a.nocc = hs.nocc; a.nvirt = hs.nvirt; a.N = N; a.M = M;
   if (prec != RPA_FP64) return fail(RPA_E_ARG, "precision %d not available in this path", (int)prec);
-  RPA_HIP(launch_chi0_f64(c.stream, a, 1, cplx));
+  RPA_HIP(launch_chi0_weights(c.stream, a, 1));
+  RPA_HIP(launch_chi0_f64(c.stream, a, 1, cplx, chi0_kt()));
   if (!direct) RPA_TRY(deliver_complex(c, chi0, out, (int64_t)N * N, hs.is_complex, sys->memspace));
   RPA_HIP(hipStreamSynchronize(c.stream));
   return RPA_OK;

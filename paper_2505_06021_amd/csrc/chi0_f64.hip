@@ -8,11 +8,10 @@
 //
 // Work decomposition: one workgroup per 64 x 64 complex tile on or below the diagonal
 // of one (q, w) point's output; the point index is blockIdx.y so every point of a
-// q-group shares one launch.  The contraction runs in K steps of 16 rows: each thread
-// loads 4 consecutive complex coefficients of one row for both operand panels, the
-// right operand is multiplied by w_m zeta_k in registers (the weight is computed from
-// the band energies there, never stored), and both panels go to a double-buffered LDS
-// tile.  Four waves each own a 32 x 32 sub-tile (2 x 2 MFMA blocks, Re and Im
+// q-group shares one launch.  The contraction runs in K steps of KT rows (8, 16 or 32):
+// sixteen lanes load one row of both operand panels, the right operand is multiplied by
+// w_m zeta_k in registers (from a per-point table of the transition weights), and both
+// panels go to a double-buffered LDS tile.  Four waves each own a 32 x 32 sub-tile (2 x 2 MFMA blocks, Re and Im
 // accumulators).  Off-diagonal tiles also store their conjugate transpose, so the full
 // Hermitian matrix is produced from the lower-triangle work only.
 #include "common.hpp"
@@ -21,7 +20,6 @@ namespace rpa {
 namespace {
 
 constexpr int TN = 64;        // output tile edge (complex elements)
-constexpr int KT = 16;        // contraction rows per pipeline step
 constexpr int LDP = TN + 1;   // LDS row pitch in complex elements (one element of padding)
 
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
@@ -42,60 +40,145 @@ __device__ __forceinline__ void tile_of(int t, int &tr, int &tc) {
   tc = t - r * (r + 1) / 2;
 }
 
-template <bool CPLX_B>
-__global__ __launch_bounds__(256, 2) void chi0_f64_kernel(Chi0Args a) {
+// w_m zeta_k for every contraction row m of every point of a launch (Delta and the
+// frequency weight of the polarizability equation), one table row per point.
+__global__ __launch_bounds__(256) void weight_table_kernel(Chi0Args a, int32_t npts) {
+  const int nov = a.nocc * a.nvirt;
+  const int64_t total = (int64_t)npts * a.M;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int p = (int)(g / a.M);
+    const int m = (int)(g - (int64_t)p * a.M);
+    const PointDesc pd = a.pts[p];
+    const int k = m / nov;
+    const int rem = m - k * nov;
+    const int i = rem / a.nvirt;
+    const int av = rem - i * a.nvirt;
+    const int kq = a.kq[(int64_t)pd.q * a.nk + k];
+    const double d = a.eps_virt[(int64_t)k * a.nvirt + av] - a.eps_occ[(int64_t)kq * a.nocc + i];
+    a.wtab[g] = -4.0 * a.zeta_k[k] * d / (d * d + pd.omega * pd.omega);
+  }
+}
+
+// Per-thread loader state: 16 lanes per row, lane lc loads columns lc, lc+16, lc+32,
+// lc+48 of both operand panels, so each load instruction of 16 lanes reads 256
+// contiguous bytes and the LDS stores are conflict-free.
+template <int NPASS>
+struct Stage {
+  double2 a[NPASS][4], b[NPASS][4];
+  double w[NPASS];
+  bool mv[NPASS];
+};
+
+// Raw loads only: nothing consumes them until store_stage() after the MFMA block, so
+// they stay in flight while the current tile is contracted.  Out-of-range rows and
+// columns read a clamped (valid) address and are zeroed at the store.
+template <bool CPLX_B, int NPASS, int RPI>
+__device__ __forceinline__ void load_stage(Stage<NPASS> &st, const char *bbase, const double *wrow,
+                                           int m0, int lrow, bool row_active, int M, int N,
+                                           const int (&pcol)[4], const int (&qcol)[4]) {
+#pragma unroll
+  for (int ps = 0; ps < NPASS; ++ps) {
+    const int m = m0 + ps * RPI + lrow;
+    st.mv[ps] = row_active && m < M;
+    const int mc = st.mv[ps] ? m : 0;
+    st.w[ps] = wrow[mc];
+    const int64_t rowoff = (int64_t)mc * N;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      st.a[ps][c] = load_b<CPLX_B>(bbase, rowoff + pcol[c]);
+      st.b[ps][c] = load_b<CPLX_B>(bbase, rowoff + qcol[c]);
+    }
+  }
+}
+
+template <int KT, int NPASS, int RPI>
+__device__ __forceinline__ void store_stage(const Stage<NPASS> &st, double2 (*la)[LDP],
+                                            double2 (*lb)[LDP], int lrow, int lc, bool row_active,
+                                            const bool (&pok)[4], const bool (&qok)[4]) {
+  if (!row_active) return;
+#pragma unroll
+  for (int ps = 0; ps < NPASS; ++ps) {
+    const double w = st.mv[ps] ? st.w[ps] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double2 z = make_double2(0.0, 0.0);
+      const double2 a = (st.mv[ps] && pok[c]) ? st.a[ps][c] : z;
+      const double2 b = qok[c] ? st.b[ps][c] : z;
+      la[ps * RPI + lrow][lc + 16 * c] = a;
+      lb[ps * RPI + lrow][lc + 16 * c] = make_double2(w * b.x, w * b.y);
+    }
+  }
+}
+
+// One K step of the 2 x 2 block of 16 x 16 complex products owned by a wave:
+// acc += conj(A)^T (w B) over the KT rows held in LDS.
+template <int KT>
+__device__ __forceinline__ void contract(const double2 (*la)[LDP], const double2 (*lb)[LDP], int wr,
+                                         int wc, int li, int lk, d4 (&accR)[2][2], d4 (&accI)[2][2]) {
+#pragma unroll
+  for (int ks = 0; ks < KT / 4; ++ks) {
+    double2 av[2], bv[2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) av[x] = la[ks * 4 + lk][wr * 32 + x * 16 + li];
+#pragma unroll
+    for (int y = 0; y < 2; ++y) bv[y] = lb[ks * 4 + lk][wc * 32 + y * 16 + li];
+    // conj(a) * b = (ar br + ai bi) + i (ar bi - ai br); the four products of a block are
+    // issued with the other blocks' products in between, so no MFMA waits on its
+    // predecessor's accumulator.
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) accR[x][y] = mfma(av[x].x, bv[y].x, accR[x][y]);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) accI[x][y] = mfma(av[x].x, bv[y].y, accI[x][y]);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) accR[x][y] = mfma(av[x].y, bv[y].y, accR[x][y]);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) accI[x][y] = mfma(-av[x].y, bv[y].x, accI[x][y]);
+  }
+}
+
+template <bool CPLX_B, int KT>
+__global__ __launch_bounds__(256) void chi0_f64_kernel(Chi0Args a) {
   __shared__ double2 lds[2][2][KT][LDP];
+  constexpr int RPI = 256 / 16;               // rows covered by one pass of the workgroup
+  constexpr int NPASS = KT / RPI > 0 ? KT / RPI : 1;
 
   const PointDesc pd = a.pts[blockIdx.y];
   int tr, tc;
   tile_of((int)blockIdx.x, tr, tc);
   const int N = a.N;
-  const int64_t M = a.M;
+  const int M = (int)a.M;
   const int P0 = tr * TN, Q0 = tc * TN;
   const bool diag = (tr == tc);
 
   const int tid = threadIdx.x;
-  const int lrow = tid >> 4;          // row of the K step this thread loads
-  const int lcol = (tid & 15) * 4;    // first of its 4 columns
+  const int lrow = tid >> 4;
+  const int lc = tid & 15;
+  const bool row_active = lrow < KT;
 
   const char *bbase = reinterpret_cast<const char *>(a.B) +
                       (int64_t)pd.bslot * a.b_slot_stride * (CPLX_B ? 16 : 8);
-  const int nov = a.nocc * a.nvirt;
-  const int32_t *kqrow = a.kq + (int64_t)pd.q * a.nk;
-  const double om2 = pd.omega * pd.omega;
+  const double *wrow = a.wtab + (int64_t)blockIdx.y * a.M;
 
-  double2 ra[4], rb[4];
-
-  auto gload = [&](int64_t m0) {
-    const int64_t m = m0 + lrow;
-    double w = 0.0;
-    if (m < M) {
-      const int k = (int)(m / nov);
-      const int rem = (int)(m - (int64_t)k * nov);
-      const int i = rem / a.nvirt;
-      const int av = rem - i * a.nvirt;
-      const double d = a.eps_virt[(int64_t)k * a.nvirt + av] - a.eps_occ[(int64_t)kqrow[k] * a.nocc + i];
-      w = -4.0 * a.zeta_k[k] * d / (d * d + om2);
-    }
-    const int64_t rowoff = m * N;
+  // column validity and clamped column indices are fixed for the whole contraction
+  int pcol[4], qcol[4];
+  bool pok[4], qok[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int P = P0 + lcol + c;
-      const int Q = Q0 + lcol + c;
-      ra[c] = (m < M && P < N) ? load_b<CPLX_B>(bbase, rowoff + P) : make_double2(0.0, 0.0);
-      double2 v;
-      if (diag) v = ra[c];
-      else v = (m < M && Q < N) ? load_b<CPLX_B>(bbase, rowoff + Q) : make_double2(0.0, 0.0);
-      rb[c] = make_double2(w * v.x, w * v.y);
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      lds[buf][0][lrow][lcol + c] = ra[c];
-      lds[buf][1][lrow][lcol + c] = rb[c];
-    }
-  };
+  for (int c = 0; c < 4; ++c) {
+    const int P = P0 + lc + 16 * c, Q = Q0 + lc + 16 * c;
+    pok[c] = P < N;
+    qok[c] = Q < N;
+    pcol[c] = pok[c] ? P : 0;
+    qcol[c] = qok[c] ? Q : 0;
+  }
 
   const int wave = tid >> 6, lane = tid & 63;
   const int wr = wave >> 1, wc = wave & 1;
@@ -110,34 +193,22 @@ __global__ __launch_bounds__(256, 2) void chi0_f64_kernel(Chi0Args a) {
       accI[x][y] = d4{0.0, 0.0, 0.0, 0.0};
     }
 
-  const int64_t nsteps = (M + KT - 1) / KT;
-  gload(0);
-  sstore(0);
+  Stage<NPASS> st;
+  const int nsteps = (M + KT - 1) / KT;
+  load_stage<CPLX_B, NPASS, RPI>(st, bbase, wrow, 0, lrow, row_active, M, N, pcol, qcol);
+  store_stage<KT, NPASS, RPI>(st, lds[0][0], lds[0][1], lrow, lc, row_active, pok, qok);
   __syncthreads();
-  for (int64_t s = 0; s < nsteps; ++s) {
-    const int cur = (int)(s & 1);
-    if (s + 1 < nsteps) gload((s + 1) * KT);
-#pragma unroll
-    for (int ks = 0; ks < KT / 4; ++ks) {
-      double2 av[2], bv[2];
-#pragma unroll
-      for (int x = 0; x < 2; ++x) av[x] = lds[cur][0][ks * 4 + lk][wr * 32 + x * 16 + li];
-#pragma unroll
-      for (int y = 0; y < 2; ++y) bv[y] = lds[cur][1][ks * 4 + lk][wc * 32 + y * 16 + li];
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y) {
-          // conj(a) * b = (ar br + ai bi) + i (ar bi - ai br)
-          accR[x][y] = mfma(av[x].x, bv[y].x, accR[x][y]);
-          accR[x][y] = mfma(av[x].y, bv[y].y, accR[x][y]);
-          accI[x][y] = mfma(av[x].x, bv[y].y, accI[x][y]);
-          accI[x][y] = mfma(-av[x].y, bv[y].x, accI[x][y]);
-        }
-    }
-    if (s + 1 < nsteps) sstore(cur ^ 1);
+  for (int s = 0; s + 1 < nsteps; ++s) {
+    const int cur = s & 1;
+    load_stage<CPLX_B, NPASS, RPI>(st, bbase, wrow, (s + 1) * KT, lrow, row_active, M, N, pcol, qcol);
+    // keep the next tile's loads issued ahead of the MFMA block (their latency hides under it)
+    __builtin_amdgcn_sched_barrier(0);
+    contract<KT>(lds[cur][0], lds[cur][1], wr, wc, li, lk, accR, accI);
+    __builtin_amdgcn_sched_barrier(0);
+    store_stage<KT, NPASS, RPI>(st, lds[cur ^ 1][0], lds[cur ^ 1][1], lrow, lc, row_active, pok, qok);
     __syncthreads();
   }
+  contract<KT>(lds[(nsteps - 1) & 1][0], lds[(nsteps - 1) & 1][1], wr, wc, li, lk, accR, accI);
 
   double2 *out = a.out + (int64_t)blockIdx.y * a.out_stride;
 #pragma unroll
@@ -166,14 +237,28 @@ __global__ __launch_bounds__(256, 2) void chi0_f64_kernel(Chi0Args a) {
 
 }  // namespace
 
-hipError_t launch_chi0_f64(hipStream_t s, const Chi0Args &a, int32_t npts, bool cplx_b) {
+hipError_t launch_chi0_weights(hipStream_t s, const Chi0Args &a, int32_t npts) {
+  const int64_t total = (int64_t)npts * a.M;
+  if (total <= 0) return hipSuccess;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(weight_table_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, npts);
+  return hipGetLastError();
+}
+
+hipError_t launch_chi0_f64(hipStream_t s, const Chi0Args &a, int32_t npts, bool cplx_b, int kt) {
   if (npts <= 0) return hipSuccess;
   const int T = (a.N + TN - 1) / TN;
   const dim3 grid((unsigned)(T * (T + 1) / 2), (unsigned)npts);
-  if (cplx_b)
-    hipLaunchKernelGGL(chi0_f64_kernel<true>, grid, dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL(chi0_f64_kernel<false>, grid, dim3(256), 0, s, a);
+#define RPA_CHI0_LAUNCH(C, K) hipLaunchKernelGGL((chi0_f64_kernel<C, K>), grid, dim3(256), 0, s, a)
+  if (kt == 8) {
+    if (cplx_b) RPA_CHI0_LAUNCH(true, 8); else RPA_CHI0_LAUNCH(false, 8);
+  } else if (kt == 32) {
+    if (cplx_b) RPA_CHI0_LAUNCH(true, 32); else RPA_CHI0_LAUNCH(false, 32);
+  } else {
+    if (cplx_b) RPA_CHI0_LAUNCH(true, 16); else RPA_CHI0_LAUNCH(false, 16);
+  }
+#undef RPA_CHI0_LAUNCH
   return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@ struct Chi0Args {
   const int32_t *kq;        // [nq][nk]
   const double *zeta_k;     // [nk]
   const PointDesc *pts;     // [npts]
+  double *wtab;             // [npts][M] w_m zeta_k of every contraction row
   double2 *out;             // [npts][N][N] complex
   int64_t out_stride;       // complex elements between outputs
   int32_t nk, nocc, nvirt, N;
@@ -50,7 +51,10 @@ hipError_t launch_philox_B(hipStream_t s, uint64_t seed, double sigma, int32_t n
 hipError_t launch_philox_words(hipStream_t s, uint64_t seed, int32_t nk, int32_t iq, int32_t ik,
                                uint64_t e0, int64_t count, uint32_t *out);
 
-hipError_t launch_chi0_f64(hipStream_t s, const Chi0Args &a, int32_t npts, bool cplx_b);
+// Fill a.wtab for the npts points of a launch (must precede the contraction launch).
+hipError_t launch_chi0_weights(hipStream_t s, const Chi0Args &a, int32_t npts);
+// kt: rows per K step (8, 16 or 32).
+hipError_t launch_chi0_f64(hipStream_t s, const Chi0Args &a, int32_t npts, bool cplx_b, int kt);
 
 hipError_t launch_zgemm_f64(hipStream_t s, const GemmArgs &a, int32_t batch);
 

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 
@@ -199,6 +200,15 @@ int validate_system(const rpa_system *sys, HostSmall &hs) {
 }
 
 // ---- the point pipeline -------------------------------------------------------------
+int chi0_kt() {
+  static int kt = [] {
+    const char *e = getenv("RPA_CHI0_KT");
+    const int v = e ? atoi(e) : 16;
+    return (v == 8 || v == 16 || v == 32) ? v : 16;
+  }();
+  return kt;
+}
+
 namespace {
 
 struct Arena {
@@ -237,7 +247,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   const bool vh_direct = sys->memspace == RPA_MEM_DEVICE && cplx;
   const int64_t b_slot = b_direct ? 0 : M * N * belem;
   const int64_t vh_slot = vh_direct ? 0 : nn * 16;
-  const int64_t per_pt = 2 * nn * 16 + 64;
+  const int64_t per_pt = 2 * nn * 16 + M * 8 + 64;
   const int64_t small = (int64_t)(hs.eps_occ.size() + hs.eps_virt.size() + hs.zeta_k.size()) * 8 +
                         (int64_t)hs.kq.size() * 4 + npts * 32 + 4096;
 
@@ -290,6 +300,8 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   if (vh_slot) RPA_TRY(ar.get("vhalf", gq * vh_slot, &d_vh));
   if (vh_slot && !cplx && sys->memspace == RPA_MEM_HOST) RPA_TRY(ar.get("vstage", nn * 8, &d_vstage));
   RPA_TRY(ar.get("chi", pbatch * nn * 16, &d_chi));
+  double *d_w;
+  RPA_TRY(ar.get("wtab", pbatch * M * 8, (void **)&d_w));
   RPA_TRY(ar.get("T", pbatch * nn * 16, &d_T));
 
   RPA_HIP(hipMemcpyAsync(d_eo, hs.eps_occ.data(), hs.eps_occ.size() * 8, hipMemcpyHostToDevice, st));
@@ -371,11 +383,13 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
       ca.kq = d_kq;
       ca.zeta_k = d_zk;
       ca.pts = d_pts;
+      ca.wtab = d_w;
       ca.out = (double2 *)d_chi;
       ca.out_stride = nn;
       ca.nk = hs.nk; ca.nocc = hs.nocc; ca.nvirt = hs.nvirt; ca.N = N; ca.M = M;
       if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0));
-      RPA_HIP(launch_chi0_f64(st, ca, nb, cplx));
+      RPA_HIP(launch_chi0_weights(st, ca, nb));
+      RPA_HIP(launch_chi0_f64(st, ca, nb, cplx, chi0_kt()));
       if (prof) RPA_TRY(ctx.prof_end(st));
 
       const double2 *vh = vh_direct ? (const double2 *)sys->vhalf : (const double2 *)d_vh;

@@ -118,6 +118,9 @@ struct PointJob {
 
 int run_points(Ctx &ctx, hipStream_t stream, PointJob &job, int64_t mem_budget, bool use_cache);
 
+// Rows per K step of the FP64 chi0 kernel (RPA_CHI0_KT = 8, 16 or 32; default 16).
+int chi0_kt();
+
 }  // namespace rpa
 
 struct rpa_ctx {

@@ -45,7 +45,7 @@ def sampled(make, pts):
     out = []
     t = time.time()
     for iq, j in pts:
-        out.append(dict(iq=iq, j=j, omega=float(s.omega[j]), eps=orc.point(s, iq, j)))
+        out.append(dict(iq=iq, j=j, omega=float(s.omega[j]), eps=orc.point(s, iq, j, row_block=4)))
         print(f"  point q={iq} j={j}: {out[-1]['eps']!r}  ({time.time() - t:.0f} s)", flush=True)
     return dict(recipe=recipe(s), points=out, oracle_seconds=time.time() - t)
 
