@@ -194,10 +194,12 @@ int rpa_get_stats(rpa_ctx *ctx, rpa_stats *out);
  * recorded on the stream each kernel is launched on.  Index by rpa_kernel_kind. */
 enum rpa_kernel_kind {
   RPA_K_PHILOX = 0,   /* B generation                                 */
-  RPA_K_CHI0 = 1,     /* chi0 contraction                             */
+  RPA_K_CHI0 = 1,     /* chi0 contraction (the MFMA kernel alone)     */
   RPA_K_PI = 2,       /* the two GEMMs of V^(1/2) chi0 V^(1/2)         */
   RPA_K_TRLN = 3,     /* Cholesky log-det                             */
   RPA_K_OTHER = 4,    /* quadrature, widening, copies                 */
+  RPA_K_CHI0_AUX = 5, /* transition-weight table, FP32 copy of B and the exact FP64
+                         diagonal of the reduced-precision paths       */
   RPA_K_COUNT = 8
 };
 typedef struct {

@@ -192,9 +192,19 @@ int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega, rpa_
   a.out = out;
   a.out_stride = 0;
   a.nk = hs.nk; a.nocc = hs.nocc; a.nvirt = hs.nvirt; a.N = N; a.M = M;
-  if (prec != RPA_FP64) return fail(RPA_E_ARG, "precision %d not available in this path", (int)prec);
   RPA_HIP(launch_chi0_weights(c.stream, a, 1));
-  RPA_HIP(launch_chi0_f64(c.stream, a, 1, cplx, chi0_kt()));
+  if (prec != RPA_FP64) {
+    float2 *b32;
+    double *dg, *scr;
+    RPA_TRY(c.workspace("chi0_B32", M * N * 8, (void **)&b32));
+    RPA_TRY(c.workspace("chi0_diag", (int64_t)N * 8, (void **)&dg));
+    RPA_TRY(c.workspace("chi0_diag_scratch", diag_exact_scratch_doubles(M, N, 1) * 8, (void **)&scr));
+    RPA_HIP(launch_to_f32(c.stream, B, b32, M * N, cplx));
+    RPA_HIP(launch_diag_exact(c.stream, B, cplx, M, N, wt, 1, scr, dg));
+    RPA_HIP(launch_chi0_mixed(c.stream, a, 1, b32, dg, (int)prec));
+  } else {
+    RPA_HIP(launch_chi0_f64(c.stream, a, 1, cplx, chi0_kt()));
+  }
   if (!direct) RPA_TRY(deliver_complex(c, chi0, out, (int64_t)N * N, hs.is_complex, sys->memspace));
   RPA_HIP(hipStreamSynchronize(c.stream));
   return RPA_OK;

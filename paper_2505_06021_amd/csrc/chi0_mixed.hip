@@ -1,0 +1,535 @@
+// chi0(q, i w) with a reduced-precision contraction: FP32 MFMA, or split-BF16
+// (x = hi + lo with hi = bf16(x), lo = bf16(x - hi); products hi*hi + hi*lo + lo*hi) on
+// the BF16 MFMA with FP32 accumulation.  Both keep what the FP64 path keeps in FP64:
+//  - partial sums are flushed from FP32 into FP64 accumulators every FLUSH_ROWS rows, so
+//    FP32 rounding never runs over long chains;
+//  - the diagonal chi0_PP = sum_m w_m |B_mP|^2, a sum of same-signed terms whose rounding
+//    errors do not cancel, is taken from an exact FP64 pass (diag_exact_kernel) instead
+//    of the MFMA result.
+// The contraction reads B in FP32 (the device converts the FP64 coefficients once per
+// q), the right operand is scaled by w_m zeta_k in FP32 before it is rounded to the
+// MFMA precision, and the output is FP64 complex like the FP64 path's.
+#include "common.hpp"
+
+namespace rpa {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef short s8 __attribute__((ext_vector_type(8)));
+
+constexpr int TN = 64;
+constexpr int FLUSH_ROWS = 256;
+
+__device__ __forceinline__ void tile_of(int t, int &tr, int &tc) {
+  int r = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((r + 1) * (r + 2) / 2 <= t) ++r;
+  while (r * (r + 1) / 2 > t) --r;
+  tr = r;
+  tc = t - r * (r + 1) / 2;
+}
+
+// ------------------------------------------------------------------ conversion
+
+__global__ __launch_bounds__(256) void to_f32_kernel(const void *in, float2 *out, int64_t n, int cplx) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (cplx) {
+      const double2 v = reinterpret_cast<const double2 *>(in)[i];
+      out[i] = make_float2((float)v.x, (float)v.y);
+    } else {
+      out[i] = make_float2((float)reinterpret_cast<const double *>(in)[i], 0.f);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ exact diagonal
+// partial[c][p][P] = sum over the rows m of chunk c of w_p(m) |B_mP|^2 in FP64, for all
+// the points p of a launch that share one B slab; a second pass sums the chunks in
+// order.  A workgroup covers 64 columns x DIAG_ROWS rows: four row groups of 64 lanes
+// (lanes on consecutive columns, so every load instruction reads 1 KB contiguous) whose
+// partial sums are combined in LDS in a fixed order.
+constexpr int DIAG_ROWS = 256;     // rows per chunk
+constexpr int DIAG_MAXP = 16;      // points per pass
+
+__global__ __launch_bounds__(256) void diag_partial_kernel(const void *B, int cplx, int64_t M, int N,
+                                                           const double *wtab, int npts,
+                                                           double *partial) {
+  __shared__ double red[4][DIAG_MAXP][64];
+  const int col = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int P = blockIdx.x * 64 + col;
+  const int c = blockIdx.y;
+  const int64_t m0 = (int64_t)c * DIAG_ROWS;
+  const int Pc = P < N ? P : 0;
+  double acc[DIAG_MAXP];
+#pragma unroll
+  for (int p = 0; p < DIAG_MAXP; ++p) acc[p] = 0.0;
+  for (int r = grp; r < DIAG_ROWS; r += 4) {
+    const int64_t m = m0 + r;
+    if (m >= M) break;
+    double b2;
+    if (cplx) {
+      const double2 v = reinterpret_cast<const double2 *>(B)[m * N + Pc];
+      b2 = v.x * v.x + v.y * v.y;
+    } else {
+      const double v = reinterpret_cast<const double *>(B)[m * N + Pc];
+      b2 = v * v;
+    }
+#pragma unroll
+    for (int p = 0; p < DIAG_MAXP; ++p)
+      if (p < npts) acc[p] += wtab[(int64_t)p * M + m] * b2;
+  }
+#pragma unroll
+  for (int p = 0; p < DIAG_MAXP; ++p) red[grp][p][col] = acc[p];
+  __syncthreads();
+  if (grp == 0 && P < N) {
+    for (int p = 0; p < npts; ++p)
+      partial[((int64_t)c * npts + p) * N + P] = ((red[0][p][col] + red[1][p][col]) + red[2][p][col]) +
+                                                 red[3][p][col];
+  }
+}
+
+__global__ __launch_bounds__(256) void diag_reduce_kernel(const double *partial, int nchunks, int npts,
+                                                          int N, double *diag) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)npts * N) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunks; ++c) s += partial[(int64_t)c * npts * N + i];
+  diag[i] = s;
+}
+
+// ------------------------------------------------------------------ FP32 MFMA
+
+__device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+constexpr int LDP32 = TN + 1;
+
+template <int KT>
+__global__ __launch_bounds__(256) void chi0_f32_kernel(Chi0Args a, const float2 *B32, const double *diag) {
+  __shared__ float2 lds[2][2][KT][LDP32];
+  constexpr int RPI = 16;
+  constexpr int NPASS = KT / RPI;
+
+  const PointDesc pd = a.pts[blockIdx.y];
+  int tr, tc;
+  tile_of((int)blockIdx.x, tr, tc);
+  const int N = a.N;
+  const int M = (int)a.M;
+  const int P0 = tr * TN, Q0 = tc * TN;
+  const bool is_diag = (tr == tc);
+  const int tid = threadIdx.x;
+  const int lrow = tid >> 4, lc = tid & 15;
+  const float2 *bb = B32 + (int64_t)pd.bslot * a.b_slot_stride;
+  const double *wrow = a.wtab + (int64_t)blockIdx.y * a.M;
+
+  int pcol[4], qcol[4];
+  bool pok[4], qok[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int P = P0 + lc + 16 * c, Q = Q0 + lc + 16 * c;
+    pok[c] = P < N;
+    qok[c] = Q < N;
+    pcol[c] = pok[c] ? P : 0;
+    qcol[c] = qok[c] ? Q : 0;
+  }
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int li = lane & 15, lk = lane >> 4;
+
+  f4 accR[2][2], accI[2][2];
+  double hR[2][2][4], hI[2][2][4];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      accR[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+      accI[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) hR[x][y][r] = hI[x][y][r] = 0.0;
+    }
+
+  float2 sa[NPASS][4], sb[NPASS][4];
+  double sw[NPASS];
+  bool smv[NPASS];
+  auto load = [&](int m0) {
+#pragma unroll
+    for (int ps = 0; ps < NPASS; ++ps) {
+      const int m = m0 + ps * RPI + lrow;
+      smv[ps] = m < M;
+      const int mc = smv[ps] ? m : 0;
+      sw[ps] = wrow[mc];
+      const int64_t ro = (int64_t)mc * N;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        sa[ps][c] = bb[ro + pcol[c]];
+        sb[ps][c] = bb[ro + qcol[c]];
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int ps = 0; ps < NPASS; ++ps) {
+      const float w = smv[ps] ? (float)sw[ps] : 0.f;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float2 z = make_float2(0.f, 0.f);
+        const float2 x = (smv[ps] && pok[c]) ? sa[ps][c] : z;
+        const float2 y = qok[c] ? sb[ps][c] : z;
+        lds[buf][0][ps * RPI + lrow][lc + 16 * c] = x;
+        lds[buf][1][ps * RPI + lrow][lc + 16 * c] = make_float2(w * y.x, w * y.y);
+      }
+    }
+  };
+  auto contract = [&](int buf) {
+#pragma unroll
+    for (int ks = 0; ks < KT / 4; ++ks) {
+      float2 av[2], bv[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) av[x] = lds[buf][0][ks * 4 + lk][wr * 32 + x * 16 + li];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bv[y] = lds[buf][1][ks * 4 + lk][wc * 32 + y * 16 + li];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) accR[x][y] = mfma32(av[x].x, bv[y].x, accR[x][y]);
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) accI[x][y] = mfma32(av[x].x, bv[y].y, accI[x][y]);
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) accR[x][y] = mfma32(av[x].y, bv[y].y, accR[x][y]);
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) accI[x][y] = mfma32(-av[x].y, bv[y].x, accI[x][y]);
+    }
+  };
+  auto flush = [&]() {
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          hR[x][y][r] += (double)accR[x][y][r];
+          hI[x][y][r] += (double)accI[x][y][r];
+        }
+        accR[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+        accI[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+      }
+  };
+
+  constexpr int FLUSH_STEPS = FLUSH_ROWS / KT;
+  const int nsteps = (M + KT - 1) / KT;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int s = 0; s + 1 < nsteps; ++s) {
+    const int cur = s & 1;
+    load((s + 1) * KT);
+    __builtin_amdgcn_sched_barrier(0);
+    contract(cur);
+    __builtin_amdgcn_sched_barrier(0);
+    if ((s + 1) % FLUSH_STEPS == 0) flush();
+    store(cur ^ 1);
+    __syncthreads();
+  }
+  contract((nsteps - 1) & 1);
+  flush();
+
+  double2 *out = a.out + (int64_t)blockIdx.y * a.out_stride;
+  const double *dg = diag + (int64_t)blockIdx.y * N;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // f32 16x16 accumulator layout: register r of lane l holds row 4 (l/16) + r, column l%16
+        const int P = P0 + wr * 32 + x * 16 + 4 * lk + r;
+        const int Q = Q0 + wc * 32 + y * 16 + li;
+        if (P >= N || Q >= N) continue;
+        const double re = hR[x][y][r], im = hI[x][y][r];
+        if (is_diag) {
+          if (P < Q) continue;
+          if (P == Q) {
+            out[(int64_t)P * N + Q] = make_double2(dg[P], 0.0);
+            continue;
+          }
+        }
+        out[(int64_t)P * N + Q] = make_double2(re, im);
+        out[(int64_t)Q * N + P] = make_double2(re, -im);
+      }
+}
+
+// ------------------------------------------------------------------ split-BF16 MFMA
+// LDS holds, per operand, four planes (re hi, re lo, im hi, im lo) of [64 columns][32
+// rows] with the contraction index contiguous, padded to 40 rows so both the 16-byte
+// stores of the staging threads and the 16-byte fragment reads are conflict-free.
+constexpr int KB = 32;          // rows per K step (the k depth of one 16x16x32 MFMA)
+constexpr int KBP = KB + 8;     // padded plane pitch in bf16 elements
+
+__device__ __forceinline__ f4 mfma_bf16(const bf8 &a, const bf8 &b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ unsigned short bf16_bits(float x) {
+  __bf16 h = (__bf16)x;   // round to nearest even
+  return __builtin_bit_cast(unsigned short, h);
+}
+__device__ __forceinline__ float bf16_val(unsigned short b) {
+  return __builtin_bit_cast(float, (unsigned)b << 16);
+}
+
+__global__ __launch_bounds__(256) void chi0_bf16x3_kernel(Chi0Args a, const float2 *B32, const double *diag) {
+  // [buf][operand][plane][column][row]
+  __shared__ __attribute__((aligned(16))) unsigned short lds[2][2][4][TN][KBP];
+
+  const PointDesc pd = a.pts[blockIdx.y];
+  int tr, tc;
+  tile_of((int)blockIdx.x, tr, tc);
+  const int N = a.N;
+  const int M = (int)a.M;
+  const int P0 = tr * TN, Q0 = tc * TN;
+  const bool is_diag = (tr == tc);
+  const int tid = threadIdx.x;
+  // staging: thread -> column cl (64 consecutive columns per wave-row), rows 8 kg .. 8 kg + 7
+  const int cl = tid & 63, kg = tid >> 6;
+  const float2 *bb = B32 + (int64_t)pd.bslot * a.b_slot_stride;
+  const double *wrow = a.wtab + (int64_t)blockIdx.y * a.M;
+  const bool pok = P0 + cl < N, qok = Q0 + cl < N;
+  const int pcol = pok ? P0 + cl : 0, qcol = qok ? Q0 + cl : 0;
+
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int li = lane & 15, lk = lane >> 4;
+
+  f4 accR[2][2], accI[2][2];
+  double hR[2][2][4], hI[2][2][4];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      accR[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+      accI[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) hR[x][y][r] = hI[x][y][r] = 0.0;
+    }
+
+  float2 sa[8], sb[8];
+  float sw[8];
+  auto load = [&](int m0) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int m = m0 + 8 * kg + e;
+      const bool mv = m < M;
+      const int mc = mv ? m : 0;
+      sw[e] = mv ? (float)wrow[mc] : 0.f;
+      const int64_t ro = (int64_t)mc * N;
+      sa[e] = bb[ro + pcol];
+      sb[e] = bb[ro + qcol];
+      if (!mv) sa[e] = make_float2(0.f, 0.f);
+    }
+  };
+  auto store = [&](int buf) {
+    s8 ah[2], al[2], bh[2], bl[2];   // [re/im]
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float2 x = pok ? sa[e] : make_float2(0.f, 0.f);
+      const float2 y0 = qok ? sb[e] : make_float2(0.f, 0.f);
+      const float2 y = make_float2(sw[e] * y0.x, sw[e] * y0.y);
+      unsigned short h;
+      h = bf16_bits(x.x); ah[0][e] = (short)h; al[0][e] = (short)bf16_bits(x.x - bf16_val(h));
+      h = bf16_bits(x.y); ah[1][e] = (short)h; al[1][e] = (short)bf16_bits(x.y - bf16_val(h));
+      h = bf16_bits(y.x); bh[0][e] = (short)h; bl[0][e] = (short)bf16_bits(y.x - bf16_val(h));
+      h = bf16_bits(y.y); bh[1][e] = (short)h; bl[1][e] = (short)bf16_bits(y.y - bf16_val(h));
+    }
+    *reinterpret_cast<s8 *>(&lds[buf][0][0][cl][8 * kg]) = ah[0];
+    *reinterpret_cast<s8 *>(&lds[buf][0][1][cl][8 * kg]) = al[0];
+    *reinterpret_cast<s8 *>(&lds[buf][0][2][cl][8 * kg]) = ah[1];
+    *reinterpret_cast<s8 *>(&lds[buf][0][3][cl][8 * kg]) = al[1];
+    *reinterpret_cast<s8 *>(&lds[buf][1][0][cl][8 * kg]) = bh[0];
+    *reinterpret_cast<s8 *>(&lds[buf][1][1][cl][8 * kg]) = bl[0];
+    *reinterpret_cast<s8 *>(&lds[buf][1][2][cl][8 * kg]) = bh[1];
+    *reinterpret_cast<s8 *>(&lds[buf][1][3][cl][8 * kg]) = bl[1];
+  };
+  auto contract = [&](int buf) {
+    // fragments: lane l holds 8 consecutive rows 8 (l/16) .. +7 of column l%16 of a block
+    bf8 A[2][4], Bv[2][4];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl)
+        A[x][pl] = *reinterpret_cast<const bf8 *>(&lds[buf][0][pl][wr * 32 + x * 16 + li][8 * lk]);
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl)
+        Bv[y][pl] = *reinterpret_cast<const bf8 *>(&lds[buf][1][pl][wc * 32 + y * 16 + li][8 * lk]);
+    // -Ai for the imaginary part: flip the sign bits of the packed bf16 values
+    bf8 nAi[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        s8 v = __builtin_bit_cast(s8, A[x][2 + h]);
+        v ^= (short)0x8000;
+        nAi[x][h] = __builtin_bit_cast(bf8, v);
+      }
+    // conj(a) * b: Re += ar br + ai bi, Im += ar bi - ai br; each real product as
+    // hi*hi + hi*lo + lo*hi
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        accR[x][y] = mfma_bf16(A[x][0], Bv[y][0], accR[x][y]);
+        accI[x][y] = mfma_bf16(A[x][0], Bv[y][2], accI[x][y]);
+      }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        accR[x][y] = mfma_bf16(A[x][0], Bv[y][1], accR[x][y]);
+        accI[x][y] = mfma_bf16(A[x][0], Bv[y][3], accI[x][y]);
+      }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        accR[x][y] = mfma_bf16(A[x][1], Bv[y][0], accR[x][y]);
+        accI[x][y] = mfma_bf16(A[x][1], Bv[y][2], accI[x][y]);
+      }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        accR[x][y] = mfma_bf16(A[x][2], Bv[y][2], accR[x][y]);
+        accI[x][y] = mfma_bf16(nAi[x][0], Bv[y][0], accI[x][y]);
+      }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        accR[x][y] = mfma_bf16(A[x][2], Bv[y][3], accR[x][y]);
+        accI[x][y] = mfma_bf16(nAi[x][0], Bv[y][1], accI[x][y]);
+      }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        accR[x][y] = mfma_bf16(A[x][3], Bv[y][2], accR[x][y]);
+        accI[x][y] = mfma_bf16(nAi[x][1], Bv[y][0], accI[x][y]);
+      }
+  };
+  auto flush = [&]() {
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          hR[x][y][r] += (double)accR[x][y][r];
+          hI[x][y][r] += (double)accI[x][y][r];
+        }
+        accR[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+        accI[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+      }
+  };
+
+  constexpr int FLUSH_STEPS = FLUSH_ROWS / KB;
+  const int nsteps = (M + KB - 1) / KB;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int s = 0; s + 1 < nsteps; ++s) {
+    const int cur = s & 1;
+    load((s + 1) * KB);
+    __builtin_amdgcn_sched_barrier(0);
+    contract(cur);
+    __builtin_amdgcn_sched_barrier(0);
+    if ((s + 1) % FLUSH_STEPS == 0) flush();
+    store(cur ^ 1);
+    __syncthreads();
+  }
+  contract((nsteps - 1) & 1);
+  flush();
+
+  double2 *out = a.out + (int64_t)blockIdx.y * a.out_stride;
+  const double *dg = diag + (int64_t)blockIdx.y * N;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int P = P0 + wr * 32 + x * 16 + 4 * lk + r;
+        const int Q = Q0 + wc * 32 + y * 16 + li;
+        if (P >= N || Q >= N) continue;
+        const double re = hR[x][y][r], im = hI[x][y][r];
+        if (is_diag) {
+          if (P < Q) continue;
+          if (P == Q) {
+            out[(int64_t)P * N + Q] = make_double2(dg[P], 0.0);
+            continue;
+          }
+        }
+        out[(int64_t)P * N + Q] = make_double2(re, im);
+        out[(int64_t)Q * N + P] = make_double2(re, -im);
+      }
+}
+
+inline unsigned grid_for(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+}  // namespace
+
+hipError_t launch_to_f32(hipStream_t s, const void *in, float2 *out, int64_t n, bool cplx) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(to_f32_kernel, dim3(grid_for(n)), dim3(256), 0, s, in, out, n, cplx ? 1 : 0);
+  return hipGetLastError();
+}
+
+int64_t diag_exact_scratch_doubles(int64_t M, int N, int npts) {
+  const int64_t nchunks = (M + DIAG_ROWS - 1) / DIAG_ROWS;
+  const int per = npts < DIAG_MAXP ? npts : DIAG_MAXP;
+  return nchunks * per * (int64_t)N;
+}
+
+hipError_t launch_diag_exact(hipStream_t s, const void *B, bool cplx, int64_t M, int N, const double *wtab,
+                             int npts, double *scratch, double *diag) {
+  const int nchunks = (int)((M + DIAG_ROWS - 1) / DIAG_ROWS);
+  for (int p0 = 0; p0 < npts; p0 += DIAG_MAXP) {
+    const int np = npts - p0 < DIAG_MAXP ? npts - p0 : DIAG_MAXP;
+    hipLaunchKernelGGL(diag_partial_kernel, dim3((unsigned)((N + 63) / 64), (unsigned)nchunks), dim3(256), 0,
+                       s, B, cplx ? 1 : 0, M, N, wtab + (int64_t)p0 * M, np, scratch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t tot = (int64_t)np * N;
+    hipLaunchKernelGGL(diag_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, scratch, nchunks,
+                       np, N, diag + (int64_t)p0 * N);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_chi0_mixed(hipStream_t s, const Chi0Args &a, int32_t npts, const float2 *B32,
+                             const double *diag, int prec) {
+  if (npts <= 0) return hipSuccess;
+  const int T = (a.N + TN - 1) / TN;
+  const dim3 grid((unsigned)(T * (T + 1) / 2), (unsigned)npts);
+  if (prec == 1)
+    hipLaunchKernelGGL(chi0_f32_kernel<16>, grid, dim3(256), 0, s, a, B32, diag);
+  else
+    hipLaunchKernelGGL(chi0_bf16x3_kernel, grid, dim3(256), 0, s, a, B32, diag);
+  return hipGetLastError();
+}
+
+}  // namespace rpa

@@ -64,6 +64,19 @@ hipError_t launch_zgemm_f64(hipStream_t s, const GemmArgs &a, int32_t batch);
 hipError_t launch_trln_f64(hipStream_t s, double2 *pi, int64_t stride, int32_t n, int32_t batch,
                            double *eps, int32_t *info, const int32_t *out_map);
 
+// ---- reduced-precision chi0 -----------------------------------------------------
+// FP64 (complex or real) [n] -> complex FP32 [n].
+hipError_t launch_to_f32(hipStream_t s, const void *in, float2 *out, int64_t n, bool cplx);
+// Exact FP64 diagonal diag[p][P] = sum_m wtab[p][m] |B_mP|^2 for npts points sharing one
+// FP64 B slab; `scratch` holds diag_exact_scratch_doubles(M, N, npts) doubles.
+int64_t diag_exact_scratch_doubles(int64_t M, int N, int npts);
+hipError_t launch_diag_exact(hipStream_t s, const void *B, bool cplx, int64_t M, int N, const double *wtab,
+                             int npts, double *scratch, double *diag);
+// chi0 with FP32 (prec 1) or split-BF16 (prec 2) MFMA from the FP32 copy B32 (slab stride
+// a.b_slot_stride), FP64 flush of partial sums and the exact diagonal `diag` [npts][N].
+hipError_t launch_chi0_mixed(hipStream_t s, const Chi0Args &a, int32_t npts, const float2 *B32,
+                             const double *diag, int prec);
+
 // E = sum_q zeta_q sum_j W_j eps[q][j] / (2 pi) in a fixed order.
 hipError_t launch_quadrature(hipStream_t s, const double *eps, const double *zeta_q,
                              const double *weight, int32_t nq, int32_t nw, double *E);

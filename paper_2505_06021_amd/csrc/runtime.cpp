@@ -239,7 +239,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   const int64_t npts = (int64_t)job.pq.size();
   job.eps.assign((size_t)npts, 0.0);
   if (npts == 0) return RPA_OK;
-  if (job.prec != RPA_FP64) return fail(RPA_E_ARG, "precision %d not available in this path", (int)job.prec);
+  const bool mixed = job.prec != RPA_FP64;
 
   const int64_t nn = (int64_t)N * N;
   const int64_t belem = cplx ? 16 : 8;
@@ -247,9 +247,11 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   const bool vh_direct = sys->memspace == RPA_MEM_DEVICE && cplx;
   const int64_t b_slot = b_direct ? 0 : M * N * belem;
   const int64_t vh_slot = vh_direct ? 0 : nn * 16;
-  const int64_t per_pt = 2 * nn * 16 + M * 8 + 64;
+  const int64_t b32_slot = mixed ? M * N * 8 : 0;
+  const int64_t per_pt = 2 * nn * 16 + M * 8 + (mixed ? (int64_t)N * 8 : 0) + 64;
+  const int64_t diag_scratch = mixed ? diag_exact_scratch_doubles(M, N, 16) * 8 : 0;
   const int64_t small = (int64_t)(hs.eps_occ.size() + hs.eps_virt.size() + hs.zeta_k.size()) * 8 +
-                        (int64_t)hs.kq.size() * 4 + npts * 32 + 4096;
+                        (int64_t)hs.kq.size() * 4 + npts * 32 + 4096 + diag_scratch;
 
   // distinct q's in order of first appearance; points grouped by q
   std::vector<int32_t> qs;
@@ -272,11 +274,11 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
     for (int i = g0; i < g0 + g && i < (int)qs.size(); ++i) c += (int64_t)by_q[qs[i]].size();
     return c;
   };
-  while (gq > 1 && gq * (b_slot + vh_slot) + std::min<int64_t>(pts_of(0, gq), 256) * per_pt > avail) --gq;
-  const int64_t rest = avail - gq * (b_slot + vh_slot);
+  while (gq > 1 && gq * (b_slot + vh_slot + b32_slot) + std::min<int64_t>(pts_of(0, gq), 256) * per_pt > avail) --gq;
+  const int64_t rest = avail - gq * (b_slot + vh_slot + b32_slot);
   if (rest < per_pt)
     return fail(RPA_E_NOMEM, "one q of this system needs %lld bytes, budget is %lld",
-                (long long)(b_slot + vh_slot + per_pt + small), (long long)budget);
+                (long long)(b_slot + vh_slot + b32_slot + per_pt + small), (long long)budget);
   int64_t pb_cap = rest / per_pt;
   int64_t max_group_pts = 0;
   for (size_t g0 = 0; g0 < qs.size(); g0 += gq) max_group_pts = std::max(max_group_pts, pts_of((int)g0, gq));
@@ -302,6 +304,13 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   RPA_TRY(ar.get("chi", pbatch * nn * 16, &d_chi));
   double *d_w;
   RPA_TRY(ar.get("wtab", pbatch * M * 8, (void **)&d_w));
+  float2 *d_B32 = nullptr;
+  double *d_diag = nullptr, *d_dscr = nullptr;
+  if (mixed) {
+    RPA_TRY(ar.get("B32", gq * b32_slot, (void **)&d_B32));
+    RPA_TRY(ar.get("diag", pbatch * N * 8, (void **)&d_diag));
+    RPA_TRY(ar.get("diag_scratch", diag_scratch, (void **)&d_dscr));
+  }
   RPA_TRY(ar.get("T", pbatch * nn * 16, &d_T));
 
   RPA_HIP(hipMemcpyAsync(d_eo, hs.eps_occ.data(), hs.eps_occ.size() * 8, hipMemcpyHostToDevice, st));
@@ -329,6 +338,13 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
           RPA_HIP(hipMemcpyAsync(dst, (const char *)sys->B + (int64_t)q * b_slot, (size_t)b_slot,
                                  hipMemcpyHostToDevice, st));
         }
+      }
+      if (mixed) {
+        const char *src = b_direct ? (const char *)sys->B + (int64_t)q * M * N * belem
+                                   : (const char *)d_B + (int64_t)s * b_slot;
+        if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0_AUX));
+        RPA_HIP(launch_to_f32(st, src, d_B32 + (int64_t)s * M * N, M * N, cplx));
+        if (prof) RPA_TRY(ctx.prof_end(st));
       }
       if (vh_slot) {
         double2 *dst = (double2 *)((char *)d_vh + (int64_t)s * vh_slot);
@@ -365,7 +381,9 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
         const int s = gslot[b0 + i];
         const int q = job.pq[(size_t)p];
         hp[i].q = q;
-        hp[i].bslot = b_direct ? q : s;
+        // the FP64 contraction reads a caller's device B by q and staged slabs by slot;
+        // the reduced-precision contraction always reads the slot's FP32 copy
+        hp[i].bslot = (b_direct && !mixed) ? q : s;
         hp[i].omega = job.pw[(size_t)p];
         vmap[i] = vh_direct ? q : s;
         imap[i] = i;
@@ -387,9 +405,28 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
       ca.out = (double2 *)d_chi;
       ca.out_stride = nn;
       ca.nk = hs.nk; ca.nocc = hs.nocc; ca.nvirt = hs.nvirt; ca.N = N; ca.M = M;
-      if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0));
+      if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0_AUX));
       RPA_HIP(launch_chi0_weights(st, ca, nb));
-      RPA_HIP(launch_chi0_f64(st, ca, nb, cplx, chi0_kt()));
+      if (mixed) {
+        // exact FP64 diagonal, one pass per B slab over the batch entries that use it
+        int i0 = 0;
+        while (i0 < nb) {
+          int i1 = i0 + 1;
+          while (i1 < nb && hp[i1].bslot == hp[i0].bslot) ++i1;
+          const int64_t slab = b_direct ? job.pq[(size_t)gp[b0 + i0]] : hp[i0].bslot;
+          const char *bsrc = (const char *)(b_direct ? sys->B : d_B) + slab * M * N * belem;
+          RPA_HIP(launch_diag_exact(st, bsrc, cplx, M, N, d_w + (int64_t)i0 * M, i1 - i0, d_dscr,
+                                    d_diag + (int64_t)i0 * N));
+          i0 = i1;
+        }
+        if (prof) RPA_TRY(ctx.prof_end(st));
+        if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0));
+        RPA_HIP(launch_chi0_mixed(st, ca, nb, d_B32, d_diag, (int)job.prec));
+      } else {
+        if (prof) RPA_TRY(ctx.prof_end(st));
+        if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0));
+        RPA_HIP(launch_chi0_f64(st, ca, nb, cplx, chi0_kt()));
+      }
       if (prof) RPA_TRY(ctx.prof_end(st));
 
       const double2 *vh = vh_direct ? (const double2 *)sys->vhalf : (const double2 *)d_vh;

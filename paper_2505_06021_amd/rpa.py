@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librpa.so")
 EXPORTS = ("rpa_init", "rpa_finalize", "rpa_last_error", "rpa_set_stream", "rpa_chi0", "rpa_pi",
            "rpa_trln", "rpa_energy", "rpa_points", "rpa_philox_B", "rpa_philox_words",
            "rpa_submit", "rpa_poll", "rpa_get_stats", "rpa_profile", "rpa_profile_read")
-KERNEL_KINDS = ("philox", "chi0", "pi", "trln", "other")
+KERNEL_KINDS = ("philox", "chi0", "pi", "trln", "other", "chi0_aux")
 
 
 class RpaError(RuntimeError):

@@ -1,0 +1,97 @@
+"""Reduced-precision chi0 (FP32 and split-BF16 MFMA with FP64 flush and exact FP64
+diagonal) against the FP64 oracle and the FP64 GPU path.
+
+Stated tolerances (measured margins are recorded in the test output):
+  chi0 FP32      ||d chi0||_F <= 1e-6 ||chi0||_F,  diagonal to 1e-13
+  chi0 BF16X3    ||d chi0||_F <= 1e-4 ||chi0||_F,  diagonal to 1e-13
+  energy FP32    |E - E_FP64| <= 1e-6 Ha per cell
+  energy BF16X3  |E - E_FP64| <= 2e-5 Ha per cell
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import rpa_oracle as orc
+from paper_2505_06021_amd import inputs
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+FP32, BF16X3 = 1, 2
+TOL_CHI0 = {FP32: 1e-6, BF16X3: 1e-4}
+TOL_E = {FP32: 1e-6, BF16X3: 2e-5}
+
+
+def say(msg):
+    print(f"[gpu-test] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2505_06021_amd import rpa
+    c = rpa.Context(0)
+    yield c
+    c.close()
+
+
+def ragged(nw=4):
+    return inputs.make_system("ragged", (2, 2, 1), 3, 7, 150, nw, 31, is_complex=True, sigma=0.15)
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16X3])
+def test_chi0_mixed_against_oracle(ctx, prec):
+    for name, s, pts in [("ragged", ragged(), [(0, 0.0), (3, 0.77)]),
+                         ("slab384", inputs.slab_3x3_384(), [(4, 0.3)])]:
+        for iq, om in pts:
+            say(f"chi0 prec={prec} {name} q={iq} w={om}")
+            ref = orc.chi0(s, iq, om)
+            got = ctx.chi0(s, iq, om, prec=prec)
+            err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+            say(f"  rel Frobenius error {err:.3e}")
+            assert err <= TOL_CHI0[prec]
+            d_ref = np.real(np.diagonal(ref))
+            d_got = np.real(np.diagonal(got))
+            assert np.max(np.abs(d_got - d_ref) / np.abs(d_ref)) <= 1e-13
+            assert np.abs(got - got.conj().T).max() == 0.0
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16X3])
+def test_chi0_mixed_real_system(ctx, prec):
+    say(f"chi0 real prec={prec}")
+    s = inputs.gamma_real_128().materialize_B()
+    ref = orc.chi0(s, 0, s.omega[2])
+    got = ctx.chi0(s, 0, s.omega[2], prec=prec)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= TOL_CHI0[prec]
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16X3])
+def test_energy_mixed_slab384(ctx, prec):
+    say(f"energy slab384 prec={prec}")
+    g = json.load(open(os.path.join(GOLD, "slab3x3_naux384.json")))
+    s = inputs.slab_3x3_384()
+    E64, eps64 = ctx.energy(s, prec=0)
+    E, eps = ctx.energy(s, prec=prec)
+    dE = abs(E - E64)
+    say(f"  E64 {E64:.12f}  E {E:.12f}  dE {dE:.3e} Ha  (oracle {g['E']:.12f})")
+    assert dE <= TOL_E[prec]
+    assert abs(E - g["E"]) <= TOL_E[prec] + 1e-10 * abs(g["E"])
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16X3])
+def test_energy_mixed_ragged_and_gamma(ctx, prec):
+    for s in (ragged(6), inputs.gamma_real_128()):
+        say(f"energy {s.name} prec={prec}")
+        E64, _ = ctx.energy(s, prec=0)
+        E, _ = ctx.energy(s, prec=prec)
+        say(f"  dE {abs(E - E64):.3e}")
+        assert abs(E - E64) <= TOL_E[prec]
+
+
+def test_mixed_is_deterministic(ctx):
+    say("mixed determinism")
+    s = ragged(3)
+    a = ctx.energy(s, prec=BF16X3)
+    b = ctx.energy(s, prec=BF16X3)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
