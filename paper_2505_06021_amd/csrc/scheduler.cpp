@@ -51,17 +51,21 @@ Scheduler::Scheduler(Ctx &c) : ctx_(c) {}
 
 Scheduler::~Scheduler() { shutdown(); }
 
-int64_t Scheduler::footprint(const HostSmall &hs, int nw, bool explicit_B) {
-  (void)explicit_B;
+int64_t Scheduler::footprint(const HostSmall &hs, int nw, rpa_precision prec) {
+  const bool mixed = prec != RPA_FP64;
   const int64_t N = hs.naux;
   const int64_t M = (int64_t)hs.nk * hs.nocc * hs.nvirt;
   const int64_t belem = hs.is_complex ? 16 : 8;
   const int64_t small = (int64_t)(hs.eps_occ.size() + hs.eps_virt.size() + hs.zeta_k.size()) * 8 +
-                        (int64_t)hs.kq.size() * 4 + (int64_t)hs.nq * nw * 32 + 4096 + (int64_t)(hs.nq + nw + 1) * 8;
-  const int64_t per_q = M * N * belem + N * N * 16 + (hs.is_complex ? 0 : N * N * 8);
-  const int64_t per_pt = 2 * N * N * 16 + 64;
+                        (int64_t)hs.kq.size() * 4 + (int64_t)hs.nq * nw * 32 + 4096 +
+                        (int64_t)(hs.nq + nw + 1) * 8 +
+                        (mixed ? diag_exact_scratch_doubles(M, (int)N, 16) * 8 : 0);
+  // one q staged at a time: FP64 B (and its FP32 copy), V^(1/2), and per point chi0, T,
+  // the weight table and the exact diagonal -- the same sizes run_points() budgets
+  const int64_t per_q = M * N * belem + N * N * 16 + (hs.is_complex ? 0 : N * N * 8) + (mixed ? M * N * 8 : 0);
+  const int64_t per_pt = 2 * N * N * 16 + M * 8 + (mixed ? N * 8 : 0) + 64;
   // allocation granularity slack per buffer
-  return small + per_q + (int64_t)nw * per_pt + 16 * 4096;
+  return small + per_q + (int64_t)nw * per_pt + 24 * 4096;
 }
 
 void Scheduler::start_locked() {
@@ -85,7 +89,7 @@ int Scheduler::submit(const rpa_system *sys, const rpa_freq *freq, rpa_precision
   const int64_t N = hs.naux;
   const int64_t M = (int64_t)hs.nk * hs.nocc * hs.nvirt;
   const int64_t belem = hs.is_complex ? 16 : 8;
-  j->need = footprint(hs, freq->nw, sys->B != nullptr);
+  j->need = footprint(hs, freq->nw, prec);
   if (j->need > ctx_.hbm_limit)
     return fail(RPA_E_NOMEM, "job needs %lld device bytes, above the limit %lld", (long long)j->need,
                 (long long)ctx_.hbm_limit);

@@ -23,7 +23,7 @@ class Scheduler {
   void shutdown();
 
   // Device bytes a job of this shape holds while it runs (one q at a time).
-  static int64_t footprint(const HostSmall &hs, int nw, bool explicit_B);
+  static int64_t footprint(const HostSmall &hs, int nw, rpa_precision prec);
 
  private:
   struct Job;

@@ -1,0 +1,104 @@
+"""Serving path (rpa_submit / rpa_poll): continuous batching with HBM admission.
+
+A job's result must not depend on what runs beside it: every job runs the same kernels
+on buffers it owns, so its energy and integrand are compared bit for bit with the
+synchronous call on the same inputs.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from paper_2505_06021_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-test] {msg}", file=sys.stderr, flush=True)
+
+
+def small_jobs():
+    specs = [((1, 1, 1), 4, 20, 96, 8), ((2, 2, 1), 3, 12, 130, 9), ((1, 1, 1), 6, 40, 200, 12),
+             ((2, 2, 1), 5, 22, 64, 10), ((3, 3, 1), 2, 10, 77, 8), ((1, 1, 1), 8, 30, 256, 16)]
+    return [inputs.make_system(f"j{i}", g, no, nv, na, nw, 500 + i, is_complex=True, sigma=0.1)
+            for i, (g, no, nv, na, nw) in enumerate(specs)]
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_results_alone_equal_results_in_the_mix(prec):
+    from paper_2505_06021_amd import rpa
+    jobs = small_jobs()
+    with rpa.Context(0) as ctx:
+        say(f"alone prec={prec}")
+        alone = [ctx.energy(s, prec=prec) for s in jobs]
+        say("submit all")
+        ids = [ctx.submit(s, prec=prec) for s in jobs]
+        for s, jid, (E, eps) in zip(jobs, ids, alone):
+            r = None
+            t0 = time.time()
+            while r is None:
+                r = ctx.poll(jid, timeout_ms=1000, nq=s.nq, nw=s.nw)
+                assert time.time() - t0 < 60
+            res, g = r
+            assert res["status"] == 0
+            assert res["E"] == E, (s.name, res["E"], E)
+            assert np.array_equal(g, eps)
+            assert res["t_submit"] <= res["t_start"] <= res["t_done"]
+            assert res["npoints"] == s.nq * s.nw
+        st = ctx.stats()
+        assert st["jobs_done"] == len(jobs) and st["jobs_queued"] == 0 and st["jobs_running"] == 0
+
+
+def test_admission_respects_the_hbm_limit():
+    from paper_2505_06021_amd import rpa
+    jobs = small_jobs()
+    biggest = 0
+    with rpa.Context(0) as probe:
+        ids = [probe.submit(s) for s in jobs]
+        for s, jid in zip(jobs, ids):
+            res, _ = probe.poll(jid, timeout_ms=-1, nq=s.nq, nw=s.nw)
+            biggest = max(biggest, res["hbm_bytes"])
+    limit = int(biggest * 1.5)     # at most one of the larger jobs at a time
+    say(f"limit {limit}")
+    with rpa.Context(0, hbm_limit=limit) as ctx:
+        ids = [ctx.submit(s) for s in jobs]
+        for s, jid in zip(jobs, ids):
+            res, _ = ctx.poll(jid, timeout_ms=-1, nq=s.nq, nw=s.nw)
+            assert res["status"] == 0
+        st = ctx.stats()
+        assert st["hbm_high_water"] <= limit
+        assert st["jobs_done"] == len(jobs)
+
+
+def test_job_that_can_never_fit_is_refused_at_submit():
+    from paper_2505_06021_amd import rpa
+    with rpa.Context(0, hbm_limit=1 << 20) as ctx:
+        with pytest.raises(rpa.RpaError) as e:
+            ctx.submit(small_jobs()[2])
+        assert e.value.code == rpa.RPA_E_NOMEM
+
+
+def test_poll_unknown_and_consumed_jobs():
+    from paper_2505_06021_amd import rpa
+    with rpa.Context(0) as ctx:
+        with pytest.raises(rpa.RpaError) as e:
+            ctx.poll(12345, timeout_ms=0)
+        assert e.value.code == rpa.RPA_E_UNKNOWN_JOB
+        s = small_jobs()[0]
+        jid = ctx.submit(s)
+        assert ctx.poll(jid, timeout_ms=-1, nq=s.nq, nw=s.nw) is not None
+        with pytest.raises(rpa.RpaError) as e:
+            ctx.poll(jid, timeout_ms=0)
+        assert e.value.code == rpa.RPA_E_UNKNOWN_JOB
+
+
+def test_finalize_with_pending_jobs_returns():
+    from paper_2505_06021_amd import rpa
+    ctx = rpa.Context(0)
+    for s in small_jobs() * 3:
+        ctx.submit(s)
+    t0 = time.time()
+    ctx.close()          # cancels queued jobs, waits for the running ones
+    assert time.time() - t0 < 120
