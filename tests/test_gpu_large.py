@@ -1,0 +1,54 @@
+"""Full-size parity on sampled points: the 6x6x1 N_aux = 1200 and 3x3x1 N_aux = 2400 slabs,
+with B streamed from the device Philox generator, in the launch configuration of the
+full energy (rpa_points groups the sampled points by q exactly like rpa_energy).
+
+The oracle values are stored (tests/golden/*_sampled.json, written by make_golden.py from
+the oracle alone).  FP64: |d eps| <= 1e-10 |eps|.  Reduced precision: |d eps| <= 1e-8
+|eps| (FP32) and 2e-7 |eps| (split-BF16); eps at these sizes is O(1e3 - 1e4) Ha.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2505_06021_amd import inputs
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL = {0: 1e-10, 1: 1e-8, 2: 2e-7}
+
+
+def say(msg):
+    print(f"[gpu-test] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2505_06021_amd import rpa
+    c = rpa.Context(0)
+    yield c
+    c.close()
+
+
+CASES = [("slab6x6_naux1200_sampled", inputs.slab_6x6_1200),
+         ("slab3x3_naux2400_sampled", inputs.slab_3x3_2400)]
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_sampled_points_full_size(ctx, name, make, prec):
+    path = os.path.join(GOLD, name + ".json")
+    if not os.path.exists(path):
+        pytest.skip(f"{name}.json not generated")
+    g = json.load(open(path))
+    s = make()
+    iq = [p["iq"] for p in g["points"]]
+    om = [p["omega"] for p in g["points"]]
+    ref = np.array([p["eps"] for p in g["points"]])
+    say(f"{name} prec={prec} points={list(zip(iq, om))}")
+    got = ctx.points(s, iq, om, prec=prec)
+    rel = np.abs(got - ref) / np.abs(ref)
+    say(f"  eps {got}  rel err {rel}")
+    assert np.all(rel <= TOL[prec])
