@@ -77,6 +77,89 @@ def cpu_baseline(make, budget_s=12.0, max_points=24):
                       f"{dt:.1f} s, NumPy FP64 with host Philox B"}
 
 
+def serving(args):
+    """Replay the Poisson job stream through rpa_submit/rpa_poll (continuous batching) and
+    compare with the same jobs run one at a time in FP64 (FIFO replay of measured service
+    times).  Prints one JSON line."""
+    import numpy as np
+    import torch
+    from paper_2505_06021_amd import inputs, rpa
+
+    jobs = inputs.serving_jobs(args.jobs, rate=args.rate, seed=77)
+    t_gen = time.perf_counter()
+    systems = []
+    for i, j in enumerate(jobs):
+        systems.append(inputs.make_job_system(j))
+        if i % 32 == 31:
+            print(f"[serve] inputs {i + 1}/{len(jobs)} ({time.perf_counter() - t_gen:.0f} s)",
+                  file=sys.stderr, flush=True)
+    prec = PREC_CODE[args.prec]
+    ctx = rpa.Context(0)
+    ctx.energy(systems[0], prec=prec)                   # warm the library and kernels
+    torch.cuda.synchronize()
+    ids = []
+    t0 = time.perf_counter()
+    for j, s in zip(jobs, systems):
+        delay = t0 + j["arrival"] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        ids.append(ctx.submit(s, prec=prec))
+        if len(ids) % 32 == 0:
+            print(f"[serve] submitted {len(ids)} at {time.perf_counter() - t0:.1f} s "
+                  f"{ctx.stats()}", file=sys.stderr, flush=True)
+    res = []
+    for n, (jid, s) in enumerate(zip(ids, systems)):
+        r, _ = ctx.poll(jid, timeout_ms=-1)
+        res.append(r)
+        if n % 64 == 63:
+            print(f"[serve] collected {n + 1}", file=sys.stderr, flush=True)
+    st = ctx.stats()
+    lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+    first = min(r["t_submit"] for r in res)
+    last = min(r["t_done"] for r in res), max(r["t_done"] for r in res)
+    npts = sum(r["npoints"] for r in res)
+    span = last[1] - first
+    # the same jobs one at a time in FP64: service times and reference energies
+    svc, dE, rel = [], [], []
+    for n, (s, r) in enumerate(zip(systems, res)):
+        ta = time.perf_counter()
+        E64, _ = ctx.energy(s, prec=0)
+        svc.append(time.perf_counter() - ta)
+        dE.append(abs(r["E"] - E64))
+        rel.append(abs(r["E"] - E64) / abs(E64))
+        if n % 32 == 31:
+            print(f"[serve] fp64 reference {n + 1}/{len(jobs)}", file=sys.stderr, flush=True)
+    ctx.close()
+    arr = np.array([j["arrival"] for j in jobs])
+    fin, t = [], 0.0
+    for a, sv in zip(arr, svc):
+        t = max(t, a) + sv
+        fin.append(t)
+    fifo_lat = np.array(fin) - arr
+    line = {
+        "metric": "serving: (q,w) RPA points/s with p50/p99 job latency",
+        "value": npts / span,
+        "unit": "points/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": span * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f64"}[args.prec],
+        "data": "synthetic job stream (seeded Poisson arrivals, log-uniform N_aux)",
+        "config": {"workload": "serving_stream", "jobs": len(jobs), "rate_per_s": args.rate,
+                   "naux": "log-U[200,1500]", "grids": "1x1x1 | 2x2x1 | 3x3x1", "nw": "U{8..16}",
+                   "chi0_precision": args.prec, "hbm_limit": st["hbm_limit"],
+                   "workers": int(os.environ.get("RPA_SERVE_WORKERS", "4"))},
+        "serving": {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                    "max_s": float(lat.max()), "points": int(npts), "span_s": span,
+                    "hbm_high_water": st["hbm_high_water"],
+                    "max_abs_dE_vs_fp64_Ha": float(max(dE)), "max_rel_dE_vs_fp64": float(max(rel)),
+                    "fifo_fp64": {"p50_s": float(np.percentile(fifo_lat, 50)),
+                                  "p99_s": float(np.percentile(fifo_lat, 99)),
+                                  "points_per_s": npts / (fin[-1] - arr[0]) if fin else None,
+                                  "total_service_s": float(sum(svc))}},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,12 +168,20 @@ def main():
     ap.add_argument("--workload", default="slab3x3_naux384", choices=sorted(WORKLOADS))
     ap.add_argument("--prec", default="fp64", choices=sorted(PREC_CODE))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", action="store_true",
+                    help="replay the serving job stream instead of the single-system step")
+    ap.add_argument("--jobs", type=int, default=256)
+    ap.add_argument("--rate", type=float, default=4.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the (q, w) points shard by q across GPUs, which this build does not do).",
               file=sys.stderr, flush=True)
         sys.exit(2)
+
+    if args.serve:
+        serving(args)
+        return
 
     import torch
     from paper_2505_06021_amd import inputs, rpa
