@@ -94,7 +94,7 @@ def serving(args):
             print(f"[serve] inputs {i + 1}/{len(jobs)} ({time.perf_counter() - t_gen:.0f} s)",
                   file=sys.stderr, flush=True)
     prec = PREC_CODE[args.prec]
-    ctx = rpa.Context(0)
+    ctx = rpa.Context(0, hbm_limit=int(args.hbm_limit_gb * 1e9))
     ctx.energy(systems[0], prec=prec)                   # warm the library and kernels
     torch.cuda.synchronize()
     ids = []
@@ -172,6 +172,8 @@ def main():
                     help="replay the serving job stream instead of the single-system step")
     ap.add_argument("--jobs", type=int, default=256)
     ap.add_argument("--rate", type=float, default=4.0)
+    ap.add_argument("--hbm-limit-gb", type=float, default=200.0,
+                    help="device-memory admission limit of the serving context")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
