@@ -189,6 +189,7 @@ int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega, rpa_
   a.kq = (const int32_t *)(da + nsmall * 8);
   a.pts = (const PointDesc *)(da + pd_off);
   a.wtab = wt;
+  a.ksplit = 1;
   a.out = out;
   a.out_stride = 0;
   a.nk = hs.nk; a.nocc = hs.nocc; a.nvirt = hs.nvirt; a.N = N; a.M = M;
@@ -256,7 +257,14 @@ int rpa_trln(rpa_ctx *ctx, int32_t n, int32_t batch, int32_t is_complex, int32_t
   int32_t *di;
   RPA_TRY(c.workspace("trln_eps", (int64_t)batch * 8, (void **)&de));
   RPA_TRY(c.workspace("trln_info", (int64_t)batch * 4, (void **)&di));
-  RPA_HIP(launch_trln_f64(c.stream, dp, nn, n, batch, de, di, nullptr));
+  if (trln_single()) {
+    RPA_HIP(launch_trln_f64(c.stream, dp, nn, n, batch, de, di, nullptr));
+  } else {
+    void *scr;
+    RPA_TRY(c.workspace("trln_scratch", trln_blocked_scratch_bytes(batch), &scr));
+    RPA_HIP(launch_negate(c.stream, dp, nn, n, batch));
+    RPA_HIP(launch_trln_blocked(c.stream, dp, nn, n, batch, de, di, nullptr, scr));
+  }
   std::vector<int32_t> info((size_t)batch);
   RPA_HIP(hipMemcpyAsync(info.data(), di, (size_t)batch * 4, hipMemcpyDeviceToHost, c.stream));
   RPA_TRY(from_device(out, de, (size_t)batch * 8, memspace, c.stream));

@@ -14,6 +14,8 @@
 // panels go to a double-buffered LDS tile.  Four waves each own a 32 x 32 sub-tile (2 x 2 MFMA blocks, Re and Im
 // accumulators).  Off-diagonal tiles also store their conjugate transpose, so the full
 // Hermitian matrix is produced from the lower-triangle work only.
+#include <cmath>
+
 #include "common.hpp"
 
 namespace rpa {
@@ -155,7 +157,11 @@ __global__ __launch_bounds__(256) void chi0_f64_kernel(Chi0Args a) {
   int tr, tc;
   tile_of((int)blockIdx.x, tr, tc);
   const int N = a.N;
-  const int M = (int)a.M;
+  // rows [mlo, mhi) of the contraction belong to split blockIdx.z
+  const int ms = (int)((((a.M + a.ksplit - 1) / a.ksplit) + KT - 1) / KT) * KT;
+  const int mlo = (int)blockIdx.z * ms;
+  const int mhi = mlo + ms < (int)a.M ? mlo + ms : (int)a.M;
+  const int M = mhi;
   const int P0 = tr * TN, Q0 = tc * TN;
   const bool diag = (tr == tc);
 
@@ -194,13 +200,13 @@ __global__ __launch_bounds__(256) void chi0_f64_kernel(Chi0Args a) {
     }
 
   Stage<NPASS> st;
-  const int nsteps = (M + KT - 1) / KT;
-  load_stage<CPLX_B, NPASS, RPI>(st, bbase, wrow, 0, lrow, row_active, M, N, pcol, qcol);
+  const int nsteps = mhi > mlo ? (mhi - mlo + KT - 1) / KT : 1;
+  load_stage<CPLX_B, NPASS, RPI>(st, bbase, wrow, mlo, lrow, row_active, M, N, pcol, qcol);
   store_stage<KT, NPASS, RPI>(st, lds[0][0], lds[0][1], lrow, lc, row_active, pok, qok);
   __syncthreads();
   for (int s = 0; s + 1 < nsteps; ++s) {
     const int cur = s & 1;
-    load_stage<CPLX_B, NPASS, RPI>(st, bbase, wrow, (s + 1) * KT, lrow, row_active, M, N, pcol, qcol);
+    load_stage<CPLX_B, NPASS, RPI>(st, bbase, wrow, mlo + (s + 1) * KT, lrow, row_active, M, N, pcol, qcol);
     // keep the next tile's loads issued ahead of the MFMA block (their latency hides under it)
     __builtin_amdgcn_sched_barrier(0);
     contract<KT>(lds[cur][0], lds[cur][1], wr, wc, li, lk, accR, accI);
@@ -210,7 +216,7 @@ __global__ __launch_bounds__(256) void chi0_f64_kernel(Chi0Args a) {
   }
   contract<KT>(lds[(nsteps - 1) & 1][0], lds[(nsteps - 1) & 1][1], wr, wc, li, lk, accR, accI);
 
-  double2 *out = a.out + (int64_t)blockIdx.y * a.out_stride;
+  double2 *out = (blockIdx.z == 0 ? a.out : a.partial) + (int64_t)blockIdx.y * a.out_stride;
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -235,7 +241,32 @@ __global__ __launch_bounds__(256) void chi0_f64_kernel(Chi0Args a) {
       }
 }
 
+// out += partial (the second row split), full matrices: a fixed order, so repeatable
+__global__ __launch_bounds__(256) void split_reduce_kernel(const double2 *partial, int64_t n, double2 *out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double2 a = out[i], b = partial[i];
+    out[i] = make_double2(a.x + b.x, a.y + b.y);
+  }
+}
+
 }  // namespace
+
+int32_t chi0_pick_ksplit(int64_t work, int64_t slots, int64_t M) {
+  // fraction of the last round of workgroups that is busy, for 1..4 splits; a split must
+  // keep at least 512 rows and costs ~2% for its extra reduction traffic
+  int best = 1;
+  double best_eff = 0.0;
+  for (int s = 1; s <= 2; ++s) {
+    if (s > 1 && M / s < 512) break;
+    const double rounds = (double)(work * s) / (double)slots;
+    const double eff = rounds / std::ceil(rounds) * (1.0 - 0.02 * (s - 1));
+    if (eff > best_eff + 1e-9) {
+      best_eff = eff;
+      best = s;
+    }
+  }
+  return best;
+}
 
 hipError_t launch_chi0_weights(hipStream_t s, const Chi0Args &a, int32_t npts) {
   const int64_t total = (int64_t)npts * a.M;
@@ -249,7 +280,8 @@ hipError_t launch_chi0_weights(hipStream_t s, const Chi0Args &a, int32_t npts) {
 hipError_t launch_chi0_f64(hipStream_t s, const Chi0Args &a, int32_t npts, bool cplx_b, int kt) {
   if (npts <= 0) return hipSuccess;
   const int T = (a.N + TN - 1) / TN;
-  const dim3 grid((unsigned)(T * (T + 1) / 2), (unsigned)npts);
+  const int ks = a.ksplit > 1 ? 2 : 1;   // split 0 writes a.out, split 1 writes a.partial
+  const dim3 grid((unsigned)(T * (T + 1) / 2), (unsigned)npts, (unsigned)ks);
 #define RPA_CHI0_LAUNCH(C, K) hipLaunchKernelGGL((chi0_f64_kernel<C, K>), grid, dim3(256), 0, s, a)
   if (kt == 8) {
     if (cplx_b) RPA_CHI0_LAUNCH(true, 8); else RPA_CHI0_LAUNCH(false, 8);
@@ -259,6 +291,16 @@ hipError_t launch_chi0_f64(hipStream_t s, const Chi0Args &a, int32_t npts, bool 
     if (cplx_b) RPA_CHI0_LAUNCH(true, 16); else RPA_CHI0_LAUNCH(false, 16);
   }
 #undef RPA_CHI0_LAUNCH
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || ks == 1) return e;
+  return launch_split_add(s, a.partial, (int64_t)npts * a.out_stride, a.out);
+}
+
+hipError_t launch_split_add(hipStream_t s, const double2 *partial, int64_t n, double2 *out) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) return hipSuccess;
+  hipLaunchKernelGGL(split_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, partial, n, out);
   return hipGetLastError();
 }
 

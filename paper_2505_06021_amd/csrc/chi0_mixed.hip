@@ -115,7 +115,10 @@ __global__ __launch_bounds__(256) void chi0_f32_kernel(Chi0Args a, const float2 
   int tr, tc;
   tile_of((int)blockIdx.x, tr, tc);
   const int N = a.N;
-  const int M = (int)a.M;
+  // rows [mlo, mhi) of the contraction belong to split blockIdx.z
+  const int ms = (int)((((a.M + gridDim.z - 1) / gridDim.z) + KT - 1) / KT) * KT;
+  const int mlo = (int)blockIdx.z * ms;
+  const int M = mlo + ms < (int)a.M ? mlo + ms : (int)a.M;
   const int P0 = tr * TN, Q0 = tc * TN;
   const bool is_diag = (tr == tc);
   const int tid = threadIdx.x;
@@ -223,13 +226,13 @@ __global__ __launch_bounds__(256) void chi0_f32_kernel(Chi0Args a, const float2 
   };
 
   constexpr int FLUSH_STEPS = FLUSH_ROWS / KT;
-  const int nsteps = (M + KT - 1) / KT;
-  load(0);
+  const int nsteps = M > mlo ? (M - mlo + KT - 1) / KT : 1;
+  load(mlo);
   store(0);
   __syncthreads();
   for (int s = 0; s + 1 < nsteps; ++s) {
     const int cur = s & 1;
-    load((s + 1) * KT);
+    load(mlo + (s + 1) * KT);
     __builtin_amdgcn_sched_barrier(0);
     contract(cur);
     __builtin_amdgcn_sched_barrier(0);
@@ -240,8 +243,9 @@ __global__ __launch_bounds__(256) void chi0_f32_kernel(Chi0Args a, const float2 
   contract((nsteps - 1) & 1);
   flush();
 
-  double2 *out = a.out + (int64_t)blockIdx.y * a.out_stride;
+  double2 *out = (blockIdx.z == 0 ? a.out : a.partial) + (int64_t)blockIdx.y * a.out_stride;
   const double *dg = diag + (int64_t)blockIdx.y * N;
+  const bool first = blockIdx.z == 0;   // the exact diagonal enters once
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -256,7 +260,7 @@ __global__ __launch_bounds__(256) void chi0_f32_kernel(Chi0Args a, const float2 
         if (is_diag) {
           if (P < Q) continue;
           if (P == Q) {
-            out[(int64_t)P * N + Q] = make_double2(dg[P], 0.0);
+            out[(int64_t)P * N + Q] = make_double2(first ? dg[P] : 0.0, 0.0);
             continue;
           }
         }
@@ -292,7 +296,9 @@ __global__ __launch_bounds__(256) void chi0_bf16x3_kernel(Chi0Args a, const floa
   int tr, tc;
   tile_of((int)blockIdx.x, tr, tc);
   const int N = a.N;
-  const int M = (int)a.M;
+  const int ms = (int)((((a.M + gridDim.z - 1) / gridDim.z) + KB - 1) / KB) * KB;
+  const int mlo = (int)blockIdx.z * ms;
+  const int M = mlo + ms < (int)a.M ? mlo + ms : (int)a.M;
   const int P0 = tr * TN, Q0 = tc * TN;
   const bool is_diag = (tr == tc);
   const int tid = threadIdx.x;
@@ -440,13 +446,13 @@ __global__ __launch_bounds__(256) void chi0_bf16x3_kernel(Chi0Args a, const floa
   };
 
   constexpr int FLUSH_STEPS = FLUSH_ROWS / KB;
-  const int nsteps = (M + KB - 1) / KB;
-  load(0);
+  const int nsteps = M > mlo ? (M - mlo + KB - 1) / KB : 1;
+  load(mlo);
   store(0);
   __syncthreads();
   for (int s = 0; s + 1 < nsteps; ++s) {
     const int cur = s & 1;
-    load((s + 1) * KB);
+    load(mlo + (s + 1) * KB);
     __builtin_amdgcn_sched_barrier(0);
     contract(cur);
     __builtin_amdgcn_sched_barrier(0);
@@ -457,8 +463,9 @@ __global__ __launch_bounds__(256) void chi0_bf16x3_kernel(Chi0Args a, const floa
   contract((nsteps - 1) & 1);
   flush();
 
-  double2 *out = a.out + (int64_t)blockIdx.y * a.out_stride;
+  double2 *out = (blockIdx.z == 0 ? a.out : a.partial) + (int64_t)blockIdx.y * a.out_stride;
   const double *dg = diag + (int64_t)blockIdx.y * N;
+  const bool first = blockIdx.z == 0;   // the exact diagonal enters once
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -472,7 +479,7 @@ __global__ __launch_bounds__(256) void chi0_bf16x3_kernel(Chi0Args a, const floa
         if (is_diag) {
           if (P < Q) continue;
           if (P == Q) {
-            out[(int64_t)P * N + Q] = make_double2(dg[P], 0.0);
+            out[(int64_t)P * N + Q] = make_double2(first ? dg[P] : 0.0, 0.0);
             continue;
           }
         }
@@ -524,12 +531,15 @@ hipError_t launch_chi0_mixed(hipStream_t s, const Chi0Args &a, int32_t npts, con
                              const double *diag, int prec) {
   if (npts <= 0) return hipSuccess;
   const int T = (a.N + TN - 1) / TN;
-  const dim3 grid((unsigned)(T * (T + 1) / 2), (unsigned)npts);
+  const int ks = a.ksplit > 1 ? 2 : 1;   // split 0 writes a.out, split 1 writes a.partial
+  const dim3 grid((unsigned)(T * (T + 1) / 2), (unsigned)npts, (unsigned)ks);
   if (prec == 1)
     hipLaunchKernelGGL(chi0_f32_kernel<16>, grid, dim3(256), 0, s, a, B32, diag);
   else
     hipLaunchKernelGGL(chi0_bf16x3_kernel, grid, dim3(256), 0, s, a, B32, diag);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || ks == 1) return e;
+  return launch_split_add(s, a.partial, (int64_t)npts * a.out_stride, a.out);
 }
 
 }  // namespace rpa

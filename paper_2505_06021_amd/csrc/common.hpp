@@ -28,6 +28,9 @@ struct Chi0Args {
   double *wtab;             // [npts][M] w_m zeta_k of every contraction row
   double2 *out;             // [npts][N][N] complex
   int64_t out_stride;       // complex elements between outputs
+  int32_t ksplit;           // 2: the contraction rows are split in two halves; the first
+                            // writes out, the second partial, and out += partial follows
+  double2 *partial;         // [npts][N][N] (used when ksplit == 2)
   int32_t nk, nocc, nvirt, N;
   int64_t M;                // nk * nocc * nvirt
 };
@@ -41,6 +44,7 @@ struct GemmArgs {
   const int32_t *b_map;   // optional: B index = b_map[b]
   int32_t N;
   int32_t lower_only;     // compute only the tiles on or below the diagonal
+  int32_t negate;         // store -C instead of C
 };
 
 // ---- launchers (each returns the launch's hipError_t) -----------------------
@@ -53,8 +57,13 @@ hipError_t launch_philox_words(hipStream_t s, uint64_t seed, int32_t nk, int32_t
 
 // Fill a.wtab for the npts points of a launch (must precede the contraction launch).
 hipError_t launch_chi0_weights(hipStream_t s, const Chi0Args &a, int32_t npts);
-// kt: rows per K step (8, 16 or 32).
+// kt: rows per K step (8, 16 or 32).  With a.ksplit == 2 the launch also adds the second
+// half's result into a.out (fixed order, repeatable).
 hipError_t launch_chi0_f64(hipStream_t s, const Chi0Args &a, int32_t npts, bool cplx_b, int kt);
+// Number of row splits (1 or 2) that best fills `slots` concurrent workgroups for `work` tiles.
+int32_t chi0_pick_ksplit(int64_t work, int64_t slots, int64_t M);
+// out[i] += partial[i] for n complex elements.
+hipError_t launch_split_add(hipStream_t s, const double2 *partial, int64_t n, double2 *out);
 
 hipError_t launch_zgemm_f64(hipStream_t s, const GemmArgs &a, int32_t batch);
 
@@ -76,6 +85,15 @@ hipError_t launch_diag_exact(hipStream_t s, const void *B, bool cplx, int64_t M,
 // a.b_slot_stride), FP64 flush of partial sums and the exact diagonal `diag` [npts][N].
 hipError_t launch_chi0_mixed(hipStream_t s, const Chi0Args &a, int32_t npts, const float2 *B32,
                              const double *diag, int prec);
+
+// Blocked Cholesky log-det over the whole GPU on W = -Pi (see trln_blocked.hip):
+// eps[out_map[b]] = ln det(1 - Pi_b) + Re Tr Pi_b, info_out[out_map[b]] = -1 or the failing
+// column.  W is overwritten; scratch holds trln_blocked_scratch_bytes(batch) bytes.
+int64_t trln_blocked_scratch_bytes(int32_t batch);
+hipError_t launch_trln_blocked(hipStream_t s, double2 *w, int64_t stride, int32_t n, int32_t batch, double *eps,
+                               int32_t *info_out, const int32_t *out_map, void *scratch);
+// P <- -P elementwise for batch matrices of n x n.
+hipError_t launch_negate(hipStream_t s, double2 *p, int64_t stride, int32_t n, int32_t batch);
 
 // E = sum_q zeta_q sum_j W_j eps[q][j] / (2 pi) in a fixed order.
 hipError_t launch_quadrature(hipStream_t s, const double *eps, const double *zeta_q,

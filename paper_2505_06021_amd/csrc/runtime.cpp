@@ -209,21 +209,47 @@ int chi0_kt() {
   return kt;
 }
 
+bool trln_single() {
+  static bool v = [] {
+    const char *e = getenv("RPA_TRLN_SINGLE");
+    return e && atoi(e) != 0;
+  }();
+  return v;
+}
+
 namespace {
 
 struct Arena {
+  // All device buffers of one run_points() call come from a single slab: planned first,
+  // then allocated at once.  In cache mode the slab is the context's grow-only
+  // "pipeline" workspace; when it has to grow, every cached buffer is released first, so
+  // the call never holds more than its own plan plus what other users hold.
   Ctx &ctx;
   bool use_cache;
-  std::vector<DevBuf> owned;
+  DevBuf owned;
+  std::vector<std::pair<int64_t, void **>> reqs;
+  int64_t total = 0;
   Arena(Ctx &c, bool cache) : ctx(c), use_cache(cache) {}
-  ~Arena() {
-    for (auto &b : owned) ctx.release(b);
+  ~Arena() { ctx.release(owned); }
+  void plan(int64_t bytes, void **out) {
+    reqs.push_back({total, out});
+    total += (std::max<int64_t>(bytes, 1) + 255) / 256 * 256;
   }
-  int get(const char *name, int64_t bytes, void **out) {
-    if (use_cache) return ctx.workspace(name, bytes, out);
-    owned.emplace_back();
-    RPA_TRY(ctx.alloc(owned.back(), bytes, name));
-    *out = owned.back().p;
+  int commit(hipStream_t st) {
+    void *base;
+    if (use_cache) {
+      DevBuf &b = ctx.cache["pipeline"];
+      if (!b.p || b.bytes < total) {
+        RPA_HIP(hipStreamSynchronize(st));
+        ctx.free_cache();
+        RPA_TRY(ctx.alloc(ctx.cache["pipeline"], total, "pipeline workspace"));
+      }
+      base = ctx.cache["pipeline"].p;
+    } else {
+      RPA_TRY(ctx.alloc(owned, total, "job workspace"));
+      base = owned.p;
+    }
+    for (auto &r : reqs) *r.second = (char *)base + r.first;
     return RPA_OK;
   }
 };
@@ -248,7 +274,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   const int64_t b_slot = b_direct ? 0 : M * N * belem;
   const int64_t vh_slot = vh_direct ? 0 : nn * 16;
   const int64_t b32_slot = mixed ? M * N * 8 : 0;
-  const int64_t per_pt = 2 * nn * 16 + M * 8 + (mixed ? (int64_t)N * 8 : 0) + 64;
+  const int64_t per_pt = 2 * nn * 16 + M * 8 + (mixed ? (int64_t)N * 8 : 0) + trln_blocked_scratch_bytes(1) + 64;
   const int64_t diag_scratch = mixed ? diag_exact_scratch_doubles(M, N, 16) * 8 : 0;
   const int64_t small = (int64_t)(hs.eps_occ.size() + hs.eps_virt.size() + hs.zeta_k.size()) * 8 +
                         (int64_t)hs.kq.size() * 4 + npts * 32 + 4096 + diag_scratch;
@@ -290,28 +316,39 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   int32_t *d_kq, *d_info, *d_amap;
   PointDesc *d_pts;
   void *d_B = nullptr, *d_vh = nullptr, *d_chi = nullptr, *d_T = nullptr, *d_vstage = nullptr;
-  RPA_TRY(ar.get("eps_occ", (int64_t)hs.eps_occ.size() * 8, (void **)&d_eo));
-  RPA_TRY(ar.get("eps_virt", (int64_t)hs.eps_virt.size() * 8, (void **)&d_ev));
-  RPA_TRY(ar.get("zeta_k", (int64_t)hs.zeta_k.size() * 8, (void **)&d_zk));
-  RPA_TRY(ar.get("kq", (int64_t)hs.kq.size() * 4, (void **)&d_kq));
-  RPA_TRY(ar.get("eps_out", npts * 8, (void **)&d_eps));
-  RPA_TRY(ar.get("info", npts * 4, (void **)&d_info));
-  RPA_TRY(ar.get("pts", pbatch * (int64_t)sizeof(PointDesc), (void **)&d_pts));
-  RPA_TRY(ar.get("maps", 3 * pbatch * 4, (void **)&d_amap));
-  if (b_slot) RPA_TRY(ar.get("B", gq * b_slot, &d_B));
-  if (vh_slot) RPA_TRY(ar.get("vhalf", gq * vh_slot, &d_vh));
-  if (vh_slot && !cplx && sys->memspace == RPA_MEM_HOST) RPA_TRY(ar.get("vstage", nn * 8, &d_vstage));
-  RPA_TRY(ar.get("chi", pbatch * nn * 16, &d_chi));
+  ar.plan((int64_t)hs.eps_occ.size() * 8, (void **)&d_eo);
+  ar.plan((int64_t)hs.eps_virt.size() * 8, (void **)&d_ev);
+  ar.plan((int64_t)hs.zeta_k.size() * 8, (void **)&d_zk);
+  ar.plan((int64_t)hs.kq.size() * 4, (void **)&d_kq);
+  ar.plan(npts * 8, (void **)&d_eps);
+  ar.plan(npts * 4, (void **)&d_info);
+  ar.plan(pbatch * (int64_t)sizeof(PointDesc), (void **)&d_pts);
+  ar.plan(3 * pbatch * 4, (void **)&d_amap);
+  if (b_slot) ar.plan(gq * b_slot, &d_B);
+  if (vh_slot) ar.plan(gq * vh_slot, &d_vh);
+  if (vh_slot && !cplx && sys->memspace == RPA_MEM_HOST) ar.plan(nn * 8, &d_vstage);
+  ar.plan(pbatch * nn * 16, &d_chi);
   double *d_w;
-  RPA_TRY(ar.get("wtab", pbatch * M * 8, (void **)&d_w));
+  ar.plan(pbatch * M * 8, (void **)&d_w);
   float2 *d_B32 = nullptr;
   double *d_diag = nullptr, *d_dscr = nullptr;
   if (mixed) {
-    RPA_TRY(ar.get("B32", gq * b32_slot, (void **)&d_B32));
-    RPA_TRY(ar.get("diag", pbatch * N * 8, (void **)&d_diag));
-    RPA_TRY(ar.get("diag_scratch", diag_scratch, (void **)&d_dscr));
+    ar.plan(gq * b32_slot, (void **)&d_B32);
+    ar.plan(pbatch * N * 8, (void **)&d_diag);
+    ar.plan(diag_scratch, (void **)&d_dscr);
   }
-  RPA_TRY(ar.get("T", pbatch * nn * 16, &d_T));
+  ar.plan(pbatch * nn * 16, &d_T);
+  void *d_tscr;
+  ar.plan(trln_blocked_scratch_bytes((int32_t)pbatch), &d_tscr);
+  double *d_qw = nullptr;
+  ar.plan((int64_t)(hs.nq + 4097) * 8, (void **)&d_qw);
+  RPA_TRY(ar.commit(st));
+  const bool single_wg_trln = trln_single();
+  // two-way row split of the contraction when it fills the last round of workgroups
+  // better; the second half's result goes to the T buffer, which is free until the
+  // sandwich
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx.device) != hipSuccess) ncu = 256;
 
   RPA_HIP(hipMemcpyAsync(d_eo, hs.eps_occ.data(), hs.eps_occ.size() * 8, hipMemcpyHostToDevice, st));
   RPA_HIP(hipMemcpyAsync(d_ev, hs.eps_virt.data(), hs.eps_virt.size() * 8, hipMemcpyHostToDevice, st));
@@ -404,6 +441,13 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
       ca.wtab = d_w;
       ca.out = (double2 *)d_chi;
       ca.out_stride = nn;
+      {
+        // FP64 and FP32 contraction kernels keep two workgroups per CU, split-BF16 one
+        const int64_t T = (N + 63) / 64;
+        const int64_t slots = (job.prec == RPA_BF16X3 ? 1LL : 2LL) * ncu;
+        ca.ksplit = chi0_pick_ksplit(T * (T + 1) / 2 * nb, slots, M) >= 2 ? 2 : 1;
+        ca.partial = (double2 *)d_T;
+      }
       ca.nk = hs.nk; ca.nocc = hs.nocc; ca.nvirt = hs.nvirt; ca.N = N; ca.M = M;
       if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0_AUX));
       RPA_HIP(launch_chi0_weights(st, ca, nb));
@@ -440,10 +484,15 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
       g2.A = vh; g2.a_stride = nn; g2.a_map = d_vmap; g2.a_div = 1;
       g2.B = (const double2 *)d_T; g2.b_stride = nn; g2.b_map = d_imap; g2.b_div = 1;
       g2.C = (double2 *)d_chi; g2.c_stride = nn; g2.N = N; g2.lower_only = 1;
+      g2.negate = single_wg_trln ? 0 : 1;   // the blocked factorisation takes W = -Pi
       RPA_HIP(launch_zgemm_f64(st, g2, nb));
       if (prof) RPA_TRY(ctx.prof_end(st));
       if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_TRLN));
-      RPA_HIP(launch_trln_f64(st, (double2 *)d_chi, nn, N, nb, d_eps, d_info, d_emap));
+      if (single_wg_trln) {
+        RPA_HIP(launch_trln_f64(st, (double2 *)d_chi, nn, N, nb, d_eps, d_info, d_emap));
+      } else {
+        RPA_HIP(launch_trln_blocked(st, (double2 *)d_chi, nn, N, nb, d_eps, d_info, d_emap, d_tscr));
+      }
       if (prof) RPA_TRY(ctx.prof_end(st));
     }
   }
@@ -451,8 +500,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
     // E = sum_q zeta_q sum_j W_j eps(q, w_j) / (2 pi) over the full q-major grid, on the device
     const int nq = hs.nq, nw = (int)job.weight.size();
     if ((int64_t)nq * nw != npts) return fail(RPA_E_INTERNAL, "quadrature needs the full point grid");
-    double *d_qw;
-    RPA_TRY(ar.get("quad", (int64_t)(nq + nw + 1) * 8, (void **)&d_qw));
+    if (nw > 4096) return fail(RPA_E_ARG, "nw = %d above 4096", nw);
     std::vector<double> &hq = job.qstage;
     hq.assign(hs.zeta_q.begin(), hs.zeta_q.end());
     hq.insert(hq.end(), job.weight.begin(), job.weight.end());

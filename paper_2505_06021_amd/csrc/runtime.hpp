@@ -120,6 +120,8 @@ int run_points(Ctx &ctx, hipStream_t stream, PointJob &job, int64_t mem_budget, 
 
 // Rows per K step of the FP64 chi0 kernel (RPA_CHI0_KT = 8, 16 or 32; default 16).
 int chi0_kt();
+// RPA_TRLN_SINGLE=1 selects the one-workgroup-per-matrix Cholesky instead of the blocked one.
+bool trln_single();
 
 }  // namespace rpa
 

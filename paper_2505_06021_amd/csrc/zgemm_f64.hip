@@ -4,9 +4,9 @@
 // only the lower triangle of the Hermitian Pi feeds the Cholesky factorisation and
 // the trace.
 //
-// Tiles are 64 x 64 complex per workgroup with K steps of 16; the left operand is
-// transposed into LDS so that both MFMA operand fragments read 16 consecutive
-// elements per K row.  Four waves own 32 x 32 sub-tiles (2 x 2 MFMA blocks).
+// Tiles are 64 x 64 complex per workgroup with double-buffered K steps of 16; the next
+// step's loads are issued ahead of the MFMA block.  Four waves own 32 x 32 sub-tiles
+// (2 x 2 MFMA blocks, four real products per complex block).
 #include "common.hpp"
 
 namespace rpa {
@@ -28,9 +28,75 @@ __device__ __forceinline__ void tile_of(int t, int &tr, int &tc) {
   tc = t - r * (r + 1) / 2;
 }
 
-__global__ __launch_bounds__(256, 2) void zgemm_f64_kernel(GemmArgs g) {
-  __shared__ double2 lA[2][KT][LDP];   // [k][i]
-  __shared__ double2 lB[2][KT][LDP];   // [k][j]
+struct GStage {
+  double2 a[4], b[4];
+};
+
+// A tile [64 rows][16 k] and B tile [16 k][64 columns], both stored as read from memory:
+// with the padded pitches, the MFMA fragment reads of 16 lanes on consecutive rows (A)
+// or columns (B) hit distinct banks, so no transpose is needed.  Loads use clamped
+// (always valid) addresses and are masked at the LDS store.
+__device__ __forceinline__ void gemm_load(GStage &st, const double2 *A, const double2 *B, int N, int k0,
+                                          int ai_row, int ak, int bk, const int (&bcol)[4]) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int k = k0 + ak + c;
+    st.a[c] = A[(int64_t)ai_row * N + (k < N ? k : 0)];
+  }
+  const int kb = k0 + bk;
+  const int64_t ro = (int64_t)(kb < N ? kb : 0) * N;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) st.b[c] = B[ro + bcol[c]];
+}
+
+// component-wise select: a select of whole double2 values can become a pointer select
+// through scratch memory
+__device__ __forceinline__ double2 keep_if(bool ok, const double2 &v) {
+  return make_double2(ok ? v.x : 0.0, ok ? v.y : 0.0);
+}
+
+__device__ __forceinline__ void gemm_store(const GStage &st, double2 (*la)[KT + 1], double2 (*lb)[LDP], int N,
+                                           int k0, int arow, bool arow_ok, int ak, int bk, const bool (&bok)[4],
+                                           int bc) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) la[arow][ak + c] = keep_if(arow_ok && k0 + ak + c < N, st.a[c]);
+  const bool kv = k0 + bk < N;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) lb[bk][bc + 16 * c] = keep_if(kv && bok[c], st.b[c]);
+}
+
+__device__ __forceinline__ void gemm_contract(const double2 (*la)[KT + 1], const double2 (*lb)[LDP], int wr, int wc,
+                                              int li, int lk, d4 (&accR)[2][2], d4 (&accI)[2][2]) {
+#pragma unroll
+  for (int ks = 0; ks < KT / 4; ++ks) {
+    double2 av[2], bv[2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) av[x] = la[wr * 32 + x * 16 + li][ks * 4 + lk];
+#pragma unroll
+    for (int y = 0; y < 2; ++y) bv[y] = lb[ks * 4 + lk][wc * 32 + y * 16 + li];
+    // a * b = (ar br - ai bi) + i (ar bi + ai br)
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) accR[x][y] = mfma(av[x].x, bv[y].x, accR[x][y]);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) accI[x][y] = mfma(av[x].x, bv[y].y, accI[x][y]);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) accR[x][y] = mfma(-av[x].y, bv[y].y, accR[x][y]);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) accI[x][y] = mfma(av[x].y, bv[y].x, accI[x][y]);
+  }
+}
+
+__global__ __launch_bounds__(256) void zgemm_f64_kernel(GemmArgs g) {
+  __shared__ double2 lA[2][TN][KT + 1];   // [i][k]
+  __shared__ double2 lB[2][KT][LDP];      // [k][j]
 
   const int b = blockIdx.y;
   const int N = g.N;
@@ -50,33 +116,18 @@ __global__ __launch_bounds__(256, 2) void zgemm_f64_kernel(GemmArgs g) {
   double2 *C = g.C + (int64_t)b * g.c_stride;
 
   const int tid = threadIdx.x;
-  // A tile: 64 rows x 16 k; thread -> row tid/4, k (tid%4)*4 .. +3
-  const int arow = tid >> 2, akc = (tid & 3) * 4;
-  // B tile: 16 k x 64 cols; thread -> k tid/16, cols (tid%16)*4 .. +3
-  const int brow = tid >> 4, bcol = (tid & 15) * 4;
-
-  double2 ra[4], rb[4];
-  auto gload = [&](int k0) {
-    const int i = I0 + arow;
+  const int arow = tid >> 2, ak = (tid & 3) * 4;       // A: row, 4 consecutive k
+  const bool arow_ok = I0 + arow < N;
+  const int ai_row = arow_ok ? I0 + arow : 0;
+  const int bk = tid >> 4, bc = tid & 15;               // B: k row, columns bc + 16 c
+  int bcol[4];
+  bool bok[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int k = k0 + akc + c;
-      ra[c] = (i < N && k < N) ? A[(int64_t)i * N + k] : make_double2(0.0, 0.0);
-    }
-    const int kb = k0 + brow;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int j = J0 + bcol + c;
-      rb[c] = (kb < N && j < N) ? B[(int64_t)kb * N + j] : make_double2(0.0, 0.0);
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      lA[buf][akc + c][arow] = ra[c];
-      lB[buf][brow][bcol + c] = rb[c];
-    }
-  };
+  for (int c = 0; c < 4; ++c) {
+    const int j = J0 + bc + 16 * c;
+    bok[c] = j < N;
+    bcol[c] = bok[c] ? j : 0;
+  }
 
   const int wave = tid >> 6, lane = tid & 63;
   const int wr = wave >> 1, wc = wave & 1;
@@ -90,35 +141,23 @@ __global__ __launch_bounds__(256, 2) void zgemm_f64_kernel(GemmArgs g) {
       accI[x][y] = d4{0.0, 0.0, 0.0, 0.0};
     }
 
+  GStage st;
   const int nsteps = (N + KT - 1) / KT;
-  gload(0);
-  sstore(0);
+  gemm_load(st, A, B, N, 0, ai_row, ak, bk, bcol);
+  gemm_store(st, lA[0], lB[0], N, 0, arow, arow_ok, ak, bk, bok, bc);
   __syncthreads();
-  for (int s = 0; s < nsteps; ++s) {
+  for (int s = 0; s + 1 < nsteps; ++s) {
     const int cur = s & 1;
-    if (s + 1 < nsteps) gload((s + 1) * KT);
-#pragma unroll
-    for (int ks = 0; ks < KT / 4; ++ks) {
-      double2 av[2], bv[2];
-#pragma unroll
-      for (int x = 0; x < 2; ++x) av[x] = lA[cur][ks * 4 + lk][wr * 32 + x * 16 + li];
-#pragma unroll
-      for (int y = 0; y < 2; ++y) bv[y] = lB[cur][ks * 4 + lk][wc * 32 + y * 16 + li];
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y) {
-          // a * b = (ar br - ai bi) + i (ar bi + ai br)
-          accR[x][y] = mfma(av[x].x, bv[y].x, accR[x][y]);
-          accR[x][y] = mfma(-av[x].y, bv[y].y, accR[x][y]);
-          accI[x][y] = mfma(av[x].x, bv[y].y, accI[x][y]);
-          accI[x][y] = mfma(av[x].y, bv[y].x, accI[x][y]);
-        }
-    }
-    if (s + 1 < nsteps) sstore(cur ^ 1);
+    gemm_load(st, A, B, N, (s + 1) * KT, ai_row, ak, bk, bcol);
+    __builtin_amdgcn_sched_barrier(0);
+    gemm_contract(lA[cur], lB[cur], wr, wc, li, lk, accR, accI);
+    __builtin_amdgcn_sched_barrier(0);
+    gemm_store(st, lA[cur ^ 1], lB[cur ^ 1], N, (s + 1) * KT, arow, arow_ok, ak, bk, bok, bc);
     __syncthreads();
   }
+  gemm_contract(lA[(nsteps - 1) & 1], lB[(nsteps - 1) & 1], wr, wc, li, lk, accR, accI);
 
+  const double sg = g.negate ? -1.0 : 1.0;
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -127,7 +166,7 @@ __global__ __launch_bounds__(256, 2) void zgemm_f64_kernel(GemmArgs g) {
       for (int r = 0; r < 4; ++r) {
         const int i = I0 + wr * 32 + x * 16 + lk + 4 * r;
         const int j = J0 + wc * 32 + y * 16 + li;
-        if (i < N && j < N) C[(int64_t)i * N + j] = make_double2(accR[x][y][r], accI[x][y][r]);
+        if (i < N && j < N) C[(int64_t)i * N + j] = make_double2(sg * accR[x][y][r], sg * accI[x][y][r]);
       }
 }
 

@@ -137,7 +137,7 @@ def pis_of(s, pts):
     return [orc.pi_matrix(s.vhalf[iq], orc.chi0(s, iq, s.omega[j])) for iq, j in pts]
 
 
-@pytest.mark.parametrize("n", [1, 16, 17, 150, 384])
+@pytest.mark.parametrize("n", [1, 16, 17, 64, 65, 129, 150, 384, 700])
 def test_trln_matches_oracle(ctx, n):
     say(f"trln n={n}")
     s = inputs.make_system("t", (1, 1, 1), 4, 30, n, 6, 100 + n, is_complex=True, sigma=0.2,
@@ -157,16 +157,26 @@ def test_trln_real_input(ctx):
     assert np.max(np.abs(ctx.trln(pis) - ref)) <= 1e-10 * np.max(np.abs(ref))
 
 
-def test_trln_not_positive_definite_is_an_error(ctx):
+@pytest.mark.parametrize("n,col", [(40, 17), (200, 130)])
+def test_trln_not_positive_definite_is_an_error(ctx, n, col):
     from paper_2505_06021_amd import rpa
-    say("trln not SPD")
-    n = 40
-    pi = np.zeros((n, n), dtype=np.complex128)
-    pi[17, 17] = 2.0          # 1 - Pi has a negative pivot at column 17
+    say(f"trln not SPD n={n} col={col}")
+    pi = np.zeros((3, n, n), dtype=np.complex128)
+    pi[1, col, col] = 2.0     # 1 - Pi_1 has a negative pivot at column `col`
     with pytest.raises(rpa.RpaError) as e:
-        ctx.trln(pi[None])
+        ctx.trln(pi)
     assert e.value.code == rpa.RPA_E_NOTSPD
-    assert "column 17" in str(e.value)
+    assert f"matrix 1 (column {col})" in str(e.value)
+
+
+def test_trln_batch_mixed_sizes_of_values(ctx):
+    """Matrices of very different norms in one batch do not interact."""
+    say("trln batch independence")
+    s = inputs.make_system("t", (1, 1, 1), 4, 30, 200, 6, 77, is_complex=True, sigma=0.2, periodic=False)
+    pis = np.stack(pis_of(s, [(0, j) for j in range(s.nw)]))
+    one = np.array([ctx.trln(p)[0] for p in pis])
+    allb = ctx.trln(pis)
+    assert np.array_equal(one, allb)
 
 
 # ---------------------------------------------------------------- energy (a1-a6)
