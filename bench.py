@@ -172,6 +172,8 @@ def main():
                     help="replay the serving job stream instead of the single-system step")
     ap.add_argument("--jobs", type=int, default=256)
     ap.add_argument("--rate", type=float, default=4.0)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a plain 1 GiB device copy first (scale reference for HBM counters)")
     ap.add_argument("--hbm-limit-gb", type=float, default=200.0,
                     help="device-memory admission limit of the serving context")
     args = ap.parse_args()
@@ -187,6 +189,14 @@ def main():
 
     import torch
     from paper_2505_06021_amd import inputs, rpa
+
+    if args.calib_copy:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] calibration copy: 1 GiB read, 1 GiB written", file=sys.stderr, flush=True)
+        del src, dst
 
     make = getattr(inputs, WORKLOADS[args.workload])
     s = make()

@@ -16,7 +16,6 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-typedef short s8 __attribute__((ext_vector_type(8)));
 
 constexpr int TN = 64;
 constexpr int FLUSH_ROWS = 256;
@@ -280,14 +279,6 @@ __device__ __forceinline__ f4 mfma_bf16(const bf8 &a, const bf8 &b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ unsigned short bf16_bits(float x) {
-  __bf16 h = (__bf16)x;   // round to nearest even
-  return __builtin_bit_cast(unsigned short, h);
-}
-__device__ __forceinline__ float bf16_val(unsigned short b) {
-  return __builtin_bit_cast(float, (unsigned)b << 16);
-}
-
 __global__ __launch_bounds__(256) void chi0_bf16x3_kernel(Chi0Args a, const float2 *B32, const double *diag) {
   // [buf][operand][plane][column][row]
   __shared__ __attribute__((aligned(16))) unsigned short lds[2][2][4][TN][KBP];
@@ -302,18 +293,23 @@ __global__ __launch_bounds__(256) void chi0_bf16x3_kernel(Chi0Args a, const floa
   const int P0 = tr * TN, Q0 = tc * TN;
   const bool is_diag = (tr == tc);
   const int tid = threadIdx.x;
-  // staging: thread -> column cl (64 consecutive columns per wave-row), rows 8 kg .. 8 kg + 7
-  const int cl = tid & 63, kg = tid >> 6;
-  const float2 *bb = B32 + (int64_t)pd.bslot * a.b_slot_stride;
+  // staging: threads 0..127 stage the left panel (columns P0..), 128..255 the right panel
+  // (Q0.., scaled by w); a thread owns columns 2 cp, 2 cp + 1 of its panel and rows
+  // 8 kg .. 8 kg + 7, loaded as one 16-byte complex pair per row
+  const bool right = tid >= 128;
+  const int st_t = tid & 127;
+  const int cp = st_t & 31, kg = st_t >> 5;
   const double *wrow = a.wtab + (int64_t)blockIdx.y * a.M;
-  const bool pok = P0 + cl < N, qok = Q0 + cl < N;
-  const int pcol = pok ? P0 + cl : 0, qcol = qok ? Q0 + cl : 0;
-
+  const int c0 = (right ? Q0 : P0) + 2 * cp;
+  // columns past N read a clamped valid column; they are never stored in the output
+  const int col_a = c0 < N ? c0 : 0, col_b = c0 + 1 < N ? c0 + 1 : 0;
   const int wave = tid >> 6, lane = tid & 63;
   const int wr = wave >> 1, wc = wave & 1;
   const int li = lane & 15, lk = lane >> 4;
 
-  f4 accR[2][2], accI[2][2];
+  // Re += ar br + ai bi and Im += ar bi - ai br, with ai br kept in accJ and subtracted at
+  // the FP64 flush (no sign flips of packed operands in the loop)
+  f4 accR[2][2], accI[2][2], accJ[2][2];
   double hR[2][2][4], hI[2][2][4];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -321,46 +317,62 @@ __global__ __launch_bounds__(256) void chi0_bf16x3_kernel(Chi0Args a, const floa
     for (int y = 0; y < 2; ++y) {
       accR[x][y] = f4{0.f, 0.f, 0.f, 0.f};
       accI[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+      accJ[x][y] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int r = 0; r < 4; ++r) hR[x][y][r] = hI[x][y][r] = 0.0;
     }
 
-  float2 sa[8], sb[8];
-  float sw[8];
+  // Raw loads only (rows 8 kg .. 8 kg + 7, clamped to valid rows); masking, scaling and
+  // the split happen at the store after the MFMA block.
+  float2 sva[8], svb[8];
+  double sw[8];
+  const float2 *slab = B32 + (int64_t)pd.bslot * a.b_slot_stride;
   auto load = [&](int m0) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int m = m0 + 8 * kg + e;
-      const bool mv = m < M;
-      const int mc = mv ? m : 0;
-      sw[e] = mv ? (float)wrow[mc] : 0.f;
-      const int64_t ro = (int64_t)mc * N;
-      sa[e] = bb[ro + pcol];
-      sb[e] = bb[ro + qcol];
-      if (!mv) sa[e] = make_float2(0.f, 0.f);
+      const int mc = m < M ? m : 0;
+      sw[e] = wrow[mc];                 // used by the right panel only
+      const float2 *row = slab + (int64_t)mc * N;
+      sva[e] = row[col_a];
+      svb[e] = row[col_b];
     }
   };
-  auto store = [&](int buf) {
-    s8 ah[2], al[2], bh[2], bl[2];   // [re/im]
+  // x = hi + lo for two consecutive rows at once: hi = bf16(x) (v_cvt_pk_bf16_f32, round
+  // to nearest even), lo = bf16(x - hi); the packed dwords are already in the MFMA
+  // fragment order (consecutive contraction rows).
+  auto split2 = [](float x0, float x1, unsigned &hi, unsigned &lo) {
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+    f2v x = {x0, x1};
+    hi = __builtin_bit_cast(unsigned, __builtin_convertvector(x, b2v));
+    f2v h = {__builtin_bit_cast(float, hi << 16), __builtin_bit_cast(float, hi & 0xffff0000u)};
+    lo = __builtin_bit_cast(unsigned, __builtin_convertvector(x - h, b2v));
+  };
+  auto store = [&](int buf, int m0) {
+    // Only the scaled (right) operand is masked (w = 0 on rows past the end): a product
+    // with a zero factor vanishes whatever the clamped left operand holds, and columns
+    // past N are never stored.
+    unsigned h[2][2][4], l[2][2][4];   // [column of the pair][re/im][row pair]
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const float2 x = pok ? sa[e] : make_float2(0.f, 0.f);
-      const float2 y0 = qok ? sb[e] : make_float2(0.f, 0.f);
-      const float2 y = make_float2(sw[e] * y0.x, sw[e] * y0.y);
-      unsigned short h;
-      h = bf16_bits(x.x); ah[0][e] = (short)h; al[0][e] = (short)bf16_bits(x.x - bf16_val(h));
-      h = bf16_bits(x.y); ah[1][e] = (short)h; al[1][e] = (short)bf16_bits(x.y - bf16_val(h));
-      h = bf16_bits(y.x); bh[0][e] = (short)h; bl[0][e] = (short)bf16_bits(y.x - bf16_val(h));
-      h = bf16_bits(y.y); bh[1][e] = (short)h; bl[1][e] = (short)bf16_bits(y.y - bf16_val(h));
+    for (int pr = 0; pr < 4; ++pr) {
+      const int e0 = 2 * pr, e1 = 2 * pr + 1;
+      const float w0 = !right ? 1.f : ((m0 + 8 * kg + e0 < M) ? (float)sw[e0] : 0.f);
+      const float w1 = !right ? 1.f : ((m0 + 8 * kg + e1 < M) ? (float)sw[e1] : 0.f);
+      split2(w0 * sva[e0].x, w1 * sva[e1].x, h[0][0][pr], l[0][0][pr]);
+      split2(w0 * sva[e0].y, w1 * sva[e1].y, h[0][1][pr], l[0][1][pr]);
+      split2(w0 * svb[e0].x, w1 * svb[e1].x, h[1][0][pr], l[1][0][pr]);
+      split2(w0 * svb[e0].y, w1 * svb[e1].y, h[1][1][pr], l[1][1][pr]);
     }
-    *reinterpret_cast<s8 *>(&lds[buf][0][0][cl][8 * kg]) = ah[0];
-    *reinterpret_cast<s8 *>(&lds[buf][0][1][cl][8 * kg]) = al[0];
-    *reinterpret_cast<s8 *>(&lds[buf][0][2][cl][8 * kg]) = ah[1];
-    *reinterpret_cast<s8 *>(&lds[buf][0][3][cl][8 * kg]) = al[1];
-    *reinterpret_cast<s8 *>(&lds[buf][1][0][cl][8 * kg]) = bh[0];
-    *reinterpret_cast<s8 *>(&lds[buf][1][1][cl][8 * kg]) = bl[0];
-    *reinterpret_cast<s8 *>(&lds[buf][1][2][cl][8 * kg]) = bh[1];
-    *reinterpret_cast<s8 *>(&lds[buf][1][3][cl][8 * kg]) = bl[1];
+    const int op = right ? 1 : 0;
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+      const int col = 2 * cp + cc;
+      *reinterpret_cast<uint4 *>(&lds[buf][op][0][col][8 * kg]) = make_uint4(h[cc][0][0], h[cc][0][1], h[cc][0][2], h[cc][0][3]);
+      *reinterpret_cast<uint4 *>(&lds[buf][op][1][col][8 * kg]) = make_uint4(l[cc][0][0], l[cc][0][1], l[cc][0][2], l[cc][0][3]);
+      *reinterpret_cast<uint4 *>(&lds[buf][op][2][col][8 * kg]) = make_uint4(h[cc][1][0], h[cc][1][1], h[cc][1][2], h[cc][1][3]);
+      *reinterpret_cast<uint4 *>(&lds[buf][op][3][col][8 * kg]) = make_uint4(l[cc][1][0], l[cc][1][1], l[cc][1][2], l[cc][1][3]);
+    }
   };
   auto contract = [&](int buf) {
     // fragments: lane l holds 8 consecutive rows 8 (l/16) .. +7 of column l%16 of a block
@@ -375,16 +387,6 @@ __global__ __launch_bounds__(256) void chi0_bf16x3_kernel(Chi0Args a, const floa
 #pragma unroll
       for (int pl = 0; pl < 4; ++pl)
         Bv[y][pl] = *reinterpret_cast<const bf8 *>(&lds[buf][1][pl][wc * 32 + y * 16 + li][8 * lk]);
-    // -Ai for the imaginary part: flip the sign bits of the packed bf16 values
-    bf8 nAi[2][2];
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        s8 v = __builtin_bit_cast(s8, A[x][2 + h]);
-        v ^= (short)0x8000;
-        nAi[x][h] = __builtin_bit_cast(bf8, v);
-      }
     // conj(a) * b: Re += ar br + ai bi, Im += ar bi - ai br; each real product as
     // hi*hi + hi*lo + lo*hi
 #pragma unroll
@@ -393,6 +395,7 @@ __global__ __launch_bounds__(256) void chi0_bf16x3_kernel(Chi0Args a, const floa
       for (int y = 0; y < 2; ++y) {
         accR[x][y] = mfma_bf16(A[x][0], Bv[y][0], accR[x][y]);
         accI[x][y] = mfma_bf16(A[x][0], Bv[y][2], accI[x][y]);
+        accJ[x][y] = mfma_bf16(A[x][2], Bv[y][0], accJ[x][y]);
       }
 #pragma unroll
     for (int x = 0; x < 2; ++x)
@@ -400,6 +403,7 @@ __global__ __launch_bounds__(256) void chi0_bf16x3_kernel(Chi0Args a, const floa
       for (int y = 0; y < 2; ++y) {
         accR[x][y] = mfma_bf16(A[x][0], Bv[y][1], accR[x][y]);
         accI[x][y] = mfma_bf16(A[x][0], Bv[y][3], accI[x][y]);
+        accJ[x][y] = mfma_bf16(A[x][2], Bv[y][1], accJ[x][y]);
       }
 #pragma unroll
     for (int x = 0; x < 2; ++x)
@@ -407,27 +411,15 @@ __global__ __launch_bounds__(256) void chi0_bf16x3_kernel(Chi0Args a, const floa
       for (int y = 0; y < 2; ++y) {
         accR[x][y] = mfma_bf16(A[x][1], Bv[y][0], accR[x][y]);
         accI[x][y] = mfma_bf16(A[x][1], Bv[y][2], accI[x][y]);
+        accJ[x][y] = mfma_bf16(A[x][3], Bv[y][0], accJ[x][y]);
       }
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
       for (int y = 0; y < 2; ++y) {
         accR[x][y] = mfma_bf16(A[x][2], Bv[y][2], accR[x][y]);
-        accI[x][y] = mfma_bf16(nAi[x][0], Bv[y][0], accI[x][y]);
-      }
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y) {
         accR[x][y] = mfma_bf16(A[x][2], Bv[y][3], accR[x][y]);
-        accI[x][y] = mfma_bf16(nAi[x][0], Bv[y][1], accI[x][y]);
-      }
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y) {
         accR[x][y] = mfma_bf16(A[x][3], Bv[y][2], accR[x][y]);
-        accI[x][y] = mfma_bf16(nAi[x][1], Bv[y][0], accI[x][y]);
       }
   };
   auto flush = [&]() {
@@ -438,17 +430,18 @@ __global__ __launch_bounds__(256) void chi0_bf16x3_kernel(Chi0Args a, const floa
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           hR[x][y][r] += (double)accR[x][y][r];
-          hI[x][y][r] += (double)accI[x][y][r];
+          hI[x][y][r] += (double)accI[x][y][r] - (double)accJ[x][y][r];
         }
         accR[x][y] = f4{0.f, 0.f, 0.f, 0.f};
         accI[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+        accJ[x][y] = f4{0.f, 0.f, 0.f, 0.f};
       }
   };
 
   constexpr int FLUSH_STEPS = FLUSH_ROWS / KB;
   const int nsteps = M > mlo ? (M - mlo + KB - 1) / KB : 1;
   load(mlo);
-  store(0);
+  store(0, mlo);
   __syncthreads();
   for (int s = 0; s + 1 < nsteps; ++s) {
     const int cur = s & 1;
@@ -457,7 +450,7 @@ __global__ __launch_bounds__(256) void chi0_bf16x3_kernel(Chi0Args a, const floa
     contract(cur);
     __builtin_amdgcn_sched_barrier(0);
     if ((s + 1) % FLUSH_STEPS == 0) flush();
-    store(cur ^ 1);
+    store(cur ^ 1, mlo + (s + 1) * KB);
     __syncthreads();
   }
   contract((nsteps - 1) & 1);
