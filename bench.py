@@ -191,11 +191,12 @@ def main():
     from paper_2505_06021_amd import inputs, rpa
 
     if args.calib_copy:
-        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)   # writes 1 GiB
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.add(src, 1.0, out=dst)          # an elementwise kernel: reads 1 GiB, writes 1 GiB
         torch.cuda.synchronize()
-        print("[bench] calibration copy: 1 GiB read, 1 GiB written", file=sys.stderr, flush=True)
+        print("[bench] calibration: fill writes 1 GiB; add reads 1 GiB and writes 1 GiB",
+              file=sys.stderr, flush=True)
         del src, dst
 
     make = getattr(inputs, WORKLOADS[args.workload])
