@@ -53,18 +53,24 @@ constexpr int DIAG_MAXP = 16;      // points per pass
 __global__ __launch_bounds__(256) void diag_partial_kernel(const void *B, int cplx, int64_t M, int N,
                                                            const double *wtab, int npts,
                                                            double *partial) {
+  __shared__ double wl[DIAG_MAXP][DIAG_ROWS];   // the chunk's weights, read once
   __shared__ double red[4][DIAG_MAXP][64];
   const int col = threadIdx.x & 63, grp = threadIdx.x >> 6;
   const int P = blockIdx.x * 64 + col;
   const int c = blockIdx.y;
   const int64_t m0 = (int64_t)c * DIAG_ROWS;
+  const int rows = (int)(M - m0 < DIAG_ROWS ? M - m0 : DIAG_ROWS);
+  for (int e = threadIdx.x; e < DIAG_MAXP * DIAG_ROWS; e += 256) {
+    const int p = e / DIAG_ROWS, r = e % DIAG_ROWS;
+    wl[p][r] = (p < npts && r < rows) ? wtab[(int64_t)p * M + m0 + r] : 0.0;
+  }
+  __syncthreads();
   const int Pc = P < N ? P : 0;
   double acc[DIAG_MAXP];
 #pragma unroll
   for (int p = 0; p < DIAG_MAXP; ++p) acc[p] = 0.0;
-  for (int r = grp; r < DIAG_ROWS; r += 4) {
+  for (int r = grp; r < rows; r += 4) {
     const int64_t m = m0 + r;
-    if (m >= M) break;
     double b2;
     if (cplx) {
       const double2 v = reinterpret_cast<const double2 *>(B)[m * N + Pc];
@@ -74,8 +80,7 @@ __global__ __launch_bounds__(256) void diag_partial_kernel(const void *B, int cp
       b2 = v * v;
     }
 #pragma unroll
-    for (int p = 0; p < DIAG_MAXP; ++p)
-      if (p < npts) acc[p] += wtab[(int64_t)p * M + m] * b2;
+    for (int p = 0; p < DIAG_MAXP; ++p) acc[p] += wl[p][r] * b2;
   }
 #pragma unroll
   for (int p = 0; p < DIAG_MAXP; ++p) red[grp][p][col] = acc[p];

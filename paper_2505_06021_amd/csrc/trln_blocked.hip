@@ -101,61 +101,99 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(double2 *W, int64_t stri
                                                         int32_t *info, double2 *linv) {
   __shared__ double2 D[NB][LP];
   __shared__ double2 X[NB][LP];
+  __shared__ double2 colbuf[2][NB];
   __shared__ double ld[NB];
   const int b = blockIdx.x;
   if (info[b] >= 0) return;
   double2 *A = W + (int64_t)b * stride;
   const int jb = min(NB, n - j0);
   const int tid = threadIdx.x;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int r = e / NB, c = e % NB;
-    D[r][c] = (r < jb && c <= r) ? A[(int64_t)(j0 + r) * n + j0 + c] : make_double2(0.0, 0.0);
-    X[r][c] = make_double2(0.0, 0.0);
+  // Thread tid owns column s = tid % 64 and rows r = tid / 64 + 4 j (j < 16) of the block,
+  // kept in registers; only the current pivot column passes through LDS.
+  const int s = tid & 63, r0 = tid >> 6;
+  double2 v[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int r = r0 + 4 * j;
+    v[j] = (r < jb && s <= r) ? A[(int64_t)(j0 + r) * n + j0 + s] : make_double2(0.0, 0.0);
   }
-  __syncthreads();
+  for (int e = tid; e < NB * NB; e += 256) X[e / NB][e % NB] = make_double2(0.0, 0.0);
+  // the block's log1p terms are summed in a register of thread 0 and stored once: a global
+  // read-modify-write per column would make every barrier wait for memory
+  double lsum = 0.0;
   for (int c = 0; c < jb; ++c) {
-    const double d = D[c][c].x;
+    double2 *cb = colbuf[c & 1];
+    if (s == c) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) cb[r0 + 4 * j] = v[j];   // column c is final
+    }
+    __syncthreads();
+    const double d = cb[c].x;
     const double piv = 1.0 + d;
     if (!(piv > 0.0) || !(piv < INFINITY)) {
       if (tid == 0) info[b] = j0 + c;
       return;   // uniform: every thread read the same pivot
     }
-    const double l = sqrt(piv);
     if (tid == 0) {
-      ld[c] = l;
-      logacc[b] += log1p(d);
+      ld[c] = sqrt(piv);
+      lsum += log1p(d);
     }
-    if (tid > c && tid < jb) {
-      const double2 v = D[tid][c];
-      D[tid][c] = make_double2(v.x / l, v.y / l);
-    }
-    __syncthreads();
-    for (int e = tid; e < NB * NB; e += 256) {
-      const int r = e / NB, s = e % NB;
-      if (s > c && s <= r && r < jb) {
-        const double2 x = D[r][c], y = D[s][c];
-        D[r][s].x -= x.x * y.x + x.y * y.y;   // x conj(y)
-        D[r][s].y -= x.y * y.x - x.x * y.y;
+    if (s > c && s < jb) {
+      // W[r][s] -= W[r][c] conj(W[s][c]) / piv for r >= s
+      const double2 ys = cb[s];
+      const double ip = 1.0 / piv;
+      const double yr = ys.x * ip, yi = ys.y * ip;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int r = r0 + 4 * j;
+        if (r >= s && r < jb) {
+          const double2 x = cb[r];
+          v[j].x -= x.x * yr + x.y * yi;
+          v[j].y -= x.y * yr - x.x * yi;
+        }
       }
     }
-    __syncthreads();
   }
-  // X = L11^{-1}: thread t < jb solves L x = e_t for column t (forward substitution)
-  if (tid < jb) {
-    const int t = tid;
-    X[t][t] = make_double2(1.0 / ld[t], 0.0);
-    for (int i = t + 1; i < jb; ++i) {
-      double sr = 0.0, si = 0.0;
-      for (int k = t; k < i; ++k) {
-        const double2 lv = D[i][k], xv = X[k][t];
-        sr += lv.x * xv.x - lv.y * xv.y;
-        si += lv.x * xv.y + lv.y * xv.x;
-      }
-      const double il = 1.0 / ld[i];
-      X[i][t] = make_double2(-sr * il, -si * il);
+  if (tid == 0) logacc[b] += lsum;
+  __syncthreads();
+  // the factor L11 into D: L[r][s] = W[r][s] / l_s below the diagonal, l_s on it
+  {
+    const double ls = s < jb ? ld[s] : 1.0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int r = r0 + 4 * j;
+      D[r][s] = (r < jb && s < r) ? make_double2(v[j].x / ls, v[j].y / ls)
+                                  : (r == s && r < jb ? make_double2(ls, 0.0) : make_double2(0.0, 0.0));
     }
   }
   __syncthreads();
+  // X = L11^{-1}, row by row: X[i][j] = -(sum_{k<i} L[i][k] X[k][j]) / l_i for j < i,
+  // X[i][i] = 1 / l_i.  X is zero above its diagonal, so every lane can run over all
+  // k < i: L[i][k] is a broadcast read, X[k][j] a conflict-free row read.  The 256
+  // threads split k into four interleaved partitions summed in a fixed order.
+  {
+    __shared__ double2 part[4][NB];
+    const int j = tid & 63, g = tid >> 6;
+    if (tid < jb) X[tid][tid] = make_double2(1.0 / ld[tid], 0.0);
+    __syncthreads();
+    for (int i = 1; i < jb; ++i) {
+      double sr = 0.0, si = 0.0;
+      for (int k = g; k < i; k += 4) {
+        const double2 lv = D[i][k], xv = X[k][j];
+        sr += lv.x * xv.x - lv.y * xv.y;
+        si += lv.x * xv.y + lv.y * xv.x;
+      }
+      part[g][j] = make_double2(sr, si);
+      __syncthreads();
+      if (g == 0 && j < i) {
+        const double il = 1.0 / ld[i];
+        const double r = (part[0][j].x + part[1][j].x) + (part[2][j].x + part[3][j].x);
+        const double m = (part[0][j].y + part[1][j].y) + (part[2][j].y + part[3][j].y);
+        X[i][j] = make_double2(-r * il, -m * il);
+      }
+      __syncthreads();
+    }
+  }
   double2 *out = linv + (int64_t)b * NB * NB;
   for (int e = tid; e < NB * NB; e += 256) out[e] = X[e / NB][e % NB];
 }
