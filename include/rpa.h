@@ -211,6 +211,16 @@ typedef struct {
 int rpa_profile(rpa_ctx *ctx, int32_t enable);
 int rpa_profile_read(rpa_ctx *ctx, rpa_kernel_times *out);
 
+/* K-step depth choices of the FP64 chi0 contraction made so far in this process.
+ * The depth (rows of B staged per LDS step: 8, 16 or 32) changes the speed of the
+ * contraction, never its result's definition (eq. for chi0 in the periodic RPA section);
+ * each shape bucket is timed once on its first launch.  Writes "bucket depth" lines,
+ * NUL-terminated and truncated to len bytes, into buf (caller-owned; may be NULL when
+ * len is 0) and the untruncated length into *needed (may be NULL).  Environment:
+ * RPA_CHI0_KT=8|16|32 fixes the depth, RPA_TUNE=0 keeps 16, RPA_TUNE_CACHE=<file> keeps
+ * the choices across processes.  Never fails. */
+int rpa_tuned(char *buf, int32_t len, int32_t *needed);
+
 #ifdef __cplusplus
 }
 #endif

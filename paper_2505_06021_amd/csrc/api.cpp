@@ -194,7 +194,26 @@ int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega, rpa_
   a.out_stride = 0;
   a.nk = hs.nk; a.nocc = hs.nocc; a.nvirt = hs.nvirt; a.N = N; a.M = M;
   RPA_HIP(launch_chi0_weights(c.stream, a, 1));
-  if (prec != RPA_FP64) {
+  if (prec == RPA_BF16X3) {
+    // prepared left (unscaled) and right (scaled) operands, then the split contraction
+    double *dg, *scr;
+    unsigned short *lr;
+    float2 *part;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c.device) != hipSuccess) ncu = 256;
+    Bf16Plan pl;
+    bf16_plan(M, N, 1, ncu, 0, &pl);
+    const int64_t pe = bf16_prepared_elems(M, N);
+    RPA_TRY(c.workspace("chi0_bf16_ops", 2 * pe * 2, (void **)&lr));
+    RPA_TRY(c.workspace("chi0_bf16_part", bf16_partial_elems(pl, 1) * 8, (void **)&part));
+    RPA_TRY(c.workspace("chi0_diag", (int64_t)N * 8, (void **)&dg));
+    RPA_TRY(c.workspace("chi0_diag_scratch", diag_exact_scratch_doubles(M, N, 1) * 8, (void **)&scr));
+    RPA_HIP(launch_diag_exact(c.stream, B, cplx, M, N, wt, 1, scr, dg));
+    RPA_HIP(launch_bf16_prepare(c.stream, B, cplx, M, N, nullptr, 1, lr));
+    RPA_HIP(launch_bf16_prepare(c.stream, B, cplx, M, N, wt, 1, lr + pe));
+    RPA_HIP(launch_bf16_herk(c.stream, pl, lr, 0, lr + pe, a.pts, 1, cplx, part, N, M));
+    RPA_HIP(launch_bf16_reduce(c.stream, pl, part, 1, N, dg, out, 0));
+  } else if (prec != RPA_FP64) {
     float2 *b32;
     double *dg, *scr;
     RPA_TRY(c.workspace("chi0_B32", M * N * 8, (void **)&b32));
@@ -204,7 +223,9 @@ int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega, rpa_
     RPA_HIP(launch_diag_exact(c.stream, B, cplx, M, N, wt, 1, scr, dg));
     RPA_HIP(launch_chi0_mixed(c.stream, a, 1, b32, dg, (int)prec));
   } else {
-    RPA_HIP(launch_chi0_f64(c.stream, a, 1, cplx, chi0_kt()));
+    int kt = 16;
+    RPA_TRY(tune_chi0_kt(c.stream, a, 1, cplx, &kt));
+    RPA_HIP(launch_chi0_f64(c.stream, a, 1, cplx, kt));
   }
   if (!direct) RPA_TRY(deliver_complex(c, chi0, out, (int64_t)N * N, hs.is_complex, sys->memspace));
   RPA_HIP(hipStreamSynchronize(c.stream));
@@ -414,6 +435,12 @@ int rpa_profile_read(rpa_ctx *ctx, rpa_kernel_times *out) {
     out->launches[k] = c.prof_launches[k];
     out->ms[k] = c.prof_ms[k];
   }
+  return RPA_OK;
+}
+
+int rpa_tuned(char *buf, int32_t len, int32_t *needed) {
+  const int n = tuned_entries(buf, len);
+  if (needed) *needed = n;
   return RPA_OK;
 }
 

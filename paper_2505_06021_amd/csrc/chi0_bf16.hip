@@ -1,0 +1,409 @@
+// Split-BF16 chi0 from prepared operands (the reduced-precision path of the chi0 build,
+// periodic RPA section: chi0_PQ(q, i w) = sum_k zeta_k sum_ia conj(B_iaP) w_ia B_iaQ).
+//
+// The operands are written once into HBM in the form the BF16 MFMA consumes:
+//   L   = B            per q (shared by every frequency of that q)
+//   R_p = w_p zeta B   per point p of a launch
+// every element x of both split in FP64 as hi = bf16(x), lo = bf16(x - hi), for its real
+// and imaginary parts: four planes (re hi, re lo, im hi, im lo).  The contraction then
+// does nothing but copy panels into LDS and issue MFMAs:
+//   Re chi0 += Lr Rr + Li Ri,   Im chi0 += Lr Ri - Li Rr,
+// each real product as hi*hi + hi*lo + lo*hi with FP32 accumulation (the lo*lo term is
+// below the FP32 rounding of the sum).  The contraction rows are cut into splits of at
+// most BF16_SPLIT_ROWS rows; each split's FP32 tile goes to a partial buffer, so no FP32
+// sum runs over more rows than that, and a reduction adds the splits in FP64 in a fixed
+// order, mirrors the lower triangle into the Hermitian matrix and puts in the diagonal
+// from the exact FP64 pass (a sum of same-signed terms whose rounding errors would not
+// cancel).
+//
+// Prepared layout of one operand (bf16 elements, Mp = M rounded up to 32 rows, Np = N
+// rounded up to the 128-wide output tile; rows >= M and columns >= N are zero):
+//   element (m, n, plane) at ((m / 32 * 4 + plane) * Np + n) * 32 + pos(m % 32, n)
+//   pos(r, n) = ((r / 8) ^ ((n / 4) % 4)) * 8 + r % 8
+// so the 32 rows of one column are 64 contiguous bytes, a 128-column panel of one plane
+// is 8 KB contiguous (copied into LDS as is), and the XOR on the 16-byte segments makes
+// the MFMA fragment reads from LDS free of bank conflicts.
+#include "common.hpp"
+
+namespace rpa {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int HT = 128;          // output tile edge (one workgroup)
+constexpr int HK = 32;           // contraction rows per step (the K of one BF16 MFMA)
+constexpr int PREP_COLS = 64;    // columns per preparation workgroup
+constexpr int PREP_MAXP = 16;    // points per preparation launch
+
+__device__ __forceinline__ void tile_of(int t, int &tr, int &tc) {
+  int r = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((r + 1) * (r + 2) / 2 <= t) ++r;
+  while (r * (r + 1) / 2 > t) --r;
+  tr = r;
+  tc = t - r * (r + 1) / 2;
+}
+
+__device__ __forceinline__ int seg_pos(int s, int n) { return s ^ ((n >> 2) & 3); }
+
+// hi = bf16(x) (round to nearest even through FP32), lo = bf16(x - hi) with the
+// difference taken in FP64; two values at once, packed as the MFMA reads them.
+__device__ __forceinline__ void split_pair(double x0, double x1, unsigned &hi, unsigned &lo) {
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+  const f2v xf = {(float)x0, (float)x1};
+  hi = __builtin_bit_cast(unsigned, __builtin_convertvector(xf, b2v));
+  const double h0 = (double)__builtin_bit_cast(float, hi << 16);
+  const double h1 = (double)__builtin_bit_cast(float, hi & 0xffff0000u);
+  const f2v r = {(float)(x0 - h0), (float)(x1 - h1)};
+  lo = __builtin_bit_cast(unsigned, __builtin_convertvector(r, b2v));
+}
+
+// ------------------------------------------------------------------ preparation
+// One workgroup: 32 rows (one step) x 64 columns.  B rows are read coalesced into LDS,
+// then thread (c, s) splits rows 8 s .. 8 s + 7 of column c for every point (or once,
+// unscaled, when wtab is null) and writes one 16-byte segment per plane.
+template <bool CPLX>
+__global__ __launch_bounds__(256) void bf16_prepare_kernel(const void *B, int64_t M, int N, int Np,
+                                                           const double *wtab, int64_t w_stride, int np,
+                                                           unsigned short *out, int64_t out_stride) {
+  __shared__ double2 tb[HK][PREP_COLS + 1];
+  __shared__ double wl[PREP_MAXP][HK];
+  const int64_t kc = blockIdx.x;
+  const int c0 = blockIdx.y * PREP_COLS;
+  const int64_t m0 = kc * HK;
+  const int tid = threadIdx.x;
+  {
+    const int col = tid & 63, r0 = tid >> 6;
+    const int n = c0 + col;
+#pragma unroll
+    for (int j = 0; j < HK / 4; ++j) {
+      const int r = r0 + 4 * j;
+      const int64_t m = m0 + r;
+      double2 v = make_double2(0.0, 0.0);
+      if (m < M && n < N) {
+        if (CPLX) v = reinterpret_cast<const double2 *>(B)[m * N + n];
+        else v.x = reinterpret_cast<const double *>(B)[m * N + n];
+      }
+      tb[r][col] = v;
+    }
+    if (wtab) {
+      for (int e = tid; e < np * HK; e += 256) {
+        const int p = e / HK, r = e % HK;
+        wl[p][r] = (m0 + r < M) ? wtab[(int64_t)p * w_stride + m0 + r] : 0.0;
+      }
+    }
+  }
+  __syncthreads();
+  const int c = tid >> 2, s = tid & 3;
+  const int n = c0 + c;
+  double2 v[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) v[e] = tb[8 * s + e][c];
+  const int64_t unit = seg_pos(s, n);   // 16-byte segment within the column's 64 bytes
+  const int reps = wtab ? np : 1;
+  for (int p = 0; p < reps; ++p) {
+    unsigned hr[4], lr[4], hi_[4], li_[4];
+#pragma unroll
+    for (int e2 = 0; e2 < 4; ++e2) {
+      const double w0 = wtab ? wl[p][8 * s + 2 * e2] : 1.0;
+      const double w1 = wtab ? wl[p][8 * s + 2 * e2 + 1] : 1.0;
+      split_pair(w0 * v[2 * e2].x, w1 * v[2 * e2 + 1].x, hr[e2], lr[e2]);
+      if (CPLX) split_pair(w0 * v[2 * e2].y, w1 * v[2 * e2 + 1].y, hi_[e2], li_[e2]);
+    }
+    uint4 *o = reinterpret_cast<uint4 *>(out + (int64_t)p * out_stride);
+    // 16-byte units: plane base ((kc * 4 + plane) * Np + n) * 4, then the segment
+    o[((kc * 4 + 0) * Np + n) * 4 + unit] = make_uint4(hr[0], hr[1], hr[2], hr[3]);
+    o[((kc * 4 + 1) * Np + n) * 4 + unit] = make_uint4(lr[0], lr[1], lr[2], lr[3]);
+    if (CPLX) {
+      o[((kc * 4 + 2) * Np + n) * 4 + unit] = make_uint4(hi_[0], hi_[1], hi_[2], hi_[3]);
+      o[((kc * 4 + 3) * Np + n) * 4 + unit] = make_uint4(li_[0], li_[1], li_[2], li_[3]);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ contraction
+struct HerkArgs {
+  const unsigned short *L;   // prepared left operands, one per B slot
+  int64_t l_stride;          // elements between slots
+  const unsigned short *R;   // prepared right operands, one per point of the launch
+  int64_t r_stride;
+  const PointDesc *pts;
+  float2 *part;              // [npts][nsplit][ntiles][HT * HT]
+  int32_t Np, ntiles, nsplit, kc_per_split;
+  int64_t nkc;               // steps in the whole contraction (Mp / 32)
+};
+
+__device__ __forceinline__ f4 mfma_bf16(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bf8 negate(bf8 x) {
+  typedef unsigned u4v __attribute__((ext_vector_type(4)));
+  u4v u = __builtin_bit_cast(u4v, x);
+  u ^= 0x80008000u;
+  return __builtin_bit_cast(bf8, u);
+}
+
+// one 8 KB panel (128 columns x 32 rows of one plane) from HBM straight into LDS: two
+// 16-byte loads per thread; wave w fills units w * 64 .. w * 64 + 63 of each half
+__device__ __forceinline__ void copy_panel(const uint4 *src, uint4 *dst, int wave, int lane) {
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int u = j * 256 + wave * 64;
+    __builtin_amdgcn_global_load_lds((const void *)(src + u + lane),
+                                     (__attribute__((address_space(3))) void *)(dst + u), 16, 0, 0);
+  }
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void herk_bf16x3_kernel(HerkArgs h) {
+  constexpr int NPL = CPLX ? 4 : 2;
+  // [buffer][operand][plane][column * 4 + segment], 16-byte units
+  __shared__ __attribute__((aligned(16))) uint4 lds[2][2][NPL][HT * 4];
+
+  const int tile = blockIdx.x, split = blockIdx.y, p = blockIdx.z;
+  int tr, tc;
+  tile_of(tile, tr, tc);
+  const PointDesc pd = h.pts[p];
+  const int tid = threadIdx.x, lane = tid & 63;
+  // wave index as a scalar: the LDS base of a direct-to-LDS load must be wave-uniform
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave >> 1, wc = wave & 1;
+  const int li = lane & 15, lk = lane >> 4;
+
+  const uint4 *Lg = reinterpret_cast<const uint4 *>(h.L + (int64_t)pd.bslot * h.l_stride) + (int64_t)tr * HT * 4;
+  const uint4 *Rg = reinterpret_cast<const uint4 *>(h.R + (int64_t)p * h.r_stride) + (int64_t)tc * HT * 4;
+  const int64_t plane_units = (int64_t)h.Np * 4;   // 16-byte units of one plane of one step
+  const int64_t kc0 = (int64_t)split * h.kc_per_split;
+  const int64_t kc1 = kc0 + h.kc_per_split < h.nkc ? kc0 + h.kc_per_split : h.nkc;
+  const int nsteps = (int)(kc1 - kc0);
+
+  auto issue = [&](int buf, int64_t kc) {
+#pragma unroll
+    for (int pl = 0; pl < NPL; ++pl) {
+      const int64_t off = (kc * 4 + pl) * plane_units;
+      copy_panel(Lg + off, lds[buf][0][pl], wave, lane);
+      copy_panel(Rg + off, lds[buf][1][pl], wave, lane);
+    }
+  };
+
+  f4 accR[4][4], accI[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      accR[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+      accI[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+
+  // fragment of the block at column `col` of a panel: lane (li, lk) reads rows
+  // 8 lk .. 8 lk + 7 of column col
+  auto frag = [&](const uint4 *panel, int col) -> bf8 {
+    return __builtin_bit_cast(bf8, panel[col * 4 + seg_pos(lk, col)]);
+  };
+
+  auto contract = [&](int buf) {
+    bf8 Bv[4][NPL];
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int pl = 0; pl < NPL; ++pl) Bv[y][pl] = frag(lds[buf][1][pl], wc * 64 + y * 16 + li);
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      bf8 A[NPL];
+#pragma unroll
+      for (int pl = 0; pl < NPL; ++pl) A[pl] = frag(lds[buf][0][pl], wr * 64 + x * 16 + li);
+      // Re: Lr Rr (+ Li Ri); each as hi hi + hi lo + lo hi
+#pragma unroll
+      for (int y = 0; y < 4; ++y) accR[x][y] = mfma_bf16(A[0], Bv[y][0], accR[x][y]);
+#pragma unroll
+      for (int y = 0; y < 4; ++y) accR[x][y] = mfma_bf16(A[0], Bv[y][1], accR[x][y]);
+#pragma unroll
+      for (int y = 0; y < 4; ++y) accR[x][y] = mfma_bf16(A[1], Bv[y][0], accR[x][y]);
+      if (CPLX) {
+        const bf8 nh = negate(A[2]), nl = negate(A[3]);
+#pragma unroll
+        for (int y = 0; y < 4; ++y) accI[x][y] = mfma_bf16(A[0], Bv[y][2], accI[x][y]);
+#pragma unroll
+        for (int y = 0; y < 4; ++y) accR[x][y] = mfma_bf16(A[2], Bv[y][2], accR[x][y]);
+#pragma unroll
+        for (int y = 0; y < 4; ++y) accI[x][y] = mfma_bf16(A[0], Bv[y][3], accI[x][y]);
+#pragma unroll
+        for (int y = 0; y < 4; ++y) accR[x][y] = mfma_bf16(A[2], Bv[y][3], accR[x][y]);
+#pragma unroll
+        for (int y = 0; y < 4; ++y) accI[x][y] = mfma_bf16(A[1], Bv[y][2], accI[x][y]);
+#pragma unroll
+        for (int y = 0; y < 4; ++y) accR[x][y] = mfma_bf16(A[3], Bv[y][2], accR[x][y]);
+        // Im: - Li Rr
+#pragma unroll
+        for (int y = 0; y < 4; ++y) accI[x][y] = mfma_bf16(nh, Bv[y][0], accI[x][y]);
+#pragma unroll
+        for (int y = 0; y < 4; ++y) accI[x][y] = mfma_bf16(nh, Bv[y][1], accI[x][y]);
+#pragma unroll
+        for (int y = 0; y < 4; ++y) accI[x][y] = mfma_bf16(nl, Bv[y][0], accI[x][y]);
+      }
+    }
+  };
+
+  if (nsteps > 0) {
+    issue(0, kc0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    for (int s = 0; s < nsteps; ++s) {
+      const int cur = s & 1;
+      if (s + 1 < nsteps) issue(cur ^ 1, kc0 + s + 1);
+      contract(cur);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+    }
+  }
+
+  // FP32 tile of this split: row i, column j of the 128 x 128 tile at i * HT + j;
+  // accumulator register r of lane (li, lk) holds row 4 lk + r, column li of a block
+  float2 *o = h.part + (((int64_t)p * h.nsplit + split) * h.ntiles + tile) * (HT * HT);
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = wr * 64 + x * 16 + 4 * lk + r;
+        const int j = wc * 64 + y * 16 + li;
+        o[i * HT + j] = make_float2(accR[x][y][r], CPLX ? accI[x][y][r] : 0.f);
+      }
+}
+
+// ------------------------------------------------------------------ reduction
+// chi0[p][P][Q] (lower triangle and mirror, FP64) = sum over the splits, in order, of
+// the FP32 tiles; the diagonal from `diag`.  A workgroup covers a 32 x 32 block of one
+// tile; the mirrored block goes through LDS so both writes are row-contiguous.
+__global__ __launch_bounds__(256) void herk_reduce_kernel(const float2 *part, int nsplit, int ntiles, int N,
+                                                          const double *diag, double2 *out, int64_t out_stride) {
+  __shared__ double2 tb[32][33];
+  const int tile = blockIdx.x, blk = blockIdx.y, p = blockIdx.z;
+  int tr, tc;
+  tile_of(tile, tr, tc);
+  const int bi = blk >> 2, bj = blk & 3;   // 32 x 32 block of the 128 x 128 tile
+  const bool dtile = tr == tc;
+  if (dtile && bj > bi) return;           // strictly upper blocks of a diagonal tile
+  const int tid = threadIdx.x;
+  const int j = tid & 31;
+  const int64_t tstride = (int64_t)ntiles * HT * HT;
+  const float2 *src = part + ((int64_t)p * nsplit * ntiles + tile) * (HT * HT);
+  double2 *dst = out + (int64_t)p * out_stride;
+  const double *dg = diag + (int64_t)p * N;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int i = (tid >> 5) + 8 * k;
+    const int li = bi * 32 + i, lj = bj * 32 + j;
+    double re = 0.0, im = 0.0;
+    for (int s = 0; s < nsplit; ++s) {
+      const float2 v = src[s * tstride + li * HT + lj];
+      re += (double)v.x;
+      im += (double)v.y;
+    }
+    tb[i][j] = make_double2(re, im);
+    const int P = tr * HT + li, Q = tc * HT + lj;
+    if (P < N && Q < N && (!dtile || P >= Q))
+      dst[(int64_t)P * N + Q] = (P == Q) ? make_double2(dg[P], 0.0) : make_double2(re, im);
+  }
+  __syncthreads();
+  // mirror: conj(chi0[P][Q]) into chi0[Q][P] for P > Q
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int i = (tid >> 5) + 8 * k;   // row of the mirrored block = column of the source
+    const int Q = tc * HT + bj * 32 + i, P = tr * HT + bi * 32 + j;
+    if (P < N && Q < N && P > Q) {
+      const double2 v = tb[j][i];
+      dst[(int64_t)Q * N + P] = make_double2(v.x, -v.y);
+    }
+  }
+}
+
+}  // namespace
+
+int64_t bf16_prepared_elems(int64_t M, int N) {
+  const int64_t Mp = (M + HK - 1) / HK * HK;
+  const int64_t Np = (N + HT - 1) / HT * HT;
+  return Mp * Np * 4;
+}
+
+void bf16_plan(int64_t M, int N, int npts, int64_t slots, int64_t max_part, Bf16Plan *pl) {
+  pl->Np = (N + HT - 1) / HT * HT;
+  pl->nkc = (M + HK - 1) / HK;
+  const int T = pl->Np / HT;
+  pl->ntiles = T * (T + 1) / 2;
+  // fewest splits that keep every FP32 sum within BF16_SPLIT_ROWS rows, then more (down
+  // to 512 rows a split) while the launch has fewer than two workgroups per slot and the
+  // partial tiles stay within max_part elements (0: no limit)
+  int64_t per = BF16_SPLIT_ROWS / HK;
+  int64_t ns = (pl->nkc + per - 1) / per;
+  while ((int64_t)pl->ntiles * npts * ns < 2 * slots && per > 512 / HK) {
+    const int64_t per2 = per / 2, ns2 = (pl->nkc + per2 - 1) / per2;
+    if (max_part > 0 && (int64_t)npts * ns2 * pl->ntiles * HT * HT > max_part) break;
+    per = per2;
+    ns = ns2;
+  }
+  pl->kc_per_split = (int)per;
+  pl->nsplit = (int)ns;
+}
+
+int64_t bf16_partial_elems(const Bf16Plan &pl, int npts) {
+  return (int64_t)npts * pl.nsplit * pl.ntiles * HT * HT;
+}
+
+hipError_t launch_bf16_prepare(hipStream_t s, const void *B, bool cplx, int64_t M, int N, const double *wtab,
+                               int npts, unsigned short *out) {
+  const int64_t nkc = (M + HK - 1) / HK;
+  const int Np = (N + HT - 1) / HT * HT;
+  const int64_t stride = bf16_prepared_elems(M, N);
+  if (nkc <= 0) return hipSuccess;
+  const int reps = wtab ? npts : 1;
+  for (int p0 = 0; p0 < reps; p0 += PREP_MAXP) {
+    const int np = reps - p0 < PREP_MAXP ? reps - p0 : PREP_MAXP;
+    const double *w = wtab ? wtab + (int64_t)p0 * M : nullptr;
+    const dim3 grid((unsigned)nkc, (unsigned)(Np / PREP_COLS));
+    if (cplx)
+      hipLaunchKernelGGL(bf16_prepare_kernel<true>, grid, dim3(256), 0, s, B, M, N, Np, w, M, np,
+                         out + (int64_t)p0 * stride, stride);
+    else
+      hipLaunchKernelGGL(bf16_prepare_kernel<false>, grid, dim3(256), 0, s, B, M, N, Np, w, M, np,
+                         out + (int64_t)p0 * stride, stride);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_bf16_herk(hipStream_t s, const Bf16Plan &pl, const unsigned short *L, int64_t l_stride,
+                            const unsigned short *R, const PointDesc *pts, int npts, bool cplx, float2 *part, int N,
+                            int64_t M) {
+  if (npts <= 0) return hipSuccess;
+  HerkArgs h{};
+  h.L = L;
+  h.l_stride = l_stride;
+  h.R = R;
+  h.r_stride = bf16_prepared_elems(M, N);
+  h.pts = pts;
+  h.part = part;
+  h.Np = pl.Np;
+  h.ntiles = pl.ntiles;
+  h.nsplit = pl.nsplit;
+  h.kc_per_split = pl.kc_per_split;
+  h.nkc = pl.nkc;
+  const dim3 grid((unsigned)pl.ntiles, (unsigned)pl.nsplit, (unsigned)npts);
+  if (cplx) hipLaunchKernelGGL(herk_bf16x3_kernel<true>, grid, dim3(256), 0, s, h);
+  else hipLaunchKernelGGL(herk_bf16x3_kernel<false>, grid, dim3(256), 0, s, h);
+  return hipGetLastError();
+}
+
+hipError_t launch_bf16_reduce(hipStream_t s, const Bf16Plan &pl, const float2 *part, int npts, int N,
+                              const double *diag, double2 *out, int64_t out_stride) {
+  if (npts <= 0) return hipSuccess;
+  hipLaunchKernelGGL(herk_reduce_kernel, dim3((unsigned)pl.ntiles, 16, (unsigned)npts), dim3(256), 0, s, part,
+                     pl.nsplit, pl.ntiles, N, diag, out, out_stride);
+  return hipGetLastError();
+}
+
+}  // namespace rpa

@@ -86,6 +86,39 @@ hipError_t launch_diag_exact(hipStream_t s, const void *B, bool cplx, int64_t M,
 hipError_t launch_chi0_mixed(hipStream_t s, const Chi0Args &a, int32_t npts, const float2 *B32,
                              const double *diag, int prec);
 
+// ---- split-BF16 chi0 from prepared operands (chi0_bf16.hip) ------------------------
+// No FP32 sum of the contraction runs over more rows than this.
+constexpr int64_t BF16_SPLIT_ROWS = 4096;
+struct Bf16Plan {
+  int32_t Np;            // N rounded up to the 128-wide tile
+  int32_t ntiles;        // tiles on and below the diagonal
+  int32_t nsplit;        // row splits
+  int32_t kc_per_split;  // 32-row steps per split
+  int64_t nkc;           // 32-row steps of the whole contraction
+};
+// bf16 elements of one prepared operand (four planes, rows and columns padded).
+int64_t bf16_prepared_elems(int64_t M, int N);
+// Tiles and row splits of a launch of npts points on a device with `slots` CUs, with at
+// most max_part partial-tile elements when max_part > 0 (never fewer splits than needed
+// to bound the FP32 sums).
+void bf16_plan(int64_t M, int N, int npts, int64_t slots, int64_t max_part, Bf16Plan *pl);
+// float2 elements of the partial-tile buffer of such a launch.
+int64_t bf16_partial_elems(const Bf16Plan &pl, int npts);
+// Prepared operands from an FP64 B slab: wtab == nullptr gives the unscaled left operand
+// (one), else one right operand w_p B per point p < npts, at bf16_prepared_elems apart.
+hipError_t launch_bf16_prepare(hipStream_t s, const void *B, bool cplx, int64_t M, int N, const double *wtab,
+                               int npts, unsigned short *out);
+// FP32 partial tiles of the row splits of npts points (left operand of point p at
+// L + pts[p].bslot * l_stride, right operand p at R + p * bf16_prepared_elems) into part,
+// which holds bf16_partial_elems(pl, npts) float2.
+hipError_t launch_bf16_herk(hipStream_t s, const Bf16Plan &pl, const unsigned short *L, int64_t l_stride,
+                            const unsigned short *R, const PointDesc *pts, int npts, bool cplx, float2 *part, int N,
+                            int64_t M);
+// chi0 of those points into out (FP64 complex, Hermitian, point p at p * out_stride): the
+// splits summed in FP64 in order, the diagonal from diag[p][P].
+hipError_t launch_bf16_reduce(hipStream_t s, const Bf16Plan &pl, const float2 *part, int npts, int N,
+                              const double *diag, double2 *out, int64_t out_stride);
+
 // Blocked Cholesky log-det over the whole GPU on W = -Pi (see trln_blocked.hip):
 // eps[out_map[b]] = ln det(1 - Pi_b) + Re Tr Pi_b, info_out[out_map[b]] = -1 or the failing
 // column.  W is overwritten; scratch holds trln_blocked_scratch_bytes(batch) bytes.

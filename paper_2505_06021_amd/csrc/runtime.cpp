@@ -200,15 +200,6 @@ int validate_system(const rpa_system *sys, HostSmall &hs) {
 }
 
 // ---- the point pipeline -------------------------------------------------------------
-int chi0_kt() {
-  static int kt = [] {
-    const char *e = getenv("RPA_CHI0_KT");
-    const int v = e ? atoi(e) : 16;
-    return (v == 8 || v == 16 || v == 32) ? v : 16;
-  }();
-  return kt;
-}
-
 bool trln_single() {
   static bool v = [] {
     const char *e = getenv("RPA_TRLN_SINGLE");
@@ -273,7 +264,20 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   const bool vh_direct = sys->memspace == RPA_MEM_DEVICE && cplx;
   const int64_t b_slot = b_direct ? 0 : M * N * belem;
   const int64_t vh_slot = vh_direct ? 0 : nn * 16;
-  const int64_t b32_slot = mixed ? M * N * 8 : 0;
+  // split-BF16 keeps a prepared (split, padded) copy of each B slab instead of the FP32
+  // copy of the FP32 path, plus per point in flight a prepared right operand and the
+  // partial tiles of the row splits
+  const bool bsplit = job.prec == RPA_BF16X3;
+  const int64_t prep_bytes = bsplit ? bf16_prepared_elems(M, N) * 2 : 0;
+  const int64_t b32_slot = bsplit ? prep_bytes : mixed ? M * N * 8 : 0;
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx.device) != hipSuccess) ncu = 256;
+  auto bsplit_bytes = [&](int64_t r) -> int64_t {
+    if (!bsplit || r <= 0) return 0;
+    Bf16Plan pl;
+    bf16_plan(M, N, (int)r, ncu, 0, &pl);
+    return r * prep_bytes + bf16_partial_elems(pl, (int)r) * 8 + 512;
+  };
   const int64_t per_pt = 2 * nn * 16 + M * 8 + (mixed ? (int64_t)N * 8 : 0) + trln_blocked_scratch_bytes(1) + 64;
   const int64_t diag_scratch = mixed ? diag_exact_scratch_doubles(M, N, 16) * 8 : 0;
   const int64_t small = (int64_t)(hs.eps_occ.size() + hs.eps_virt.size() + hs.zeta_k.size()) * 8 +
@@ -300,15 +304,22 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
     for (int i = g0; i < g0 + g && i < (int)qs.size(); ++i) c += (int64_t)by_q[qs[i]].size();
     return c;
   };
-  while (gq > 1 && gq * (b_slot + vh_slot + b32_slot) + std::min<int64_t>(pts_of(0, gq), 256) * per_pt > avail) --gq;
+  const int64_t one_split = bsplit_bytes(1);
+  while (gq > 1 && gq * (b_slot + vh_slot + b32_slot) + std::min<int64_t>(pts_of(0, gq), 256) * per_pt + one_split >
+                       avail)
+    --gq;
   const int64_t rest = avail - gq * (b_slot + vh_slot + b32_slot);
-  if (rest < per_pt)
+  if (rest < per_pt + one_split)
     return fail(RPA_E_NOMEM, "one q of this system needs %lld bytes, budget is %lld",
-                (long long)(b_slot + vh_slot + b32_slot + per_pt + small), (long long)budget);
-  int64_t pb_cap = rest / per_pt;
+                (long long)(b_slot + vh_slot + b32_slot + per_pt + one_split + small), (long long)budget);
+  int64_t pb_cap = (rest - one_split) / per_pt;
   int64_t max_group_pts = 0;
   for (size_t g0 = 0; g0 < qs.size(); g0 += gq) max_group_pts = std::max(max_group_pts, pts_of((int)g0, gq));
   const int64_t pbatch = std::min<int64_t>(pb_cap, max_group_pts);
+  // points per split-BF16 sub-launch: as many as the rest of the budget holds
+  int64_t rbatch = bsplit ? pbatch : 0;
+  while (rbatch > 1 && pbatch * per_pt + bsplit_bytes(rbatch) > rest) rbatch = rbatch * 3 / 4;
+  if (bsplit && rbatch < 1) rbatch = 1;
 
   Arena ar(ctx, use_cache);
   const bool prof = use_cache && ctx.profile;   // timing only on the synchronous path
@@ -332,10 +343,18 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   ar.plan(pbatch * M * 8, (void **)&d_w);
   float2 *d_B32 = nullptr;
   double *d_diag = nullptr, *d_dscr = nullptr;
+  unsigned short *d_R = nullptr;
+  float2 *d_part = nullptr;
+  Bf16Plan rplan{};
   if (mixed) {
     ar.plan(gq * b32_slot, (void **)&d_B32);
     ar.plan(pbatch * N * 8, (void **)&d_diag);
     ar.plan(diag_scratch, (void **)&d_dscr);
+  }
+  if (bsplit) {
+    bf16_plan(M, N, (int)rbatch, ncu, 0, &rplan);
+    ar.plan(rbatch * prep_bytes, (void **)&d_R);
+    ar.plan(bf16_partial_elems(rplan, (int)rbatch) * 8, (void **)&d_part);
   }
   ar.plan(pbatch * nn * 16, &d_T);
   void *d_tscr;
@@ -344,11 +363,6 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   ar.plan((int64_t)(hs.nq + 4097) * 8, (void **)&d_qw);
   RPA_TRY(ar.commit(st));
   const bool single_wg_trln = trln_single();
-  // two-way row split of the contraction when it fills the last round of workgroups
-  // better; the second half's result goes to the T buffer, which is free until the
-  // sandwich
-  int ncu = 0;
-  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx.device) != hipSuccess) ncu = 256;
 
   RPA_HIP(hipMemcpyAsync(d_eo, hs.eps_occ.data(), hs.eps_occ.size() * 8, hipMemcpyHostToDevice, st));
   RPA_HIP(hipMemcpyAsync(d_ev, hs.eps_virt.data(), hs.eps_virt.size() * 8, hipMemcpyHostToDevice, st));
@@ -380,7 +394,11 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
         const char *src = b_direct ? (const char *)sys->B + (int64_t)q * M * N * belem
                                    : (const char *)d_B + (int64_t)s * b_slot;
         if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0_AUX));
-        RPA_HIP(launch_to_f32(st, src, d_B32 + (int64_t)s * M * N, M * N, cplx));
+        if (bsplit)
+          RPA_HIP(launch_bf16_prepare(st, src, cplx, M, N, nullptr, 1,
+                                      (unsigned short *)((char *)d_B32 + (int64_t)s * b32_slot)));
+        else
+          RPA_HIP(launch_to_f32(st, src, d_B32 + (int64_t)s * M * N, M * N, cplx));
         if (prof) RPA_TRY(ctx.prof_end(st));
       }
       if (vh_slot) {
@@ -463,15 +481,47 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
                                     d_diag + (int64_t)i0 * N));
           i0 = i1;
         }
-        if (prof) RPA_TRY(ctx.prof_end(st));
-        if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0));
-        RPA_HIP(launch_chi0_mixed(st, ca, nb, d_B32, d_diag, (int)job.prec));
+        if (bsplit) {
+          // sub-launches of up to rbatch points: prepare their right operands (per run of
+          // points on one B slab), then contract and reduce
+          for (int r0 = 0; r0 < nb; r0 += (int)rbatch) {
+            const int r1 = std::min<int>(nb, r0 + (int)rbatch);
+            int i0 = r0;
+            while (i0 < r1) {
+              int i1 = i0 + 1;
+              while (i1 < r1 && hp[i1].bslot == hp[i0].bslot) ++i1;
+              const int64_t slab = b_direct ? job.pq[(size_t)gp[b0 + i0]] : hp[i0].bslot;
+              const char *bsrc = (const char *)(b_direct ? sys->B : d_B) + slab * M * N * belem;
+              RPA_HIP(launch_bf16_prepare(st, bsrc, cplx, M, N, d_w + (int64_t)i0 * M, i1 - i0,
+                                          d_R + (int64_t)(i0 - r0) * (prep_bytes / 2)));
+              i0 = i1;
+            }
+            if (prof) RPA_TRY(ctx.prof_end(st));
+            if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0));
+            Bf16Plan pl;
+            bf16_plan(M, N, r1 - r0, ncu, bf16_partial_elems(rplan, (int)rbatch), &pl);
+            RPA_HIP(launch_bf16_herk(st, pl, (const unsigned short *)d_B32, prep_bytes / 2, d_R, d_pts + r0, r1 - r0,
+                                     cplx, d_part, N, M));
+            if (prof) RPA_TRY(ctx.prof_end(st));
+            if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0_AUX));
+            RPA_HIP(launch_bf16_reduce(st, pl, d_part, r1 - r0, N, d_diag + (int64_t)r0 * N,
+                                       (double2 *)d_chi + (int64_t)r0 * nn, nn));
+            if (prof) RPA_TRY(ctx.prof_end(st));
+            if (prof && r1 < nb) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0_AUX));
+          }
+        } else {
+          if (prof) RPA_TRY(ctx.prof_end(st));
+          if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0));
+          RPA_HIP(launch_chi0_mixed(st, ca, nb, d_B32, d_diag, (int)job.prec));
+        }
       } else {
         if (prof) RPA_TRY(ctx.prof_end(st));
+        int kt = 16;
+        RPA_TRY(tune_chi0_kt(st, ca, nb, cplx, &kt));
         if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0));
-        RPA_HIP(launch_chi0_f64(st, ca, nb, cplx, chi0_kt()));
+        RPA_HIP(launch_chi0_f64(st, ca, nb, cplx, kt));
       }
-      if (prof) RPA_TRY(ctx.prof_end(st));
+      if (prof && !bsplit) RPA_TRY(ctx.prof_end(st));
 
       const double2 *vh = vh_direct ? (const double2 *)sys->vhalf : (const double2 *)d_vh;
       GemmArgs g1{};   // T = chi0 V^(1/2)

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librpa.so")
 
 EXPORTS = ("rpa_init", "rpa_finalize", "rpa_last_error", "rpa_set_stream", "rpa_chi0", "rpa_pi",
            "rpa_trln", "rpa_energy", "rpa_points", "rpa_philox_B", "rpa_philox_words",
-           "rpa_submit", "rpa_poll", "rpa_get_stats", "rpa_profile", "rpa_profile_read")
+           "rpa_submit", "rpa_poll", "rpa_get_stats", "rpa_profile", "rpa_profile_read", "rpa_tuned")
 KERNEL_KINDS = ("philox", "chi0", "pi", "trln", "other", "chi0_aux")
 
 
@@ -87,6 +87,7 @@ def load():
         "rpa_get_stats": [P, C.POINTER(RpaStatsC)],
         "rpa_profile": [P, I32],
         "rpa_profile_read": [P, C.POINTER(RpaKernelTimesC)],
+        "rpa_tuned": [C.c_char_p, C.c_int32, C.POINTER(C.c_int32)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -96,6 +97,20 @@ def load():
     lib.rpa_last_error.restype = C.c_char_p
     _lib = lib
     return lib
+
+
+def tuned():
+    """{shape bucket: K-step depth} chosen so far by the chi0 depth tuner of this process."""
+    lib = load()
+    need = C.c_int32(0)
+    lib.rpa_tuned(None, 0, C.byref(need))
+    buf = C.create_string_buffer(need.value + 1)
+    lib.rpa_tuned(buf, need.value + 1, C.byref(need))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        key, kt = line.split()
+        out[key] = int(kt)
+    return out
 
 
 def _ptr(a):

@@ -95,3 +95,44 @@ def test_mixed_is_deterministic(ctx):
     a = ctx.energy(s, prec=BF16X3)
     b = ctx.energy(s, prec=BF16X3)
     assert a[0] == b[0] and np.array_equal(a[1], b[1])
+
+
+# ------------------------------------------------ split-BF16 from prepared operands
+
+@pytest.mark.parametrize("naux,nocc,nvirt", [(1, 2, 5), (127, 3, 7), (128, 4, 9), (129, 3, 7), (256, 8, 150)])
+def test_chi0_bf16x3_tile_and_split_edges(ctx, naux, nocc, nvirt):
+    # 128-wide output tiles and 32-row steps with ragged tails; (8, 150) on a 2x2x1 grid
+    # gives M = 4800 rows, more than one 4096-row split
+    s = inputs.make_system(f"edge{naux}", (2, 2, 1), nocc, nvirt, naux, 2, 77 + naux, is_complex=True)
+    ref = orc.chi0(s, 2, s.omega[1])
+    say(f"chi0 bf16x3 N={naux} M={4 * nocc * nvirt}")
+    got = ctx.chi0(s, 2, s.omega[1], prec=BF16X3)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    say(f"  rel Frobenius error {err:.3e}")
+    assert err <= TOL_CHI0[BF16X3]
+    d_ref = np.real(np.diagonal(ref))
+    assert np.max(np.abs(np.real(np.diagonal(got)) - d_ref) / np.abs(d_ref)) <= 1e-13
+    assert np.abs(got - got.conj().T).max() == 0.0
+
+
+def test_energy_bf16x3_device_inputs_bitwise(ctx):
+    say("energy bf16x3 device inputs")
+    s = ragged(3)
+    a = ctx.energy(s, prec=BF16X3, device=False)
+    b = ctx.energy(s, prec=BF16X3, device=True)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
+
+
+def test_energy_bf16x3_sub_launches_under_hbm_limit():
+    # a 600 MB limit leaves room for the prepared right operands of only a few points
+    # at a time, so each batch runs as several contraction launches
+    from paper_2505_06021_amd import rpa
+    s = inputs.slab_3x3_384()
+    with rpa.Context(0) as free:
+        E0, eps0 = free.energy(s, prec=BF16X3)
+    say("energy bf16x3 under a 600 MB limit")
+    with rpa.Context(0, hbm_limit=600 * 2 ** 20) as tight:
+        E1, eps1 = tight.energy(s, prec=BF16X3)
+    say(f"  E free {E0:.12f} E tight {E1:.12f}")
+    assert abs(E1 - E0) <= TOL_E[BF16X3]
+    assert np.max(np.abs(eps1 - eps0)) <= 1e-6 * np.max(np.abs(eps0))

@@ -1,0 +1,72 @@
+"""The K-step depth of the FP64 chi0 contraction changes speed, never results.
+
+Every depth (8, 16, 32 rows of B per LDS step) runs the same sequence of 4-row MFMA
+steps in the same row order, so with one row split chi0 is bit-for-bit the same for all
+three; each must match the oracle to 1e-12 (Frobenius, relative).  The tuner must record
+one choice per shape bucket, persist it when asked, and leave E within 1e-12 of a run
+at the fixed default depth.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import rpa_oracle as orc
+from paper_2505_06021_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-test] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2505_06021_amd import rpa
+    c = rpa.Context(0)
+    yield c
+    c.close()
+
+
+def tall_system():
+    # M = 4 * 8 * 150 = 4800 rows (more than the 4096 rows the tuner times), N = 150
+    return inputs.make_system("tall", (2, 2, 1), 8, 150, 150, 3, 41, is_complex=True)
+
+
+def test_chi0_every_depth_identical_and_exact(ctx, monkeypatch):
+    s = tall_system()
+    ref = orc.chi0(s, 1, s.omega[1])
+    got = {}
+    for kt in (8, 16, 32):
+        say(f"chi0 depth {kt}")
+        monkeypatch.setenv("RPA_CHI0_KT", str(kt))
+        got[kt] = ctx.chi0(s, 1, s.omega[1])
+        err = np.linalg.norm(got[kt] - ref) / np.linalg.norm(ref)
+        assert err <= 1e-12, (kt, err)
+    assert np.array_equal(got[8], got[16]) and np.array_equal(got[16], got[32])
+
+
+def test_tuner_records_and_persists_choice(ctx, monkeypatch, tmp_path):
+    from paper_2505_06021_amd import rpa
+    s = inputs.make_system("tune", (2, 2, 1), 3, 7, 150, 5, 31, is_complex=True, sigma=0.15)
+    monkeypatch.setenv("RPA_CHI0_KT", "16")
+    say("energy at fixed depth")
+    e_fixed, eps_fixed = ctx.energy(s)
+    monkeypatch.delenv("RPA_CHI0_KT")
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("RPA_TUNE_CACHE", str(cache))
+    say("energy with the tuner")
+    e_tuned, eps_tuned = ctx.energy(s)
+    choices = rpa.tuned()
+    assert choices, "the tuner recorded no choice"
+    assert all(v in (8, 16, 32) for v in choices.values())
+    assert any(k.startswith("f64_c_N192_") for k in choices), choices
+    assert abs(e_tuned - e_fixed) <= 1e-12 * abs(e_fixed)
+    assert np.max(np.abs(eps_tuned - eps_fixed)) <= 1e-12 * np.max(np.abs(eps_fixed))
+    e_ref = orc.energy(s)[0]
+    assert abs(e_tuned - e_ref) <= 1e-10 * abs(e_ref)
+    if cache.exists():   # written when the bucket was tuned in this test's lifetime
+        lines = dict(l.split() for l in cache.read_text().splitlines())
+        assert all(int(v) in (8, 16, 32) for v in lines.values())
