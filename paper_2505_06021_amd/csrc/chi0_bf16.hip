@@ -19,10 +19,12 @@
 // Prepared layout of one operand (bf16 elements, Mp = M rounded up to 32 rows, Np = N
 // rounded up to the 128-wide output tile; rows >= M and columns >= N are zero):
 //   element (m, n, plane) at ((m / 32 * 4 + plane) * Np + n) * 32 + pos(m % 32, n)
-//   pos(r, n) = ((r / 8) ^ ((n / 4) % 4)) * 8 + r % 8
+//   pos(r, n) = ((r / 8) ^ ((n / 2) % 4)) * 8 + r % 8
 // so the 32 rows of one column are 64 contiguous bytes, a 128-column panel of one plane
 // is 8 KB contiguous (copied into LDS as is), and the XOR on the 16-byte segments makes
-// the MFMA fragment reads from LDS free of bank conflicts.
+// the MFMA fragment reads from LDS free of bank conflicts (the eight lanes served
+// together read eight columns at one segment index: the XOR spreads them over the
+// 128 bytes the LDS delivers per clock).
 #include "common.hpp"
 
 namespace rpa {
@@ -35,6 +37,7 @@ constexpr int HT = 128;          // output tile edge (one workgroup)
 constexpr int HK = 32;           // contraction rows per step (the K of one BF16 MFMA)
 constexpr int PREP_COLS = 64;    // columns per preparation workgroup
 constexpr int PREP_MAXP = 16;    // points per preparation launch
+constexpr int HWAVES = 8;        // waves of a contraction workgroup: 2 x 4, 64 x 32 each
 
 __device__ __forceinline__ void tile_of(int t, int &tr, int &tc) {
   int r = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
@@ -44,7 +47,7 @@ __device__ __forceinline__ void tile_of(int t, int &tr, int &tc) {
   tc = t - r * (r + 1) / 2;
 }
 
-__device__ __forceinline__ int seg_pos(int s, int n) { return s ^ ((n >> 2) & 3); }
+__device__ __forceinline__ int seg_pos(int s, int n) { return s ^ ((n >> 1) & 3); }
 
 // hi = bf16(x) (round to nearest even through FP32), lo = bf16(x - hi) with the
 // difference taken in FP64; two values at once, packed as the MFMA reads them.
@@ -145,31 +148,34 @@ __device__ __forceinline__ bf8 negate(bf8 x) {
   return __builtin_bit_cast(bf8, u);
 }
 
-// one 8 KB panel (128 columns x 32 rows of one plane) from HBM straight into LDS: two
-// 16-byte loads per thread; wave w fills units w * 64 .. w * 64 + 63 of each half
+// one 8 KB panel (128 columns x 32 rows of one plane) from HBM straight into LDS: one
+// 16-byte load per thread; wave w fills units w * 64 .. w * 64 + 63
 __device__ __forceinline__ void copy_panel(const uint4 *src, uint4 *dst, int wave, int lane) {
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int u = j * 256 + wave * 64;
-    __builtin_amdgcn_global_load_lds((const void *)(src + u + lane),
-                                     (__attribute__((address_space(3))) void *)(dst + u), 16, 0, 0);
-  }
+  const int u = wave * 64;
+  __builtin_amdgcn_global_load_lds((const void *)(src + u + lane),
+                                   (__attribute__((address_space(3))) void *)(dst + u), 16, 0, 0);
 }
 
 template <bool CPLX>
-__global__ __launch_bounds__(256) void herk_bf16x3_kernel(HerkArgs h) {
+__global__ __launch_bounds__(64 * HWAVES) void herk_bf16x3_kernel(HerkArgs h) {
   constexpr int NPL = CPLX ? 4 : 2;
   // [buffer][operand][plane][column * 4 + segment], 16-byte units
   __shared__ __attribute__((aligned(16))) uint4 lds[2][2][NPL][HT * 4];
 
-  const int tile = blockIdx.x, split = blockIdx.y, p = blockIdx.z;
+  // workgroups go to the 8 XCDs round-robin; give each XCD a contiguous range of the
+  // (tile fastest, then split, then point) order so that its L2 serves shared panels
+  const int G = gridDim.x, hw = blockIdx.x;
+  const int per = (G + 7) / 8, tall = G % 8 == 0 ? 8 : G % 8;
+  const int xcd = hw % 8, loc = hw / 8;
+  const int lg = xcd < tall ? xcd * per + loc : tall * per + (xcd - tall) * (per - 1) + loc;
+  const int tile = lg % h.ntiles, split = (lg / h.ntiles) % h.nsplit, p = lg / (h.ntiles * h.nsplit);
   int tr, tc;
   tile_of(tile, tr, tc);
   const PointDesc pd = h.pts[p];
   const int tid = threadIdx.x, lane = tid & 63;
   // wave index as a scalar: the LDS base of a direct-to-LDS load must be wave-uniform
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave >> 2, wc = wave & 3;     // 64 rows x 32 columns of the tile
   const int li = lane & 15, lk = lane >> 4;
 
   const uint4 *Lg = reinterpret_cast<const uint4 *>(h.L + (int64_t)pd.bslot * h.l_stride) + (int64_t)tr * HT * 4;
@@ -188,11 +194,11 @@ __global__ __launch_bounds__(256) void herk_bf16x3_kernel(HerkArgs h) {
     }
   };
 
-  f4 accR[4][4], accI[4][4];
+  f4 accR[4][2], accI[4][2];
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
+    for (int y = 0; y < 2; ++y) {
       accR[x][y] = f4{0.f, 0.f, 0.f, 0.f};
       accI[x][y] = f4{0.f, 0.f, 0.f, 0.f};
     }
@@ -204,11 +210,11 @@ __global__ __launch_bounds__(256) void herk_bf16x3_kernel(HerkArgs h) {
   };
 
   auto contract = [&](int buf) {
-    bf8 Bv[4][NPL];
+    bf8 Bv[2][NPL];
 #pragma unroll
-    for (int y = 0; y < 4; ++y)
+    for (int y = 0; y < 2; ++y)
 #pragma unroll
-      for (int pl = 0; pl < NPL; ++pl) Bv[y][pl] = frag(lds[buf][1][pl], wc * 64 + y * 16 + li);
+      for (int pl = 0; pl < NPL; ++pl) Bv[y][pl] = frag(lds[buf][1][pl], wc * 32 + y * 16 + li);
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
       bf8 A[NPL];
@@ -216,32 +222,32 @@ __global__ __launch_bounds__(256) void herk_bf16x3_kernel(HerkArgs h) {
       for (int pl = 0; pl < NPL; ++pl) A[pl] = frag(lds[buf][0][pl], wr * 64 + x * 16 + li);
       // Re: Lr Rr (+ Li Ri); each as hi hi + hi lo + lo hi
 #pragma unroll
-      for (int y = 0; y < 4; ++y) accR[x][y] = mfma_bf16(A[0], Bv[y][0], accR[x][y]);
+      for (int y = 0; y < 2; ++y) accR[x][y] = mfma_bf16(A[0], Bv[y][0], accR[x][y]);
 #pragma unroll
-      for (int y = 0; y < 4; ++y) accR[x][y] = mfma_bf16(A[0], Bv[y][1], accR[x][y]);
+      for (int y = 0; y < 2; ++y) accR[x][y] = mfma_bf16(A[0], Bv[y][1], accR[x][y]);
 #pragma unroll
-      for (int y = 0; y < 4; ++y) accR[x][y] = mfma_bf16(A[1], Bv[y][0], accR[x][y]);
+      for (int y = 0; y < 2; ++y) accR[x][y] = mfma_bf16(A[1], Bv[y][0], accR[x][y]);
       if (CPLX) {
         const bf8 nh = negate(A[2]), nl = negate(A[3]);
 #pragma unroll
-        for (int y = 0; y < 4; ++y) accI[x][y] = mfma_bf16(A[0], Bv[y][2], accI[x][y]);
+        for (int y = 0; y < 2; ++y) accI[x][y] = mfma_bf16(A[0], Bv[y][2], accI[x][y]);
 #pragma unroll
-        for (int y = 0; y < 4; ++y) accR[x][y] = mfma_bf16(A[2], Bv[y][2], accR[x][y]);
+        for (int y = 0; y < 2; ++y) accR[x][y] = mfma_bf16(A[2], Bv[y][2], accR[x][y]);
 #pragma unroll
-        for (int y = 0; y < 4; ++y) accI[x][y] = mfma_bf16(A[0], Bv[y][3], accI[x][y]);
+        for (int y = 0; y < 2; ++y) accI[x][y] = mfma_bf16(A[0], Bv[y][3], accI[x][y]);
 #pragma unroll
-        for (int y = 0; y < 4; ++y) accR[x][y] = mfma_bf16(A[2], Bv[y][3], accR[x][y]);
+        for (int y = 0; y < 2; ++y) accR[x][y] = mfma_bf16(A[2], Bv[y][3], accR[x][y]);
 #pragma unroll
-        for (int y = 0; y < 4; ++y) accI[x][y] = mfma_bf16(A[1], Bv[y][2], accI[x][y]);
+        for (int y = 0; y < 2; ++y) accI[x][y] = mfma_bf16(A[1], Bv[y][2], accI[x][y]);
 #pragma unroll
-        for (int y = 0; y < 4; ++y) accR[x][y] = mfma_bf16(A[3], Bv[y][2], accR[x][y]);
+        for (int y = 0; y < 2; ++y) accR[x][y] = mfma_bf16(A[3], Bv[y][2], accR[x][y]);
         // Im: - Li Rr
 #pragma unroll
-        for (int y = 0; y < 4; ++y) accI[x][y] = mfma_bf16(nh, Bv[y][0], accI[x][y]);
+        for (int y = 0; y < 2; ++y) accI[x][y] = mfma_bf16(nh, Bv[y][0], accI[x][y]);
 #pragma unroll
-        for (int y = 0; y < 4; ++y) accI[x][y] = mfma_bf16(nh, Bv[y][1], accI[x][y]);
+        for (int y = 0; y < 2; ++y) accI[x][y] = mfma_bf16(nh, Bv[y][1], accI[x][y]);
 #pragma unroll
-        for (int y = 0; y < 4; ++y) accI[x][y] = mfma_bf16(nl, Bv[y][0], accI[x][y]);
+        for (int y = 0; y < 2; ++y) accI[x][y] = mfma_bf16(nl, Bv[y][0], accI[x][y]);
       }
     }
   };
@@ -265,11 +271,11 @@ __global__ __launch_bounds__(256) void herk_bf16x3_kernel(HerkArgs h) {
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y)
+    for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = wr * 64 + x * 16 + 4 * lk + r;
-        const int j = wc * 64 + y * 16 + li;
+        const int j = wc * 32 + y * 16 + li;
         o[i * HT + j] = make_float2(accR[x][y][r], CPLX ? accI[x][y][r] : 0.f);
       }
 }
@@ -392,9 +398,11 @@ hipError_t launch_bf16_herk(hipStream_t s, const Bf16Plan &pl, const unsigned sh
   h.nsplit = pl.nsplit;
   h.kc_per_split = pl.kc_per_split;
   h.nkc = pl.nkc;
-  const dim3 grid((unsigned)pl.ntiles, (unsigned)pl.nsplit, (unsigned)npts);
-  if (cplx) hipLaunchKernelGGL(herk_bf16x3_kernel<true>, grid, dim3(256), 0, s, h);
-  else hipLaunchKernelGGL(herk_bf16x3_kernel<false>, grid, dim3(256), 0, s, h);
+  const int64_t nwg = (int64_t)pl.ntiles * pl.nsplit * npts;
+  if (nwg > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)nwg);
+  if (cplx) hipLaunchKernelGGL(herk_bf16x3_kernel<true>, grid, dim3(64 * HWAVES), 0, s, h);
+  else hipLaunchKernelGGL(herk_bf16x3_kernel<false>, grid, dim3(64 * HWAVES), 0, s, h);
   return hipGetLastError();
 }
 
