@@ -260,7 +260,8 @@ def main():
         "config": {"workload": args.workload, "grid": list(s.grid), "nk": s.nk, "nq": s.nq,
                    "nocc": s.nocc, "nvirt": s.nvirt, "naux": s.naux, "nw": s.nw,
                    "is_complex": s.is_complex, "chi0_precision": args.prec,
-                   "B": "Philox4x32-10 on device", "parallelism": "single GPU"},
+                   "B": "Philox4x32-10 on device", "parallelism": "single GPU",
+                   "chi0_tile_config": sorted(set(rpa.tuned().values())) if args.prec == "fp64" else None},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "kernel": "chi0", "flops_per_launch": issued_launch,

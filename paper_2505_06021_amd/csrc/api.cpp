@@ -223,9 +223,9 @@ int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega, rpa_
     RPA_HIP(launch_diag_exact(c.stream, B, cplx, M, N, wt, 1, scr, dg));
     RPA_HIP(launch_chi0_mixed(c.stream, a, 1, b32, dg, (int)prec));
   } else {
-    int kt = 16;
-    RPA_TRY(tune_chi0_kt(c.stream, a, 1, cplx, &kt));
-    RPA_HIP(launch_chi0_f64(c.stream, a, 1, cplx, kt));
+    int cfg = 1;
+    RPA_TRY(tune_chi0_cfg(c.stream, a, 1, cplx, &cfg));
+    RPA_HIP(launch_chi0_f64(c.stream, a, 1, cplx, cfg));
   }
   if (!direct) RPA_TRY(deliver_complex(c, chi0, out, (int64_t)N * N, hs.is_complex, sys->memspace));
   RPA_HIP(hipStreamSynchronize(c.stream));

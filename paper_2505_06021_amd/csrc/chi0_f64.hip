@@ -241,6 +241,155 @@ __global__ __launch_bounds__(256) void chi0_f64_kernel(Chi0Args a) {
       }
 }
 
+// The same contraction on 128 x 128 tiles: eight waves, each a 64 x 32 sub-tile (4 x 2
+// MFMA blocks), 16-row K steps (64 KB of LDS per stage, double-buffered, one workgroup
+// per CU).  Twice the MFMA work per loaded byte of the 64-wide tile.  A thread stages one
+// row and four columns (32 apart) of both panels, so every load instruction of a wave
+// reads two 512-byte row segments.  Workgroups are numbered so that each of the 8 XCDs
+// (which take workgroups round-robin) gets a contiguous range of the (tile, point,
+// split) order and its L2 serves the panels those tiles share.
+constexpr int TW = 128;
+constexpr int LDPW = TW + 1;
+constexpr int KTW = 16;
+
+template <bool CPLX_B>
+__global__ __launch_bounds__(512) void chi0_f64_t128_kernel(Chi0Args a, int32_t ntiles, int32_t npts) {
+  __shared__ double2 lds[2][2][KTW][LDPW];
+  const int G = gridDim.x, hw = blockIdx.x;
+  const int per = (G + 7) / 8, tall = G % 8 == 0 ? 8 : G % 8;
+  const int xcd = hw % 8, loc = hw / 8;
+  const int lg = xcd < tall ? xcd * per + loc : tall * per + (xcd - tall) * (per - 1) + loc;
+  const int tile = lg % ntiles, p = (lg / ntiles) % npts, split = lg / (ntiles * npts);
+
+  const PointDesc pd = a.pts[p];
+  int tr, tc;
+  tile_of(tile, tr, tc);
+  const int N = a.N;
+  const int ms = (int)((((a.M + a.ksplit - 1) / a.ksplit) + KTW - 1) / KTW) * KTW;
+  const int mlo = split * ms;
+  const int M = mlo + ms < (int)a.M ? mlo + ms : (int)a.M;
+  const int P0 = tr * TW, Q0 = tc * TW;
+  const bool diag = (tr == tc);
+
+  const int tid = threadIdx.x;
+  const int lrow = tid >> 5, lc = tid & 31;
+  const char *bbase = reinterpret_cast<const char *>(a.B) + (int64_t)pd.bslot * a.b_slot_stride * (CPLX_B ? 16 : 8);
+  const double *wrow = a.wtab + (int64_t)p * a.M;
+  int pcol[4], qcol[4];
+  bool pok[4], qok[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int P = P0 + lc + 32 * c, Q = Q0 + lc + 32 * c;
+    pok[c] = P < N;
+    qok[c] = Q < N;
+    pcol[c] = pok[c] ? P : 0;
+    qcol[c] = qok[c] ? Q : 0;
+  }
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = wave >> 2, wc = wave & 3;
+  const int li = lane & 15, lk = lane >> 4;
+
+  d4 accR[4][2], accI[4][2];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      accR[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+      accI[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+
+  double2 sa[4], sb[4];
+  double sw;
+  bool mv;
+  auto load = [&](int m0) {
+    const int m = m0 + lrow;
+    mv = m < M;
+    const int mc = mv ? m : 0;
+    sw = wrow[mc];
+    const int64_t rowoff = (int64_t)mc * N;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      sa[c] = load_b<CPLX_B>(bbase, rowoff + pcol[c]);
+      sb[c] = load_b<CPLX_B>(bbase, rowoff + qcol[c]);
+    }
+  };
+  auto store = [&](int buf) {
+    const double w = mv ? sw : 0.0;
+    const double2 z = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double2 av = (mv && pok[c]) ? sa[c] : z;
+      const double2 bv = qok[c] ? sb[c] : z;
+      lds[buf][0][lrow][lc + 32 * c] = av;
+      lds[buf][1][lrow][lc + 32 * c] = make_double2(w * bv.x, w * bv.y);
+    }
+  };
+  auto contract = [&](int buf) {
+#pragma unroll
+    for (int ks = 0; ks < KTW / 4; ++ks) {
+      double2 av[4], bv[2];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) av[x] = lds[buf][0][ks * 4 + lk][wr * 64 + x * 16 + li];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bv[y] = lds[buf][1][ks * 4 + lk][wc * 32 + y * 16 + li];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) accR[x][y] = mfma(av[x].x, bv[y].x, accR[x][y]);
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) accI[x][y] = mfma(av[x].x, bv[y].y, accI[x][y]);
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) accR[x][y] = mfma(av[x].y, bv[y].y, accR[x][y]);
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) accI[x][y] = mfma(-av[x].y, bv[y].x, accI[x][y]);
+    }
+  };
+
+  const int nsteps = M > mlo ? (M - mlo + KTW - 1) / KTW : 1;
+  load(mlo);
+  store(0);
+  __syncthreads();
+  for (int s = 0; s + 1 < nsteps; ++s) {
+    const int cur = s & 1;
+    load(mlo + (s + 1) * KTW);
+    __builtin_amdgcn_sched_barrier(0);
+    contract(cur);
+    __builtin_amdgcn_sched_barrier(0);
+    store(cur ^ 1);
+    __syncthreads();
+  }
+  contract((nsteps - 1) & 1);
+
+  double2 *out = (split == 0 ? a.out : a.partial) + (int64_t)p * a.out_stride;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int P = P0 + wr * 64 + x * 16 + lk + 4 * r;
+        const int Q = Q0 + wc * 32 + y * 16 + li;
+        if (P >= N || Q >= N) continue;
+        const double re = accR[x][y][r];
+        const double im = accI[x][y][r];
+        if (diag) {
+          if (P < Q) continue;
+          if (P == Q) {
+            out[(int64_t)P * N + Q] = make_double2(re, 0.0);
+            continue;
+          }
+        }
+        out[(int64_t)P * N + Q] = make_double2(re, im);
+        out[(int64_t)Q * N + P] = make_double2(re, -im);
+      }
+}
+
 // out += partial (the second row split), full matrices: a fixed order, so repeatable
 __global__ __launch_bounds__(256) void split_reduce_kernel(const double2 *partial, int64_t n, double2 *out) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -277,10 +426,31 @@ hipError_t launch_chi0_weights(hipStream_t s, const Chi0Args &a, int32_t npts) {
   return hipGetLastError();
 }
 
-hipError_t launch_chi0_f64(hipStream_t s, const Chi0Args &a, int32_t npts, bool cplx_b, int kt) {
+int chi0_cfg_count() { return 4; }
+int chi0_cfg_tile(int cfg) { return cfg == 3 ? TW : TN; }
+int chi0_cfg_slots_per_cu(int cfg) { return cfg == 3 ? 1 : 2; }
+const char *chi0_cfg_name(int cfg) {
+  static const char *names[4] = {"t64k8", "t64k16", "t64k32", "t128k16"};
+  return (cfg >= 0 && cfg < 4) ? names[cfg] : "?";
+}
+
+hipError_t launch_chi0_f64(hipStream_t s, const Chi0Args &a, int32_t npts, bool cplx_b, int cfg) {
   if (npts <= 0) return hipSuccess;
-  const int T = (a.N + TN - 1) / TN;
   const int ks = a.ksplit > 1 ? 2 : 1;   // split 0 writes a.out, split 1 writes a.partial
+  if (cfg == 3) {
+    const int T = (a.N + TW - 1) / TW;
+    const int64_t nwg = (int64_t)T * (T + 1) / 2 * npts * ks;
+    if (nwg > 0x7fffffff) return hipErrorInvalidValue;
+    if (cplx_b)
+      hipLaunchKernelGGL((chi0_f64_t128_kernel<true>), dim3((unsigned)nwg), dim3(512), 0, s, a, T * (T + 1) / 2, npts);
+    else
+      hipLaunchKernelGGL((chi0_f64_t128_kernel<false>), dim3((unsigned)nwg), dim3(512), 0, s, a, T * (T + 1) / 2, npts);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || ks == 1) return e;
+    return launch_split_add(s, a.partial, (int64_t)npts * a.out_stride, a.out);
+  }
+  const int kt = cfg == 0 ? 8 : cfg == 2 ? 32 : 16;
+  const int T = (a.N + TN - 1) / TN;
   const dim3 grid((unsigned)(T * (T + 1) / 2), (unsigned)npts, (unsigned)ks);
 #define RPA_CHI0_LAUNCH(C, K) hipLaunchKernelGGL((chi0_f64_kernel<C, K>), grid, dim3(256), 0, s, a)
   if (kt == 8) {

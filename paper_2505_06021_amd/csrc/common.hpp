@@ -57,9 +57,15 @@ hipError_t launch_philox_words(hipStream_t s, uint64_t seed, int32_t nk, int32_t
 
 // Fill a.wtab for the npts points of a launch (must precede the contraction launch).
 hipError_t launch_chi0_weights(hipStream_t s, const Chi0Args &a, int32_t npts);
-// kt: rows per K step (8, 16 or 32).  With a.ksplit == 2 the launch also adds the second
-// half's result into a.out (fixed order, repeatable).
-hipError_t launch_chi0_f64(hipStream_t s, const Chi0Args &a, int32_t npts, bool cplx_b, int kt);
+// cfg selects the tile and K step: 0, 1, 2 = 64-wide tiles with 8, 16, 32-row steps,
+// 3 = 128-wide tiles with 16-row steps (all give the same sums in the same row order).
+// With a.ksplit == 2 the launch also adds the second half's result into a.out (fixed
+// order, repeatable).
+hipError_t launch_chi0_f64(hipStream_t s, const Chi0Args &a, int32_t npts, bool cplx_b, int cfg);
+int chi0_cfg_count();
+int chi0_cfg_tile(int cfg);            // output tile edge of a configuration
+int chi0_cfg_slots_per_cu(int cfg);    // workgroups of it that fit on one CU
+const char *chi0_cfg_name(int cfg);
 // Number of row splits (1 or 2) that best fills `slots` concurrent workgroups for `work` tiles.
 int32_t chi0_pick_ksplit(int64_t work, int64_t slots, int64_t M);
 // out[i] += partial[i] for n complex elements.

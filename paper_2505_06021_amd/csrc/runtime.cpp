@@ -459,16 +459,22 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
       ca.wtab = d_w;
       ca.out = (double2 *)d_chi;
       ca.out_stride = nn;
-      {
-        // FP64 and FP32 contraction kernels keep two workgroups per CU, split-BF16 one
-        const int64_t T = (N + 63) / 64;
-        const int64_t slots = (job.prec == RPA_BF16X3 ? 1LL : 2LL) * ncu;
-        ca.ksplit = chi0_pick_ksplit(T * (T + 1) / 2 * nb, slots, M) >= 2 ? 2 : 1;
-        ca.partial = (double2 *)d_T;
-      }
       ca.nk = hs.nk; ca.nocc = hs.nocc; ca.nvirt = hs.nvirt; ca.N = N; ca.M = M;
+      ca.ksplit = 1;
+      ca.partial = (double2 *)d_T;
+      int cfg = 1;   // FP64 tile configuration (the tuner's choice, made after the weights)
       if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0_AUX));
       RPA_HIP(launch_chi0_weights(st, ca, nb));
+      if (!mixed) RPA_TRY(tune_chi0_cfg(st, ca, nb, cplx, &cfg));
+      {
+        // two-way row split of the contraction when it fills the last round of
+        // workgroups better; the second half's result goes to the T buffer, which is
+        // free until the sandwich
+        const int64_t tn = mixed ? 64 : chi0_cfg_tile(cfg);
+        const int64_t T = (N + tn - 1) / tn;
+        const int64_t slots = (mixed ? 2LL : (int64_t)chi0_cfg_slots_per_cu(cfg)) * ncu;
+        ca.ksplit = chi0_pick_ksplit(T * (T + 1) / 2 * nb, slots, M) >= 2 ? 2 : 1;
+      }
       if (mixed) {
         // exact FP64 diagonal, one pass per B slab over the batch entries that use it
         int i0 = 0;
@@ -516,10 +522,8 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
         }
       } else {
         if (prof) RPA_TRY(ctx.prof_end(st));
-        int kt = 16;
-        RPA_TRY(tune_chi0_kt(st, ca, nb, cplx, &kt));
         if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0));
-        RPA_HIP(launch_chi0_f64(st, ca, nb, cplx, kt));
+        RPA_HIP(launch_chi0_f64(st, ca, nb, cplx, cfg));
       }
       if (prof && !bsplit) RPA_TRY(ctx.prof_end(st));
 

@@ -119,10 +119,11 @@ struct PointJob {
 int run_points(Ctx &ctx, hipStream_t stream, PointJob &job, int64_t mem_budget, bool use_cache);
 
 // Rows per K step of the FP64 chi0 kernel (RPA_CHI0_KT = 8, 16 or 32; default 16).
-// K-step depth (8, 16 or 32 rows) of the FP64 chi0 contraction for this launch shape:
-// fixed by RPA_CHI0_KT, else timed once per shape bucket and cached (tuner.cpp).
-int tune_chi0_kt(hipStream_t st, const Chi0Args &a, int npts, bool cplx, int *kt_out);
-// "bucket depth" lines of the choices made so far; returns the full length.
+// Tile and K-step configuration (launch_chi0_f64's cfg) of the FP64 chi0 contraction for
+// this launch shape: fixed by the environment, else timed once per shape bucket and
+// cached (tuner.cpp).  a.out must hold npts outputs; its contents are overwritten.
+int tune_chi0_cfg(hipStream_t st, const Chi0Args &a, int npts, bool cplx, int *cfg_out);
+// "bucket configuration" lines of the choices made so far; returns the full length.
 int tuned_entries(char *buf, int len);
 // RPA_TRLN_SINGLE=1 selects the one-workgroup-per-matrix Cholesky instead of the blocked one.
 bool trln_single();

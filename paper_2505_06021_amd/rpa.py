@@ -100,7 +100,7 @@ def load():
 
 
 def tuned():
-    """{shape bucket: K-step depth} chosen so far by the chi0 depth tuner of this process."""
+    """{shape bucket: configuration name} chosen so far by the FP64 chi0 tuner of this process."""
     lib = load()
     need = C.c_int32(0)
     lib.rpa_tuned(None, 0, C.byref(need))
@@ -108,8 +108,8 @@ def tuned():
     lib.rpa_tuned(buf, need.value + 1, C.byref(need))
     out = {}
     for line in buf.value.decode().splitlines():
-        key, kt = line.split()
-        out[key] = int(kt)
+        key, cfg = line.split()
+        out[key] = cfg
     return out
 
 

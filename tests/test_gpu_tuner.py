@@ -1,10 +1,10 @@
-"""The K-step depth of the FP64 chi0 contraction changes speed, never results.
+"""The tile configuration of the FP64 chi0 contraction changes speed, never results.
 
-Every depth (8, 16, 32 rows of B per LDS step) runs the same sequence of 4-row MFMA
-steps in the same row order, so with one row split chi0 is bit-for-bit the same for all
-three; each must match the oracle to 1e-12 (Frobenius, relative).  The tuner must record
-one choice per shape bucket, persist it when asked, and leave E within 1e-12 of a run
-at the fixed default depth.
+Every configuration (64-wide tiles with 8, 16, 32 rows of B per LDS step; 128-wide tiles
+with 16) runs the same sequence of 4-row MFMA steps in the same row order, so with one
+row split chi0 is bit-for-bit the same for all; each must match the oracle to 1e-12
+(Frobenius, relative).  The tuner must record one choice per shape bucket, persist it
+when asked, and leave E within 1e-12 of a run at the fixed default configuration.
 """
 import os
 import sys
@@ -35,33 +35,59 @@ def tall_system():
     return inputs.make_system("tall", (2, 2, 1), 8, 150, 150, 3, 41, is_complex=True)
 
 
-def test_chi0_every_depth_identical_and_exact(ctx, monkeypatch):
-    s = tall_system()
+CFGS = ("t64k8", "t64k16", "t64k32", "t128k16")
+
+
+@pytest.mark.parametrize("naux", [150, 257])
+def test_chi0_every_configuration_identical_and_exact(ctx, monkeypatch, naux):
+    # N = 150 and 257: ragged 64- and 128-wide tiles (257 leaves a one-column tile)
+    s = inputs.make_system("tall", (2, 2, 1), 8, 150, naux, 3, 41, is_complex=True)
     ref = orc.chi0(s, 1, s.omega[1])
     got = {}
-    for kt in (8, 16, 32):
-        say(f"chi0 depth {kt}")
-        monkeypatch.setenv("RPA_CHI0_KT", str(kt))
-        got[kt] = ctx.chi0(s, 1, s.omega[1])
-        err = np.linalg.norm(got[kt] - ref) / np.linalg.norm(ref)
-        assert err <= 1e-12, (kt, err)
-    assert np.array_equal(got[8], got[16]) and np.array_equal(got[16], got[32])
+    for cfg in CFGS:
+        say(f"chi0 configuration {cfg} N={naux}")
+        monkeypatch.setenv("RPA_CHI0_CFG", cfg)
+        got[cfg] = ctx.chi0(s, 1, s.omega[1])
+        err = np.linalg.norm(got[cfg] - ref) / np.linalg.norm(ref)
+        assert err <= 1e-12, (cfg, err)
+    for cfg in CFGS[1:]:
+        assert np.array_equal(got[cfg], got[CFGS[0]]), cfg
+
+
+def test_energy_every_configuration_matches_oracle(ctx, monkeypatch):
+    s = inputs.make_system("cfgE", (2, 2, 1), 3, 7, 150, 4, 32, is_complex=True, sigma=0.15)
+    E_ref = orc.energy(s)[0]
+    for cfg in CFGS:
+        say(f"energy configuration {cfg}")
+        monkeypatch.setenv("RPA_CHI0_CFG", cfg)
+        E, _ = ctx.energy(s)
+        assert abs(E - E_ref) <= 1e-10 * abs(E_ref), cfg
+
+
+def test_legacy_depth_variable(ctx, monkeypatch):
+    s = tall_system()
+    monkeypatch.setenv("RPA_CHI0_CFG", "t64k32")
+    a = ctx.chi0(s, 0, s.omega[0])
+    monkeypatch.delenv("RPA_CHI0_CFG")
+    monkeypatch.setenv("RPA_CHI0_KT", "32")
+    b = ctx.chi0(s, 0, s.omega[0])
+    assert np.array_equal(a, b)
 
 
 def test_tuner_records_and_persists_choice(ctx, monkeypatch, tmp_path):
     from paper_2505_06021_amd import rpa
     s = inputs.make_system("tune", (2, 2, 1), 3, 7, 150, 5, 31, is_complex=True, sigma=0.15)
-    monkeypatch.setenv("RPA_CHI0_KT", "16")
-    say("energy at fixed depth")
+    monkeypatch.setenv("RPA_CHI0_CFG", "t64k16")
+    say("energy at the fixed default configuration")
     e_fixed, eps_fixed = ctx.energy(s)
-    monkeypatch.delenv("RPA_CHI0_KT")
+    monkeypatch.delenv("RPA_CHI0_CFG")
     cache = tmp_path / "tune.txt"
     monkeypatch.setenv("RPA_TUNE_CACHE", str(cache))
     say("energy with the tuner")
     e_tuned, eps_tuned = ctx.energy(s)
     choices = rpa.tuned()
     assert choices, "the tuner recorded no choice"
-    assert all(v in (8, 16, 32) for v in choices.values())
+    assert all(v in CFGS for v in choices.values())
     assert any(k.startswith("f64_c_N192_") for k in choices), choices
     assert abs(e_tuned - e_fixed) <= 1e-12 * abs(e_fixed)
     assert np.max(np.abs(eps_tuned - eps_fixed)) <= 1e-12 * np.max(np.abs(eps_fixed))
@@ -69,4 +95,4 @@ def test_tuner_records_and_persists_choice(ctx, monkeypatch, tmp_path):
     assert abs(e_tuned - e_ref) <= 1e-10 * abs(e_ref)
     if cache.exists():   # written when the bucket was tuned in this test's lifetime
         lines = dict(l.split() for l in cache.read_text().splitlines())
-        assert all(int(v) in (8, 16, 32) for v in lines.values())
+        assert all(v in CFGS for v in lines.values())
