@@ -44,7 +44,7 @@ def kernel_source_hash(name):
 
 def traffic_from_profiles(workload, prec):
     """HBM bytes per chi0 launch from committed counter runs, if the kernel is unchanged."""
-    src = {"fp64": "chi0_f64.hip"}.get(prec, "chi0_mixed.hip")
+    src = {"fp64": "chi0_f64.hip", "fp32": "chi0_mixed.hip", "bf16x3": "chi0_bf16.hip"}[prec]
     f = os.path.join(ROOT, "profiles", f"chi0_{prec}_{workload}_traffic.json")
     if not os.path.exists(f) or not os.path.exists(os.path.join(ROOT, "paper_2505_06021_amd", "csrc", src)):
         return None
