@@ -317,7 +317,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   for (size_t g0 = 0; g0 < qs.size(); g0 += gq) max_group_pts = std::max(max_group_pts, pts_of((int)g0, gq));
   const int64_t pbatch = std::min<int64_t>(pb_cap, max_group_pts);
   // points per split-BF16 sub-launch: as many as the rest of the budget holds
-  int64_t rbatch = bsplit ? pbatch : 0;
+  int64_t rbatch = bsplit ? std::min<int64_t>(pbatch, 16) : 0;   // 16: the points one prepare pass serves
   while (rbatch > 1 && pbatch * per_pt + bsplit_bytes(rbatch) > rest) rbatch = rbatch * 3 / 4;
   if (bsplit && rbatch < 1) rbatch = 1;
 

@@ -56,16 +56,28 @@ int64_t Scheduler::footprint(const HostSmall &hs, int nw, rpa_precision prec) {
   const int64_t N = hs.naux;
   const int64_t M = (int64_t)hs.nk * hs.nocc * hs.nvirt;
   const int64_t belem = hs.is_complex ? 16 : 8;
+  const bool bsplit = prec == RPA_BF16X3;
   const int64_t small = (int64_t)(hs.eps_occ.size() + hs.eps_virt.size() + hs.zeta_k.size()) * 8 +
                         (int64_t)hs.kq.size() * 4 + (int64_t)hs.nq * nw * 32 + 4096 +
                         (int64_t)(hs.nq + nw + 1) * 8 +
                         (mixed ? diag_exact_scratch_doubles(M, (int)N, 16) * 8 : 0);
-  // one q staged at a time: FP64 B (and its FP32 copy), V^(1/2), and per point chi0, T,
-  // the weight table and the exact diagonal -- the same sizes run_points() budgets
-  const int64_t per_q = M * N * belem + N * N * 16 + (hs.is_complex ? 0 : N * N * 8) + (mixed ? M * N * 8 : 0);
-  const int64_t per_pt = 2 * N * N * 16 + M * 8 + (mixed ? N * 8 : 0) + 64;
+  // one q staged at a time: FP64 B (and its FP32 copy, or its prepared split-BF16 copy),
+  // V^(1/2), and per point chi0, T, the weight table and the exact diagonal -- the same
+  // sizes run_points() budgets
+  const int64_t prep = bsplit ? bf16_prepared_elems(M, (int)N) * 2 : 0;
+  const int64_t per_q = M * N * belem + N * N * 16 + (hs.is_complex ? 0 : N * N * 8) +
+                        (bsplit ? prep : mixed ? M * N * 8 : 0);
+  const int64_t per_pt = 2 * N * N * 16 + M * 8 + (mixed ? N * 8 : 0) + trln_blocked_scratch_bytes(1) + 64;
+  // split-BF16: prepared right operands and partial tiles of up to four points at a time
+  int64_t split_extra = 0;
+  if (bsplit) {
+    const int r = nw < 4 ? nw : 4;
+    Bf16Plan pl;
+    bf16_plan(M, (int)N, r, 256, 0, &pl);
+    split_extra = r * prep + bf16_partial_elems(pl, r) * 8 + 512;
+  }
   // allocation granularity slack per buffer
-  return small + per_q + (int64_t)nw * per_pt + 24 * 4096;
+  return small + per_q + (int64_t)nw * per_pt + split_extra + 24 * 4096;
 }
 
 void Scheduler::start_locked() {
@@ -134,20 +146,26 @@ int Scheduler::submit(const rpa_system *sys, const rpa_freq *freq, rpa_precision
 }
 
 Scheduler::Job *Scheduler::pick_locked() {
-  int64_t free_now;
-  {
-    std::lock_guard<std::mutex> g(ctx_.mem_mu);
-    int64_t cached = 0;
-    for (auto &kv : ctx_.cache) cached += kv.second.bytes;
-    // synchronous-call caches stay allocated; everything else in use is reserved by jobs
-    free_now = ctx_.hbm_limit - cached - reserved_;
-  }
-  for (auto it = queue_.begin(); it != queue_.end(); ++it) {
-    if ((*it)->need <= free_now) {
-      Job *j = *it;
-      queue_.erase(it);
-      return j;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    int64_t free_now, cached = 0;
+    {
+      std::lock_guard<std::mutex> g(ctx_.mem_mu);
+      for (auto &kv : ctx_.cache) cached += kv.second.bytes;
+      // synchronous-call caches stay allocated; everything else in use is reserved by jobs
+      free_now = ctx_.hbm_limit - cached - reserved_;
     }
+    for (auto it = queue_.begin(); it != queue_.end(); ++it) {
+      if ((*it)->need <= free_now) {
+        Job *j = *it;
+        queue_.erase(it);
+        return j;
+      }
+    }
+    // nothing fits: if the workspace cache of the synchronous calls is in the way and no
+    // synchronous call is running (try_lock never waits), release it and look again
+    if (attempt > 0 || cached == 0 || !ctx_.mu.try_lock()) break;
+    ctx_.free_cache();
+    ctx_.mu.unlock();
   }
   return nullptr;
 }

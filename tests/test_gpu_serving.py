@@ -102,3 +102,27 @@ def test_finalize_with_pending_jobs_returns():
     t0 = time.time()
     ctx.close()          # cancels queued jobs, waits for the running ones
     assert time.time() - t0 < 120
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_workspace_of_synchronous_calls_does_not_block_admission(prec):
+    # a synchronous call leaves its grow-only workspace allocated; a job that only fits
+    # without it must still be admitted (the scheduler releases the idle workspace)
+    from paper_2505_06021_amd import rpa
+    s = small_jobs()[5]
+    with rpa.Context(0) as probe:
+        jid = probe.submit(s, prec=prec)
+        res, _ = probe.poll(jid, timeout_ms=-1, nq=s.nq, nw=s.nw)
+        need = res["hbm_bytes"]
+    limit = int(need * 1.2)
+    say(f"limit {limit} need {need}")
+    with rpa.Context(0, hbm_limit=limit) as ctx:
+        E, _ = ctx.energy(s, prec=prec)
+        jid = ctx.submit(s, prec=prec)
+        t0 = time.time()
+        r = None
+        while r is None:
+            r = ctx.poll(jid, timeout_ms=1000, nq=s.nq, nw=s.nw)
+            assert time.time() - t0 < 60, "job never admitted"
+        res, _ = r
+        assert res["status"] == 0 and res["E"] == E
