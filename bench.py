@@ -151,6 +151,9 @@ def serving(args):
         "serving": {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
                     "max_s": float(lat.max()), "points": int(npts), "span_s": span,
                     "hbm_high_water": st["hbm_high_water"],
+                    "fused_contraction_launches": st.get("fused_launches"),
+                    "fused_sub_batches": st.get("fused_groups"),
+                    "unfused_sub_batches": st.get("solo_groups"),
                     "max_abs_dE_vs_fp64_Ha": float(max(dE)), "max_rel_dE_vs_fp64": float(max(rel)),
                     "fifo_fp64": {"p50_s": float(np.percentile(fifo_lat, 50)),
                                   "p99_s": float(np.percentile(fifo_lat, 99)),

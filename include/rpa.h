@@ -108,6 +108,9 @@ typedef struct {
 typedef struct {
   int64_t hbm_limit, hbm_in_use, hbm_high_water;
   int64_t jobs_submitted, jobs_done, jobs_running, jobs_queued;
+  /* split-BF16 contractions of served jobs: fused launches, the job sub-batches they
+   * carried, and sub-batches large enough to be launched alone */
+  int64_t fused_launches, fused_groups, solo_groups;
 } rpa_stats;
 
 /* Create a context on HIP device `device`.  hbm_limit_bytes caps the device memory the

@@ -156,18 +156,42 @@ __device__ __forceinline__ void copy_panel(const uint4 *src, uint4 *dst, int wav
                                    (__attribute__((address_space(3))) void *)(dst + u), 16, 0, 0);
 }
 
+// A launch holds up to BF16_MAX_GROUPS groups (sub-batches of one or of several jobs of
+// a serving loop); group g owns workgroups [begin[g], begin[g + 1]).
+struct HerkLaunch {
+  int32_t ngroups;
+  int32_t begin[BF16_MAX_GROUPS + 1];
+  HerkArgs g[BF16_MAX_GROUPS];
+};
+
 template <bool CPLX>
-__global__ __launch_bounds__(64 * HWAVES) void herk_bf16x3_kernel(HerkArgs h) {
+__global__ __launch_bounds__(64 * HWAVES) void herk_bf16x3_kernel(HerkLaunch hl) {
   constexpr int NPL = CPLX ? 4 : 2;
   // [buffer][operand][plane][column * 4 + segment], 16-byte units
   __shared__ __attribute__((aligned(16))) uint4 lds[2][2][NPL][HT * 4];
 
   // workgroups go to the 8 XCDs round-robin; give each XCD a contiguous range of the
-  // (tile fastest, then split, then point) order so that its L2 serves shared panels
+  // (group, then tile fastest, then split, then point) order so that its L2 serves
+  // shared panels
   const int G = gridDim.x, hw = blockIdx.x;
   const int per = (G + 7) / 8, tall = G % 8 == 0 ? 8 : G % 8;
   const int xcd = hw % 8, loc = hw / 8;
-  const int lg = xcd < tall ? xcd * per + loc : tall * per + (xcd - tall) * (per - 1) + loc;
+  const int lgg = xcd < tall ? xcd * per + loc : tall * per + (xcd - tall) * (per - 1) + loc;
+  // the group (uniform over the workgroup), selected with constant indices only so the
+  // arguments stay in scalar registers
+  int gi = 0;
+#pragma unroll
+  for (int k = 1; k < BF16_MAX_GROUPS; ++k)
+    if (k < hl.ngroups && lgg >= hl.begin[k]) gi = k;
+  HerkArgs h = hl.g[0];
+  int g0 = hl.begin[0];
+#pragma unroll
+  for (int k = 1; k < BF16_MAX_GROUPS; ++k)
+    if (k == gi) {
+      h = hl.g[k];
+      g0 = hl.begin[k];
+    }
+  const int lg = lgg - g0;
   const int tile = lg % h.ntiles, split = (lg / h.ntiles) % h.nsplit, p = lg / (h.ntiles * h.nsplit);
   int tr, tc;
   tile_of(tile, tr, tc);
@@ -382,28 +406,54 @@ hipError_t launch_bf16_prepare(hipStream_t s, const void *B, bool cplx, int64_t 
   return hipSuccess;
 }
 
+hipError_t launch_bf16_herk_groups(hipStream_t s, const Bf16Group *groups, int ngroups, bool cplx) {
+  if (ngroups <= 0) return hipSuccess;
+  if (ngroups > BF16_MAX_GROUPS) return hipErrorInvalidValue;
+  HerkLaunch hl{};
+  int64_t total = 0;
+  int n = 0;
+  for (int i = 0; i < ngroups; ++i) {
+    const Bf16Group &g = groups[i];
+    if (g.npts <= 0) continue;
+    HerkArgs &h = hl.g[n];
+    h.L = g.L;
+    h.l_stride = g.l_stride;
+    h.R = g.R;
+    h.r_stride = g.r_stride;
+    h.pts = g.pts;
+    h.part = g.part;
+    h.Np = g.pl.Np;
+    h.ntiles = g.pl.ntiles;
+    h.nsplit = g.pl.nsplit;
+    h.kc_per_split = g.pl.kc_per_split;
+    h.nkc = g.pl.nkc;
+    hl.begin[n] = (int32_t)total;
+    total += (int64_t)g.pl.ntiles * g.pl.nsplit * g.npts;
+    if (total > 0x7fffffff) return hipErrorInvalidValue;
+    ++n;
+  }
+  if (n == 0) return hipSuccess;
+  hl.ngroups = n;
+  for (int i = n; i <= BF16_MAX_GROUPS; ++i) hl.begin[i] = (int32_t)total;
+  const dim3 grid((unsigned)total);
+  if (cplx) hipLaunchKernelGGL(herk_bf16x3_kernel<true>, grid, dim3(64 * HWAVES), 0, s, hl);
+  else hipLaunchKernelGGL(herk_bf16x3_kernel<false>, grid, dim3(64 * HWAVES), 0, s, hl);
+  return hipGetLastError();
+}
+
 hipError_t launch_bf16_herk(hipStream_t s, const Bf16Plan &pl, const unsigned short *L, int64_t l_stride,
                             const unsigned short *R, const PointDesc *pts, int npts, bool cplx, float2 *part, int N,
                             int64_t M) {
-  if (npts <= 0) return hipSuccess;
-  HerkArgs h{};
-  h.L = L;
-  h.l_stride = l_stride;
-  h.R = R;
-  h.r_stride = bf16_prepared_elems(M, N);
-  h.pts = pts;
-  h.part = part;
-  h.Np = pl.Np;
-  h.ntiles = pl.ntiles;
-  h.nsplit = pl.nsplit;
-  h.kc_per_split = pl.kc_per_split;
-  h.nkc = pl.nkc;
-  const int64_t nwg = (int64_t)pl.ntiles * pl.nsplit * npts;
-  if (nwg > 0x7fffffff) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)nwg);
-  if (cplx) hipLaunchKernelGGL(herk_bf16x3_kernel<true>, grid, dim3(64 * HWAVES), 0, s, h);
-  else hipLaunchKernelGGL(herk_bf16x3_kernel<false>, grid, dim3(64 * HWAVES), 0, s, h);
-  return hipGetLastError();
+  Bf16Group g{};
+  g.L = L;
+  g.l_stride = l_stride;
+  g.R = R;
+  g.r_stride = bf16_prepared_elems(M, N);
+  g.pts = pts;
+  g.part = part;
+  g.pl = pl;
+  g.npts = npts;
+  return launch_bf16_herk_groups(s, &g, 1, cplx);
 }
 
 hipError_t launch_bf16_reduce(hipStream_t s, const Bf16Plan &pl, const float2 *part, int npts, int N,

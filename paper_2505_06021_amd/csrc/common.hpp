@@ -120,6 +120,21 @@ hipError_t launch_bf16_prepare(hipStream_t s, const void *B, bool cplx, int64_t 
 hipError_t launch_bf16_herk(hipStream_t s, const Bf16Plan &pl, const unsigned short *L, int64_t l_stride,
                             const unsigned short *R, const PointDesc *pts, int npts, bool cplx, float2 *part, int N,
                             int64_t M);
+// One contraction launch's worth of work (a sub-batch of one job) inside a fused launch.
+constexpr int BF16_MAX_GROUPS = 16;
+struct Bf16Group {
+  const unsigned short *L;
+  int64_t l_stride;
+  const unsigned short *R;
+  int64_t r_stride;          // bf16_prepared_elems of the group's shape
+  const PointDesc *pts;
+  float2 *part;
+  Bf16Plan pl;
+  int32_t npts;
+};
+// Up to BF16_MAX_GROUPS groups of any shapes (all complex or all real) in one launch;
+// every group's results are exactly those of launching it alone.
+hipError_t launch_bf16_herk_groups(hipStream_t s, const Bf16Group *groups, int ngroups, bool cplx);
 // chi0 of those points into out (FP64 complex, Hermitian, point p at p * out_stride): the
 // splits summed in FP64 in order, the diagonal from diag[p][P].
 hipError_t launch_bf16_reduce(hipStream_t s, const Bf16Plan &pl, const float2 *part, int npts, int N,

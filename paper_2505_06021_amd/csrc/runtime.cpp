@@ -506,8 +506,16 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
             if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0));
             Bf16Plan pl;
             bf16_plan(M, N, r1 - r0, ncu, bf16_partial_elems(rplan, (int)rbatch), &pl);
-            RPA_HIP(launch_bf16_herk(st, pl, (const unsigned short *)d_B32, prep_bytes / 2, d_R, d_pts + r0, r1 - r0,
-                                     cplx, d_part, N, M));
+            Bf16Group grp{};
+            grp.L = (const unsigned short *)d_B32;
+            grp.l_stride = prep_bytes / 2;
+            grp.R = d_R;
+            grp.r_stride = prep_bytes / 2;
+            grp.pts = d_pts + r0;
+            grp.part = d_part;
+            grp.pl = pl;
+            grp.npts = r1 - r0;
+            RPA_TRY(fused_herk(job.fuser, st, grp, cplx));
             if (prof) RPA_TRY(ctx.prof_end(st));
             if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0_AUX));
             RPA_HIP(launch_bf16_reduce(st, pl, d_part, r1 - r0, N, d_diag + (int64_t)r0 * N,

@@ -101,6 +101,18 @@ PlanSizes plan_sizes(const HostSmall &hs, bool b_on_device_complex, bool b_devic
 // One evaluation job over a list of (q, w) points of one system, used by rpa_energy,
 // rpa_points and the scheduler.  Device memory comes from the context's workspace cache
 // (use_cache, synchronous calls) or from buffers owned by the call.
+// ---- fused split-BF16 contraction launches of concurrent serving jobs (fuser.cpp) ----
+struct Fuser;
+Fuser *fuser_create(int device, int ncu);
+void fuser_destroy(Fuser *f);
+// A job that may post groups registers (+1) when it starts and unregisters (-1) when done.
+void fuser_register(Fuser *f, int delta);
+void fuser_stats(Fuser *f, int64_t *launches, int64_t *fused_groups, int64_t *solo_groups);
+// Launch the contraction group g, whose operands stream st prepares: alone on st if it
+// fills the GPU by itself (or f is null), else fused with the groups other jobs post at
+// about the same time; st waits for the launch either way.
+int fused_herk(Fuser *f, hipStream_t st, const Bf16Group &g, bool cplx);
+
 struct PointJob {
   const rpa_system *sys;     // caller's description (pointers valid during run)
   const HostSmall *hs;
@@ -114,11 +126,11 @@ struct PointJob {
   std::vector<double> qstage;   // host staging of zeta_q and W_j
   double E = 0.0;
   int max_q_group = 0;          // > 0: at most this many q's staged at once
+  Fuser *fuser = nullptr;       // serving: split-BF16 contractions may be fused across jobs
 };
 
 int run_points(Ctx &ctx, hipStream_t stream, PointJob &job, int64_t mem_budget, bool use_cache);
 
-// Rows per K step of the FP64 chi0 kernel (RPA_CHI0_KT = 8, 16 or 32; default 16).
 // Tile and K-step configuration (launch_chi0_f64's cfg) of the FP64 chi0 contraction for
 // this launch shape: fixed by the environment, else timed once per shape bucket and
 // cached (tuner.cpp).  a.out must hold npts outputs; its contents are overwritten.

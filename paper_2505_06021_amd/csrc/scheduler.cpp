@@ -83,6 +83,9 @@ int64_t Scheduler::footprint(const HostSmall &hs, int nw, rpa_precision prec) {
 void Scheduler::start_locked() {
   if (started_) return;
   started_ = true;
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx_.device) != hipSuccess) ncu = 256;
+  fuser_ = fuser_create(ctx_.device, ncu);   // null: every contraction launches alone
   const int n = worker_count();
   for (int w = 0; w < n; ++w) workers_.emplace_back(&Scheduler::worker, this, w);
 }
@@ -204,7 +207,11 @@ void Scheduler::worker(int w) {
       pj.quadrature = true;
       pj.weight = j->weight;
       pj.max_q_group = 1;
+      pj.fuser = fuser_;
+      const bool fusing = j->prec == RPA_BF16X3;
+      if (fusing) fuser_register(fuser_, +1);
       rc = run_points(ctx_, st, pj, j->need, false);
+      if (fusing) fuser_register(fuser_, -1);
       if (rc == RPA_OK) {
         j->E = pj.E;
         j->eps = std::move(pj.eps);
@@ -264,6 +271,7 @@ void Scheduler::fill_stats(rpa_stats *out) {
   out->jobs_done = done_;
   out->jobs_running = running_;
   out->jobs_queued = (int64_t)queue_.size();
+  fuser_stats(fuser_, &out->fused_launches, &out->fused_groups, &out->solo_groups);
 }
 
 void Scheduler::shutdown() {
@@ -283,6 +291,8 @@ void Scheduler::shutdown() {
   cv_done_.notify_all();
   for (auto &t : workers_) t.join();
   workers_.clear();
+  fuser_destroy(fuser_);
+  fuser_ = nullptr;
   std::lock_guard<std::mutex> g(mu_);
   for (auto &kv : jobs_) delete kv.second;
   jobs_.clear();

@@ -52,7 +52,8 @@ class RpaResultC(C.Structure):
 
 class RpaStatsC(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("hbm_limit", "hbm_in_use", "hbm_high_water", "jobs_submitted",
-                                         "jobs_done", "jobs_running", "jobs_queued")]
+                                         "jobs_done", "jobs_running", "jobs_queued", "fused_launches",
+                                         "fused_groups", "solo_groups")]
 
 
 _lib = None

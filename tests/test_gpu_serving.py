@@ -49,6 +49,11 @@ def test_results_alone_equal_results_in_the_mix(prec):
             assert res["npoints"] == s.nq * s.nw
         st = ctx.stats()
         assert st["jobs_done"] == len(jobs) and st["jobs_queued"] == 0 and st["jobs_running"] == 0
+        if prec == 2:
+            # the small jobs' contractions went through the cross-job fuser (and the
+            # results above are bit-identical to the unfused synchronous ones)
+            say(f"fused launches {st['fused_launches']} carrying {st['fused_groups']} sub-batches")
+            assert st["fused_launches"] >= 1 and st["fused_groups"] >= st["fused_launches"]
 
 
 def test_admission_respects_the_hbm_limit():
