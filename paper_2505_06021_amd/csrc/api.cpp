@@ -202,17 +202,29 @@ int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega, rpa_
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c.device) != hipSuccess) ncu = 256;
     Bf16Plan pl;
-    bf16_plan(M, N, 1, ncu, 0, &pl);
+    bf16_plan(M, N, 1, ncu, 0, 128, &pl);   // the larger of the two tiles' partial buffers
     const int64_t pe = bf16_prepared_elems(M, N);
+    const int64_t max_part = bf16_partial_elems(pl, 1);
     RPA_TRY(c.workspace("chi0_bf16_ops", 2 * pe * 2, (void **)&lr));
-    RPA_TRY(c.workspace("chi0_bf16_part", bf16_partial_elems(pl, 1) * 8, (void **)&part));
+    RPA_TRY(c.workspace("chi0_bf16_part", max_part * 8, (void **)&part));
     RPA_TRY(c.workspace("chi0_diag", (int64_t)N * 8, (void **)&dg));
     RPA_TRY(c.workspace("chi0_diag_scratch", diag_exact_scratch_doubles(M, N, 1) * 8, (void **)&scr));
     RPA_HIP(launch_diag_exact(c.stream, B, cplx, M, N, wt, 1, scr, dg));
     RPA_HIP(launch_bf16_prepare(c.stream, B, cplx, M, N, nullptr, 1, lr));
     RPA_HIP(launch_bf16_prepare(c.stream, B, cplx, M, N, wt, 1, lr + pe));
-    RPA_HIP(launch_bf16_herk(c.stream, pl, lr, 0, lr + pe, a.pts, 1, cplx, part, N, M));
-    RPA_HIP(launch_bf16_reduce(c.stream, pl, part, 1, N, dg, out, 0));
+    Bf16Group g{};
+    g.L = lr;
+    g.l_stride = 0;
+    g.R = lr + pe;
+    g.r_stride = pe;
+    g.pts = a.pts;
+    g.part = part;
+    g.npts = 1;
+    int tn = 128;
+    RPA_TRY(tune_bf16_tile(c.stream, g, M, N, ncu, max_part, cplx, &tn));
+    bf16_plan(M, N, 1, ncu, max_part, tn, &g.pl);
+    RPA_HIP(launch_bf16_herk_groups(c.stream, &g, 1, cplx));
+    RPA_HIP(launch_bf16_reduce(c.stream, g.pl, part, 1, N, dg, out, 0));
   } else if (prec != RPA_FP64) {
     float2 *b32;
     double *dg, *scr;

@@ -33,11 +33,12 @@ namespace {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-constexpr int HT = 128;          // output tile edge (one workgroup)
+constexpr int HT = 128;          // column padding of the prepared layout (the largest tile)
 constexpr int HK = 32;           // contraction rows per step (the K of one BF16 MFMA)
 constexpr int PREP_COLS = 64;    // columns per preparation workgroup
 constexpr int PREP_MAXP = 16;    // points per preparation launch
-constexpr int HWAVES = 8;        // waves of a contraction workgroup: 2 x 4, 64 x 32 each
+// a contraction workgroup owns a TW x TW tile (TW = 64 or 128) with TW / 16 waves of
+// (TW / 2) x 32 each: 2 x 2 waves for 64, 2 x 4 for 128
 
 __device__ __forceinline__ void tile_of(int t, int &tr, int &tc) {
   int r = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
@@ -132,7 +133,7 @@ struct HerkArgs {
   const unsigned short *R;   // prepared right operands, one per point of the launch
   int64_t r_stride;
   const PointDesc *pts;
-  float2 *part;              // [npts][nsplit][ntiles][HT * HT]
+  float2 *part;              // [npts][nsplit][ntiles][TW * TW]
   int32_t Np, ntiles, nsplit, kc_per_split;
   int64_t nkc;               // steps in the whole contraction (Mp / 32)
 };
@@ -164,11 +165,13 @@ struct HerkLaunch {
   HerkArgs g[BF16_MAX_GROUPS];
 };
 
-template <bool CPLX>
-__global__ __launch_bounds__(64 * HWAVES) void herk_bf16x3_kernel(HerkLaunch hl) {
+template <bool CPLX, int TW>
+__global__ __launch_bounds__(4 * TW) void herk_bf16x3_kernel(HerkLaunch hl) {
   constexpr int NPL = CPLX ? 4 : 2;
+  constexpr int XB = TW / 32;      // 16-row blocks per wave (wave rows: TW / 2)
+  constexpr int NWC = TW / 32;     // waves across the tile's columns (32 columns each)
   // [buffer][operand][plane][column * 4 + segment], 16-byte units
-  __shared__ __attribute__((aligned(16))) uint4 lds[2][2][NPL][HT * 4];
+  __shared__ __attribute__((aligned(16))) uint4 lds[2][2][NPL][TW * 4];
 
   // workgroups go to the 8 XCDs round-robin; give each XCD a contiguous range of the
   // (group, then tile fastest, then split, then point) order so that its L2 serves
@@ -199,11 +202,11 @@ __global__ __launch_bounds__(64 * HWAVES) void herk_bf16x3_kernel(HerkLaunch hl)
   const int tid = threadIdx.x, lane = tid & 63;
   // wave index as a scalar: the LDS base of a direct-to-LDS load must be wave-uniform
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wr = wave >> 2, wc = wave & 3;     // 64 rows x 32 columns of the tile
+  const int wr = wave / NWC, wc = wave % NWC;   // (TW / 2) rows x 32 columns of the tile
   const int li = lane & 15, lk = lane >> 4;
 
-  const uint4 *Lg = reinterpret_cast<const uint4 *>(h.L + (int64_t)pd.bslot * h.l_stride) + (int64_t)tr * HT * 4;
-  const uint4 *Rg = reinterpret_cast<const uint4 *>(h.R + (int64_t)p * h.r_stride) + (int64_t)tc * HT * 4;
+  const uint4 *Lg = reinterpret_cast<const uint4 *>(h.L + (int64_t)pd.bslot * h.l_stride) + (int64_t)tr * TW * 4;
+  const uint4 *Rg = reinterpret_cast<const uint4 *>(h.R + (int64_t)p * h.r_stride) + (int64_t)tc * TW * 4;
   const int64_t plane_units = (int64_t)h.Np * 4;   // 16-byte units of one plane of one step
   const int64_t kc0 = (int64_t)split * h.kc_per_split;
   const int64_t kc1 = kc0 + h.kc_per_split < h.nkc ? kc0 + h.kc_per_split : h.nkc;
@@ -218,9 +221,9 @@ __global__ __launch_bounds__(64 * HWAVES) void herk_bf16x3_kernel(HerkLaunch hl)
     }
   };
 
-  f4 accR[4][2], accI[4][2];
+  f4 accR[XB][2], accI[XB][2];
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int x = 0; x < XB; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) {
       accR[x][y] = f4{0.f, 0.f, 0.f, 0.f};
@@ -240,10 +243,10 @@ __global__ __launch_bounds__(64 * HWAVES) void herk_bf16x3_kernel(HerkLaunch hl)
 #pragma unroll
       for (int pl = 0; pl < NPL; ++pl) Bv[y][pl] = frag(lds[buf][1][pl], wc * 32 + y * 16 + li);
 #pragma unroll
-    for (int x = 0; x < 4; ++x) {
+    for (int x = 0; x < XB; ++x) {
       bf8 A[NPL];
 #pragma unroll
-      for (int pl = 0; pl < NPL; ++pl) A[pl] = frag(lds[buf][0][pl], wr * 64 + x * 16 + li);
+      for (int pl = 0; pl < NPL; ++pl) A[pl] = frag(lds[buf][0][pl], wr * (TW / 2) + x * 16 + li);
       // Re: Lr Rr (+ Li Ri); each as hi hi + hi lo + lo hi
 #pragma unroll
       for (int y = 0; y < 2; ++y) accR[x][y] = mfma_bf16(A[0], Bv[y][0], accR[x][y]);
@@ -289,38 +292,40 @@ __global__ __launch_bounds__(64 * HWAVES) void herk_bf16x3_kernel(HerkLaunch hl)
     }
   }
 
-  // FP32 tile of this split: row i, column j of the 128 x 128 tile at i * HT + j;
+  // FP32 tile of this split: row i, column j of the TW x TW tile at i * TW + j;
   // accumulator register r of lane (li, lk) holds row 4 lk + r, column li of a block
-  float2 *o = h.part + (((int64_t)p * h.nsplit + split) * h.ntiles + tile) * (HT * HT);
+  float2 *o = h.part + (((int64_t)p * h.nsplit + split) * h.ntiles + tile) * (TW * TW);
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int x = 0; x < XB; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = wr * 64 + x * 16 + 4 * lk + r;
+        const int i = wr * (TW / 2) + x * 16 + 4 * lk + r;
         const int j = wc * 32 + y * 16 + li;
-        o[i * HT + j] = make_float2(accR[x][y][r], CPLX ? accI[x][y][r] : 0.f);
+        o[i * TW + j] = make_float2(accR[x][y][r], CPLX ? accI[x][y][r] : 0.f);
       }
 }
 
 // ------------------------------------------------------------------ reduction
 // chi0[p][P][Q] (lower triangle and mirror, FP64) = sum over the splits, in order, of
 // the FP32 tiles; the diagonal from `diag`.  A workgroup covers a 32 x 32 block of one
-// tile; the mirrored block goes through LDS so both writes are row-contiguous.
-__global__ __launch_bounds__(256) void herk_reduce_kernel(const float2 *part, int nsplit, int ntiles, int N,
+// tile (tw x tw); the mirrored block goes through LDS so both writes are row-contiguous.
+__global__ __launch_bounds__(256) void herk_reduce_kernel(const float2 *part, int nsplit, int ntiles, int tw, int N,
                                                           const double *diag, double2 *out, int64_t out_stride) {
   __shared__ double2 tb[32][33];
   const int tile = blockIdx.x, blk = blockIdx.y, p = blockIdx.z;
   int tr, tc;
   tile_of(tile, tr, tc);
-  const int bi = blk >> 2, bj = blk & 3;   // 32 x 32 block of the 128 x 128 tile
+  const int nb = tw / 32;
+  const int bi = blk / nb, bj = blk % nb;   // 32 x 32 block of the tile
   const bool dtile = tr == tc;
   if (dtile && bj > bi) return;           // strictly upper blocks of a diagonal tile
   const int tid = threadIdx.x;
   const int j = tid & 31;
-  const int64_t tstride = (int64_t)ntiles * HT * HT;
-  const float2 *src = part + ((int64_t)p * nsplit * ntiles + tile) * (HT * HT);
+  const int64_t tsz = (int64_t)tw * tw;
+  const int64_t tstride = (int64_t)ntiles * tsz;
+  const float2 *src = part + ((int64_t)p * nsplit * ntiles + tile) * tsz;
   double2 *dst = out + (int64_t)p * out_stride;
   const double *dg = diag + (int64_t)p * N;
 #pragma unroll
@@ -329,12 +334,12 @@ __global__ __launch_bounds__(256) void herk_reduce_kernel(const float2 *part, in
     const int li = bi * 32 + i, lj = bj * 32 + j;
     double re = 0.0, im = 0.0;
     for (int s = 0; s < nsplit; ++s) {
-      const float2 v = src[s * tstride + li * HT + lj];
+      const float2 v = src[s * tstride + li * tw + lj];
       re += (double)v.x;
       im += (double)v.y;
     }
     tb[i][j] = make_double2(re, im);
-    const int P = tr * HT + li, Q = tc * HT + lj;
+    const int P = tr * tw + li, Q = tc * tw + lj;
     if (P < N && Q < N && (!dtile || P >= Q))
       dst[(int64_t)P * N + Q] = (P == Q) ? make_double2(dg[P], 0.0) : make_double2(re, im);
   }
@@ -343,7 +348,7 @@ __global__ __launch_bounds__(256) void herk_reduce_kernel(const float2 *part, in
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int i = (tid >> 5) + 8 * k;   // row of the mirrored block = column of the source
-    const int Q = tc * HT + bj * 32 + i, P = tr * HT + bi * 32 + j;
+    const int Q = tc * tw + bj * 32 + i, P = tr * tw + bi * 32 + j;
     if (P < N && Q < N && P > Q) {
       const double2 v = tb[j][i];
       dst[(int64_t)Q * N + P] = make_double2(v.x, -v.y);
@@ -359,19 +364,22 @@ int64_t bf16_prepared_elems(int64_t M, int N) {
   return Mp * Np * 4;
 }
 
-void bf16_plan(int64_t M, int N, int npts, int64_t slots, int64_t max_part, Bf16Plan *pl) {
+void bf16_plan(int64_t M, int N, int npts, int64_t slots, int64_t max_part, int tn, Bf16Plan *pl) {
+  pl->tn = tn == 64 ? 64 : HT;
   pl->Np = (N + HT - 1) / HT * HT;
   pl->nkc = (M + HK - 1) / HK;
-  const int T = pl->Np / HT;
+  const int T = (N + pl->tn - 1) / pl->tn;
   pl->ntiles = T * (T + 1) / 2;
+  const int64_t tsz = (int64_t)pl->tn * pl->tn;
   // fewest splits that keep every FP32 sum within BF16_SPLIT_ROWS rows, then more (down
   // to 512 rows a split) while the launch has fewer than two workgroups per slot and the
   // partial tiles stay within max_part elements (0: no limit)
+  const int64_t wg_per_slot = pl->tn == 64 ? 4 : 2;   // 64-wide tiles: two workgroups per CU
   int64_t per = BF16_SPLIT_ROWS / HK;
   int64_t ns = (pl->nkc + per - 1) / per;
-  while ((int64_t)pl->ntiles * npts * ns < 2 * slots && per > 512 / HK) {
+  while ((int64_t)pl->ntiles * npts * ns < wg_per_slot * slots && per > 512 / HK) {
     const int64_t per2 = per / 2, ns2 = (pl->nkc + per2 - 1) / per2;
-    if (max_part > 0 && (int64_t)npts * ns2 * pl->ntiles * HT * HT > max_part) break;
+    if (max_part > 0 && (int64_t)npts * ns2 * pl->ntiles * tsz > max_part) break;
     per = per2;
     ns = ns2;
   }
@@ -380,7 +388,7 @@ void bf16_plan(int64_t M, int N, int npts, int64_t slots, int64_t max_part, Bf16
 }
 
 int64_t bf16_partial_elems(const Bf16Plan &pl, int npts) {
-  return (int64_t)npts * pl.nsplit * pl.ntiles * HT * HT;
+  return (int64_t)npts * pl.nsplit * pl.ntiles * pl.tn * pl.tn;
 }
 
 hipError_t launch_bf16_prepare(hipStream_t s, const void *B, bool cplx, int64_t M, int N, const double *wtab,
@@ -409,6 +417,9 @@ hipError_t launch_bf16_prepare(hipStream_t s, const void *B, bool cplx, int64_t 
 hipError_t launch_bf16_herk_groups(hipStream_t s, const Bf16Group *groups, int ngroups, bool cplx) {
   if (ngroups <= 0) return hipSuccess;
   if (ngroups > BF16_MAX_GROUPS) return hipErrorInvalidValue;
+  const int tn = groups[0].pl.tn;
+  for (int i = 1; i < ngroups; ++i)
+    if (groups[i].pl.tn != tn) return hipErrorInvalidValue;   // one tile size per launch
   HerkLaunch hl{};
   int64_t total = 0;
   int n = 0;
@@ -436,31 +447,22 @@ hipError_t launch_bf16_herk_groups(hipStream_t s, const Bf16Group *groups, int n
   hl.ngroups = n;
   for (int i = n; i <= BF16_MAX_GROUPS; ++i) hl.begin[i] = (int32_t)total;
   const dim3 grid((unsigned)total);
-  if (cplx) hipLaunchKernelGGL(herk_bf16x3_kernel<true>, grid, dim3(64 * HWAVES), 0, s, hl);
-  else hipLaunchKernelGGL(herk_bf16x3_kernel<false>, grid, dim3(64 * HWAVES), 0, s, hl);
+  if (tn == 64) {
+    if (cplx) hipLaunchKernelGGL((herk_bf16x3_kernel<true, 64>), grid, dim3(256), 0, s, hl);
+    else hipLaunchKernelGGL((herk_bf16x3_kernel<false, 64>), grid, dim3(256), 0, s, hl);
+  } else {
+    if (cplx) hipLaunchKernelGGL((herk_bf16x3_kernel<true, 128>), grid, dim3(512), 0, s, hl);
+    else hipLaunchKernelGGL((herk_bf16x3_kernel<false, 128>), grid, dim3(512), 0, s, hl);
+  }
   return hipGetLastError();
-}
-
-hipError_t launch_bf16_herk(hipStream_t s, const Bf16Plan &pl, const unsigned short *L, int64_t l_stride,
-                            const unsigned short *R, const PointDesc *pts, int npts, bool cplx, float2 *part, int N,
-                            int64_t M) {
-  Bf16Group g{};
-  g.L = L;
-  g.l_stride = l_stride;
-  g.R = R;
-  g.r_stride = bf16_prepared_elems(M, N);
-  g.pts = pts;
-  g.part = part;
-  g.pl = pl;
-  g.npts = npts;
-  return launch_bf16_herk_groups(s, &g, 1, cplx);
 }
 
 hipError_t launch_bf16_reduce(hipStream_t s, const Bf16Plan &pl, const float2 *part, int npts, int N,
                               const double *diag, double2 *out, int64_t out_stride) {
   if (npts <= 0) return hipSuccess;
-  hipLaunchKernelGGL(herk_reduce_kernel, dim3((unsigned)pl.ntiles, 16, (unsigned)npts), dim3(256), 0, s, part,
-                     pl.nsplit, pl.ntiles, N, diag, out, out_stride);
+  const int nb = pl.tn / 32;
+  hipLaunchKernelGGL(herk_reduce_kernel, dim3((unsigned)pl.ntiles, (unsigned)(nb * nb), (unsigned)npts), dim3(256), 0,
+                     s, part, pl.nsplit, pl.ntiles, pl.tn, N, diag, out, out_stride);
   return hipGetLastError();
 }
 

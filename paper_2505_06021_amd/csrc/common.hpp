@@ -96,7 +96,8 @@ hipError_t launch_chi0_mixed(hipStream_t s, const Chi0Args &a, int32_t npts, con
 // No FP32 sum of the contraction runs over more rows than this.
 constexpr int64_t BF16_SPLIT_ROWS = 4096;
 struct Bf16Plan {
-  int32_t Np;            // N rounded up to the 128-wide tile
+  int32_t tn;            // output tile edge: 64 or 128
+  int32_t Np;            // N rounded up to 128 (the prepared layout's padding)
   int32_t ntiles;        // tiles on and below the diagonal
   int32_t nsplit;        // row splits
   int32_t kc_per_split;  // 32-row steps per split
@@ -104,23 +105,17 @@ struct Bf16Plan {
 };
 // bf16 elements of one prepared operand (four planes, rows and columns padded).
 int64_t bf16_prepared_elems(int64_t M, int N);
-// Tiles and row splits of a launch of npts points on a device with `slots` CUs, with at
-// most max_part partial-tile elements when max_part > 0 (never fewer splits than needed
-// to bound the FP32 sums).
-void bf16_plan(int64_t M, int N, int npts, int64_t slots, int64_t max_part, Bf16Plan *pl);
+// Tiles (edge tn = 64 or 128) and row splits of a launch of npts points on a device with
+// `slots` CUs, with at most max_part partial-tile elements when max_part > 0 (never
+// fewer splits than needed to bound the FP32 sums).
+void bf16_plan(int64_t M, int N, int npts, int64_t slots, int64_t max_part, int tn, Bf16Plan *pl);
 // float2 elements of the partial-tile buffer of such a launch.
 int64_t bf16_partial_elems(const Bf16Plan &pl, int npts);
 // Prepared operands from an FP64 B slab: wtab == nullptr gives the unscaled left operand
 // (one), else one right operand w_p B per point p < npts, at bf16_prepared_elems apart.
 hipError_t launch_bf16_prepare(hipStream_t s, const void *B, bool cplx, int64_t M, int N, const double *wtab,
                                int npts, unsigned short *out);
-// FP32 partial tiles of the row splits of npts points (left operand of point p at
-// L + pts[p].bslot * l_stride, right operand p at R + p * bf16_prepared_elems) into part,
-// which holds bf16_partial_elems(pl, npts) float2.
-hipError_t launch_bf16_herk(hipStream_t s, const Bf16Plan &pl, const unsigned short *L, int64_t l_stride,
-                            const unsigned short *R, const PointDesc *pts, int npts, bool cplx, float2 *part, int N,
-                            int64_t M);
-// One contraction launch's worth of work (a sub-batch of one job) inside a fused launch.
+// One contraction launch's worth of work (a sub-batch of one job).
 constexpr int BF16_MAX_GROUPS = 16;
 struct Bf16Group {
   const unsigned short *L;
@@ -132,8 +127,11 @@ struct Bf16Group {
   Bf16Plan pl;
   int32_t npts;
 };
-// Up to BF16_MAX_GROUPS groups of any shapes (all complex or all real) in one launch;
-// every group's results are exactly those of launching it alone.
+// FP32 partial tiles of the row splits of every group's points (left operand of point p
+// at L + pts[p].bslot * l_stride, right operand p at R + p * r_stride) into its part
+// buffer (bf16_partial_elems(pl, npts) float2).  Up to BF16_MAX_GROUPS groups of any
+// shapes (all complex or all real, all of one tile edge) in one launch; every group's
+// results are exactly those of launching it alone.
 hipError_t launch_bf16_herk_groups(hipStream_t s, const Bf16Group *groups, int ngroups, bool cplx);
 // chi0 of those points into out (FP64 complex, Hermitian, point p at p * out_stride): the
 // splits summed in FP64 in order, the diagonal from diag[p][P].

@@ -77,8 +77,9 @@ void Fuser::run() {
                                                 (int)items.size() >= BF16_MAX_GROUPS; });
     std::vector<Item *> batch;
     const bool cplx = items.front()->cplx;
+    const int tn = items.front()->g.pl.tn;
     for (auto it = items.begin(); it != items.end() && (int)batch.size() < BF16_MAX_GROUPS;) {
-      if ((*it)->cplx == cplx) {
+      if ((*it)->cplx == cplx && (*it)->g.pl.tn == tn) {
         batch.push_back(*it);
         it = items.erase(it);
       } else {

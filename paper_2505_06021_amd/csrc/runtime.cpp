@@ -275,7 +275,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   auto bsplit_bytes = [&](int64_t r) -> int64_t {
     if (!bsplit || r <= 0) return 0;
     Bf16Plan pl;
-    bf16_plan(M, N, (int)r, ncu, 0, &pl);
+    bf16_plan(M, N, (int)r, ncu, 0, 128, &pl);
     return r * prep_bytes + bf16_partial_elems(pl, (int)r) * 8 + 512;
   };
   const int64_t per_pt = 2 * nn * 16 + M * 8 + (mixed ? (int64_t)N * 8 : 0) + trln_blocked_scratch_bytes(1) + 64;
@@ -346,13 +346,14 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   unsigned short *d_R = nullptr;
   float2 *d_part = nullptr;
   Bf16Plan rplan{};
+  int bf16_tn = 0;   // split-BF16 tile edge, chosen on the first contraction
   if (mixed) {
     ar.plan(gq * b32_slot, (void **)&d_B32);
     ar.plan(pbatch * N * 8, (void **)&d_diag);
     ar.plan(diag_scratch, (void **)&d_dscr);
   }
   if (bsplit) {
-    bf16_plan(M, N, (int)rbatch, ncu, 0, &rplan);
+    bf16_plan(M, N, (int)rbatch, ncu, 0, 128, &rplan);
     ar.plan(rbatch * prep_bytes, (void **)&d_R);
     ar.plan(bf16_partial_elems(rplan, (int)rbatch) * 8, (void **)&d_part);
   }
@@ -502,10 +503,21 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
                                           d_R + (int64_t)(i0 - r0) * (prep_bytes / 2)));
               i0 = i1;
             }
-            if (prof) RPA_TRY(ctx.prof_end(st));
-            if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0));
+            const int64_t max_part = bf16_partial_elems(rplan, (int)rbatch);
+            if (bf16_tn == 0) {
+              // the tile edge of this shape, timed once on the first sub-batch
+              Bf16Group tg{};
+              tg.L = (const unsigned short *)d_B32;
+              tg.l_stride = prep_bytes / 2;
+              tg.R = d_R;
+              tg.r_stride = prep_bytes / 2;
+              tg.pts = d_pts + r0;
+              tg.part = d_part;
+              tg.npts = r1 - r0;
+              RPA_TRY(tune_bf16_tile(st, tg, M, N, ncu, max_part, cplx, &bf16_tn));
+            }
             Bf16Plan pl;
-            bf16_plan(M, N, r1 - r0, ncu, bf16_partial_elems(rplan, (int)rbatch), &pl);
+            bf16_plan(M, N, r1 - r0, ncu, max_part, bf16_tn, &pl);
             Bf16Group grp{};
             grp.L = (const unsigned short *)d_B32;
             grp.l_stride = prep_bytes / 2;
@@ -515,6 +527,8 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
             grp.part = d_part;
             grp.pl = pl;
             grp.npts = r1 - r0;
+            if (prof) RPA_TRY(ctx.prof_end(st));
+            if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0));
             RPA_TRY(fused_herk(job.fuser, st, grp, cplx));
             if (prof) RPA_TRY(ctx.prof_end(st));
             if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0_AUX));

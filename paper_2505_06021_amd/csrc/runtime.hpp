@@ -135,6 +135,11 @@ int run_points(Ctx &ctx, hipStream_t stream, PointJob &job, int64_t mem_budget, 
 // this launch shape: fixed by the environment, else timed once per shape bucket and
 // cached (tuner.cpp).  a.out must hold npts outputs; its contents are overwritten.
 int tune_chi0_cfg(hipStream_t st, const Chi0Args &a, int npts, bool cplx, int *cfg_out);
+// Tile edge (64 or 128) of the split-BF16 contraction of group g (operands prepared on
+// st, g.part large enough for the candidates' truncated launches: at most max_part
+// elements): fixed by RPA_BF16_TILE, else timed once per shape bucket and cached.
+int tune_bf16_tile(hipStream_t st, const Bf16Group &g, int64_t M, int N, int64_t slots, int64_t max_part, bool cplx,
+                   int *tn_out);
 // "bucket configuration" lines of the choices made so far; returns the full length.
 int tuned_entries(char *buf, int len);
 // RPA_TRLN_SINGLE=1 selects the one-workgroup-per-matrix Cholesky instead of the blocked one.

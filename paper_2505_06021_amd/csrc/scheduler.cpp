@@ -73,7 +73,7 @@ int64_t Scheduler::footprint(const HostSmall &hs, int nw, rpa_precision prec) {
   if (bsplit) {
     const int r = nw < 4 ? nw : 4;
     Bf16Plan pl;
-    bf16_plan(M, (int)N, r, 256, 0, &pl);
+    bf16_plan(M, (int)N, r, 256, 0, 128, &pl);
     split_extra = r * prep + bf16_partial_elems(pl, r) * 8 + 512;
   }
   // allocation granularity slack per buffer

@@ -1,4 +1,6 @@
-// Autotuner of the FP64 chi0 contraction's tile shape and K-step depth.
+// Autotuner of the chi0 contractions' tile shapes: the FP64 contraction's tile and
+// K-step depth, and the split-BF16 contraction's tile edge (64 or 128; RPA_BF16_TILE
+// fixes it).
 //
 // Candidates (launch_chi0_f64 configurations): 64-wide tiles with 8, 16 or 32 rows per
 // LDS step (two workgroups per CU) and 128-wide tiles with 16-row steps (one per CU).
@@ -45,16 +47,25 @@ void load_cache_locked() {
   std::ifstream f(p);
   std::string key, name;
   while (f >> key >> name) {
+    if (key.compare(0, 5, "bf16_") == 0) {
+      if (name == "t64" || name == "t128") g_tuned[key] = name == "t64" ? 64 : 128;
+      continue;
+    }
     const int c = cfg_by_name(name);
     if (c >= 0) g_tuned[key] = c;
   }
+}
+
+std::string entry_name(const std::string &key, int v) {
+  if (key.compare(0, 5, "bf16_") == 0) return v == 64 ? "t64" : "t128";
+  return chi0_cfg_name(v);
 }
 
 void store_cache_locked() {
   const char *p = getenv("RPA_TUNE_CACHE");
   if (!p) return;
   std::ofstream f(p, std::ios::trunc);
-  for (auto &kv : g_tuned) f << kv.first << " " << chi0_cfg_name(kv.second) << "\n";
+  for (auto &kv : g_tuned) f << kv.first << " " << entry_name(kv.first, kv.second) << "\n";
 }
 
 std::string bucket(const Chi0Args &a, int npts, bool cplx) {
@@ -130,10 +141,73 @@ int tune_chi0_cfg(hipStream_t st, const Chi0Args &a, int npts, bool cplx, int *c
   return RPA_OK;
 }
 
+int tune_bf16_tile(hipStream_t st, const Bf16Group &g, int64_t M, int N, int64_t slots, int64_t max_part, bool cplx,
+                   int *tn_out) {
+  if (const char *e = getenv("RPA_BF16_TILE")) {
+    const int v = atoi(e);
+    if (v == 64 || v == 128) {
+      *tn_out = v;
+      return RPA_OK;
+    }
+  }
+  if (const char *t = getenv("RPA_TUNE"))
+    if (t[0] == '0') {
+      *tn_out = 128;
+      return RPA_OK;
+    }
+  int mlog = 0;
+  for (int64_t m = M; m > 1; m >>= 1) ++mlog;
+  std::ostringstream k;
+  k << "bf16_" << (cplx ? "c" : "r") << "_N" << ((N + 63) / 64) * 64 << "_p" << (g.npts > 512 ? 512 : g.npts) << "_m"
+    << mlog;
+  const std::string key = k.str();
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  load_cache_locked();
+  auto it = g_tuned.find(key);
+  if (it != g_tuned.end()) {
+    *tn_out = it->second;
+    return RPA_OK;
+  }
+  // time both tile edges on the first 4096 rows as one split, into the group's partial
+  // buffer (which the real launch overwrites wherever the reduction reads)
+  const int cands[2] = {128, 64};
+  float best_ms = 1e30f;
+  int best = 128;
+  hipEvent_t e0, e1;
+  RPA_HIP(hipEventCreate(&e0));
+  RPA_HIP(hipEventCreate(&e1));
+  for (int rep = 0; rep < 2; ++rep) {
+    for (int tn : cands) {
+      Bf16Group t = g;
+      bf16_plan(M, N, g.npts, slots, max_part, tn, &t.pl);
+      t.pl.nkc = t.pl.nkc < 128 ? t.pl.nkc : 128;
+      t.pl.nsplit = 1;
+      t.pl.kc_per_split = (int)t.pl.nkc;
+      if (max_part > 0 && bf16_partial_elems(t.pl, g.npts) > max_part) continue;
+      RPA_HIP(hipEventRecord(e0, st));
+      RPA_HIP(launch_bf16_herk_groups(st, &t, 1, cplx));
+      RPA_HIP(hipEventRecord(e1, st));
+      RPA_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      RPA_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (rep == 1 && ms < best_ms) {
+        best_ms = ms;
+        best = tn;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  g_tuned[key] = best;
+  store_cache_locked();
+  *tn_out = best;
+  return RPA_OK;
+}
+
 int tuned_entries(char *buf, int len) {
   std::lock_guard<std::mutex> g(g_tune_mu);
   std::string s;
-  for (auto &kv : g_tuned) s += kv.first + " " + chi0_cfg_name(kv.second) + "\n";
+  for (auto &kv : g_tuned) s += kv.first + " " + entry_name(kv.first, kv.second) + "\n";
   if (buf && len > 0) {
     strncpy(buf, s.c_str(), (size_t)len - 1);
     buf[len - 1] = 0;

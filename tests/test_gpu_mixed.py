@@ -99,13 +99,15 @@ def test_mixed_is_deterministic(ctx):
 
 # ------------------------------------------------ split-BF16 from prepared operands
 
+@pytest.mark.parametrize("tile", ["64", "128"])
 @pytest.mark.parametrize("naux,nocc,nvirt", [(1, 2, 5), (127, 3, 7), (128, 4, 9), (129, 3, 7), (256, 8, 150)])
-def test_chi0_bf16x3_tile_and_split_edges(ctx, naux, nocc, nvirt):
-    # 128-wide output tiles and 32-row steps with ragged tails; (8, 150) on a 2x2x1 grid
-    # gives M = 4800 rows, more than one 4096-row split
+def test_chi0_bf16x3_tile_and_split_edges(ctx, monkeypatch, naux, nocc, nvirt, tile):
+    # 64- and 128-wide output tiles and 32-row steps with ragged tails; (8, 150) on a
+    # 2x2x1 grid gives M = 4800 rows, more than one 4096-row split
+    monkeypatch.setenv("RPA_BF16_TILE", tile)
     s = inputs.make_system(f"edge{naux}", (2, 2, 1), nocc, nvirt, naux, 2, 77 + naux, is_complex=True)
     ref = orc.chi0(s, 2, s.omega[1])
-    say(f"chi0 bf16x3 N={naux} M={4 * nocc * nvirt}")
+    say(f"chi0 bf16x3 tile {tile} N={naux} M={4 * nocc * nvirt}")
     got = ctx.chi0(s, 2, s.omega[1], prec=BF16X3)
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     say(f"  rel Frobenius error {err:.3e}")
@@ -136,3 +138,13 @@ def test_energy_bf16x3_sub_launches_under_hbm_limit():
     say(f"  E free {E0:.12f} E tight {E1:.12f}")
     assert abs(E1 - E0) <= TOL_E[BF16X3]
     assert np.max(np.abs(eps1 - eps0)) <= 1e-6 * np.max(np.abs(eps0))
+
+
+def test_bf16x3_tile_edges_agree_bitwise_with_one_split(ctx, monkeypatch):
+    # with one row split both tile edges issue the same MFMA sequence for every element
+    s = inputs.make_system("tiles", (2, 2, 1), 3, 7, 200, 3, 5, is_complex=True)   # M = 84
+    got = {}
+    for tile in ("64", "128"):
+        monkeypatch.setenv("RPA_BF16_TILE", tile)
+        got[tile] = ctx.energy(s, prec=BF16X3)
+    assert got["64"][0] == got["128"][0] and np.array_equal(got["64"][1], got["128"][1])
