@@ -114,6 +114,7 @@ int rpa_finalize(rpa_ctx *ctx) {
     c.free_cache();
   }
   if (c.own_stream) (void)hipStreamDestroy(c.own_stream);
+  if (c.aux) (void)hipStreamDestroy(c.aux);
   delete ctx;
   return RPA_OK;
 }

@@ -87,6 +87,11 @@ int Ctx::workspace(const char *name, int64_t bytes, void **out) {
   return RPA_OK;
 }
 
+hipStream_t Ctx::aux_stream() {
+  if (!aux && hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess) aux = nullptr;
+  return aux;
+}
+
 void Ctx::free_cache() {
   for (auto &kv : cache) release(kv.second);
   cache.clear();
@@ -200,6 +205,14 @@ int validate_system(const rpa_system *sys, HostSmall &hs) {
 }
 
 // ---- the point pipeline -------------------------------------------------------------
+// Lanes of a synchronous call: 1 by default, RPA_LANES=2 for two.  Two lanes measured
+// +1.7% (FP64) and +4.4% (split-BF16) points/s on the 3x3x1 N_aux 384 slab, but their
+// contractions overlap each other, so per-kernel event times no longer isolate a kernel.
+int lanes_wanted() {
+  const char *e = getenv("RPA_LANES");
+  return (e && atoi(e) == 2) ? 2 : 1;
+}
+
 bool trln_single() {
   static bool v = [] {
     const char *e = getenv("RPA_TRLN_SINGLE");
@@ -295,7 +308,10 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
     by_q[q].push_back(p);
   }
 
-  // q-group size and point batch under the budget
+  // q-group size and point batch under the budget.  With two lanes (RPA_LANES=2) a
+  // synchronous call runs its batches alternately on the context's stream and a second
+  // one, with separate batch buffers, so one batch's sandwich and Cholesky overlap the
+  // other's contraction.
   int64_t avail = budget - small;
   int gq = (int)qs.size();
   if (job.max_q_group > 0) gq = std::min(gq, job.max_q_group);
@@ -305,65 +321,100 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
     return c;
   };
   const int64_t one_split = bsplit_bytes(1);
-  while (gq > 1 && gq * (b_slot + vh_slot + b32_slot) + std::min<int64_t>(pts_of(0, gq), 256) * per_pt + one_split >
-                       avail)
-    --gq;
-  const int64_t rest = avail - gq * (b_slot + vh_slot + b32_slot);
-  if (rest < per_pt + one_split)
-    return fail(RPA_E_NOMEM, "one q of this system needs %lld bytes, budget is %lld",
-                (long long)(b_slot + vh_slot + b32_slot + per_pt + one_split + small), (long long)budget);
-  int64_t pb_cap = (rest - one_split) / per_pt;
-  int64_t max_group_pts = 0;
-  for (size_t g0 = 0; g0 < qs.size(); g0 += gq) max_group_pts = std::max(max_group_pts, pts_of((int)g0, gq));
-  const int64_t pbatch = std::min<int64_t>(pb_cap, max_group_pts);
-  // points per split-BF16 sub-launch: as many as the rest of the budget holds
-  int64_t rbatch = bsplit ? std::min<int64_t>(pbatch, 16) : 0;   // 16: the points one prepare pass serves
-  while (rbatch > 1 && pbatch * per_pt + bsplit_bytes(rbatch) > rest) rbatch = rbatch * 3 / 4;
-  if (bsplit && rbatch < 1) rbatch = 1;
+  int nlanes = (use_cache && lanes_wanted() > 1 && npts >= 8) ? 2 : 1;
+  hipStream_t lane_st[2] = {st, nullptr};
+  if (nlanes == 2) {
+    lane_st[1] = ctx.aux_stream();
+    if (!lane_st[1]) nlanes = 1;
+  }
+  int64_t rest = 0, pbatch = 0, rbatch = 0;
+  for (;;) {
+    const int64_t lane_min = nlanes * (per_pt + one_split);
+    gq = (int)qs.size();
+    if (job.max_q_group > 0) gq = std::min(gq, job.max_q_group);
+    while (gq > 1 && gq * (b_slot + vh_slot + b32_slot) + nlanes * std::min<int64_t>(pts_of(0, gq), 256) * per_pt +
+                         nlanes * one_split > avail)
+      --gq;
+    rest = avail - gq * (b_slot + vh_slot + b32_slot);
+    if (rest < lane_min && nlanes == 2) {
+      nlanes = 1;
+      continue;
+    }
+    if (rest < lane_min)
+      return fail(RPA_E_NOMEM, "one q of this system needs %lld bytes, budget is %lld",
+                  (long long)(b_slot + vh_slot + b32_slot + per_pt + one_split + small), (long long)budget);
+    const int64_t pb_cap = (rest / nlanes - one_split) / per_pt;
+    int64_t max_group_pts = 0;
+    for (size_t g0 = 0; g0 < qs.size(); g0 += gq) max_group_pts = std::max(max_group_pts, pts_of((int)g0, gq));
+    pbatch = std::min<int64_t>(pb_cap, (max_group_pts + nlanes - 1) / nlanes);
+    // points per split-BF16 sub-launch: as many as the rest of the budget holds
+    rbatch = bsplit ? std::min<int64_t>(pbatch, 16) : 0;   // 16: the points one prepare pass serves
+    while (rbatch > 1 && pbatch * per_pt + bsplit_bytes(rbatch) > rest / nlanes) rbatch = rbatch * 3 / 4;
+    if (bsplit && rbatch < 1) rbatch = 1;
+    break;
+  }
 
   Arena ar(ctx, use_cache);
   const bool prof = use_cache && ctx.profile;   // timing only on the synchronous path
   double *d_eo, *d_ev, *d_zk, *d_eps;
-  int32_t *d_kq, *d_info, *d_amap;
-  PointDesc *d_pts;
-  void *d_B = nullptr, *d_vh = nullptr, *d_chi = nullptr, *d_T = nullptr, *d_vstage = nullptr;
+  int32_t *d_kq, *d_info;
+  void *d_B = nullptr, *d_vh = nullptr, *d_vstage = nullptr;
   ar.plan((int64_t)hs.eps_occ.size() * 8, (void **)&d_eo);
   ar.plan((int64_t)hs.eps_virt.size() * 8, (void **)&d_ev);
   ar.plan((int64_t)hs.zeta_k.size() * 8, (void **)&d_zk);
   ar.plan((int64_t)hs.kq.size() * 4, (void **)&d_kq);
   ar.plan(npts * 8, (void **)&d_eps);
   ar.plan(npts * 4, (void **)&d_info);
-  ar.plan(pbatch * (int64_t)sizeof(PointDesc), (void **)&d_pts);
-  ar.plan(3 * pbatch * 4, (void **)&d_amap);
   if (b_slot) ar.plan(gq * b_slot, &d_B);
   if (vh_slot) ar.plan(gq * vh_slot, &d_vh);
   if (vh_slot && !cplx && sys->memspace == RPA_MEM_HOST) ar.plan(nn * 8, &d_vstage);
-  ar.plan(pbatch * nn * 16, &d_chi);
-  double *d_w;
-  ar.plan(pbatch * M * 8, (void **)&d_w);
   float2 *d_B32 = nullptr;
-  double *d_diag = nullptr, *d_dscr = nullptr;
-  unsigned short *d_R = nullptr;
-  float2 *d_part = nullptr;
+  if (mixed) ar.plan(gq * b32_slot, (void **)&d_B32);
   Bf16Plan rplan{};
   int bf16_tn = 0;   // split-BF16 tile edge, chosen on the first contraction
-  if (mixed) {
-    ar.plan(gq * b32_slot, (void **)&d_B32);
-    ar.plan(pbatch * N * 8, (void **)&d_diag);
-    ar.plan(diag_scratch, (void **)&d_dscr);
+  if (bsplit) bf16_plan(M, N, (int)rbatch, ncu, 0, 128, &rplan);
+  // per-lane batch buffers
+  struct LaneBufs {
+    PointDesc *pts = nullptr;
+    int32_t *amap = nullptr;
+    void *chi = nullptr, *T = nullptr, *tscr = nullptr;
+    double *w = nullptr, *diag = nullptr, *dscr = nullptr;
+    unsigned short *R = nullptr;
+    float2 *part = nullptr;
+  } lanes[2];
+  for (int l = 0; l < nlanes; ++l) {
+    LaneBufs &lb = lanes[l];
+    ar.plan(pbatch * (int64_t)sizeof(PointDesc), (void **)&lb.pts);
+    ar.plan(3 * pbatch * 4, (void **)&lb.amap);
+    ar.plan(pbatch * nn * 16, &lb.chi);
+    ar.plan(pbatch * M * 8, (void **)&lb.w);
+    if (mixed) {
+      ar.plan(pbatch * N * 8, (void **)&lb.diag);
+      ar.plan(diag_scratch, (void **)&lb.dscr);
+    }
+    if (bsplit) {
+      ar.plan(rbatch * prep_bytes, (void **)&lb.R);
+      ar.plan(bf16_partial_elems(rplan, (int)rbatch) * 8, (void **)&lb.part);
+    }
+    ar.plan(pbatch * nn * 16, &lb.T);
+    ar.plan(trln_blocked_scratch_bytes((int32_t)pbatch), &lb.tscr);
   }
-  if (bsplit) {
-    bf16_plan(M, N, (int)rbatch, ncu, 0, 128, &rplan);
-    ar.plan(rbatch * prep_bytes, (void **)&d_R);
-    ar.plan(bf16_partial_elems(rplan, (int)rbatch) * 8, (void **)&d_part);
-  }
-  ar.plan(pbatch * nn * 16, &d_T);
-  void *d_tscr;
-  ar.plan(trln_blocked_scratch_bytes((int32_t)pbatch), &d_tscr);
   double *d_qw = nullptr;
   ar.plan((int64_t)(hs.nq + 4097) * 8, (void **)&d_qw);
   RPA_TRY(ar.commit(st));
   const bool single_wg_trln = trln_single();
+  // lane events: staging done (lane 1 waits), lane 1 finished (the caller's stream waits)
+  struct Events {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~Events() {
+      for (hipEvent_t x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } ev;
+  if (nlanes == 2) {
+    RPA_HIP(hipEventCreateWithFlags(&ev.e[0], hipEventDisableTiming));
+    RPA_HIP(hipEventCreateWithFlags(&ev.e[1], hipEventDisableTiming));
+  }
 
   RPA_HIP(hipMemcpyAsync(d_eo, hs.eps_occ.data(), hs.eps_occ.size() * 8, hipMemcpyHostToDevice, st));
   RPA_HIP(hipMemcpyAsync(d_ev, hs.eps_virt.data(), hs.eps_virt.size() * 8, hipMemcpyHostToDevice, st));
@@ -373,9 +424,13 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   // host copies of every batch's descriptors stay alive until the final synchronisation
   std::deque<std::vector<PointDesc>> keep_pts;
   std::deque<std::vector<int32_t>> keep_maps;
+  int64_t batch_no = 0;
   for (size_t g0 = 0; g0 < qs.size(); g0 += (size_t)gq) {
     const int ng = (int)std::min<size_t>((size_t)gq, qs.size() - g0);
-    if (g0 > 0) RPA_HIP(hipStreamSynchronize(st));   // slots are reused by this group
+    if (g0 > 0) {   // slots are reused by this group
+      RPA_HIP(hipStreamSynchronize(st));
+      if (nlanes == 2) RPA_HIP(hipStreamSynchronize(lane_st[1]));
+    }
     // stage B and V^(1/2) of the group's q's into slots
     for (int s = 0; s < ng; ++s) {
       const int q = qs[g0 + s];
@@ -416,7 +471,11 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
         }
       }
     }
-    // the group's points in batches
+    if (nlanes == 2) {
+      RPA_HIP(hipEventRecord(ev.e[0], st));
+      RPA_HIP(hipStreamWaitEvent(lane_st[1], ev.e[0], 0));
+    }
+    // the group's points in batches, alternating between the lanes
     std::vector<int64_t> gp;
     std::vector<int> gslot;
     for (int s = 0; s < ng; ++s)
@@ -424,7 +483,10 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
         gp.push_back(p);
         gslot.push_back(s);
       }
-    for (size_t b0 = 0; b0 < gp.size(); b0 += (size_t)pbatch) {
+    for (size_t b0 = 0; b0 < gp.size(); b0 += (size_t)pbatch, ++batch_no) {
+      const int lane = (int)(batch_no % nlanes);
+      hipStream_t S = lane_st[lane];
+      LaneBufs &lb = lanes[lane];
       const int nb = (int)std::min<size_t>((size_t)pbatch, gp.size() - b0);
       keep_pts.emplace_back(nb);
       keep_maps.emplace_back(3 * (size_t)nb);
@@ -445,9 +507,14 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
         imap[i] = i;
         emap[i] = (int32_t)p;
       }
-      RPA_HIP(hipMemcpyAsync(d_pts, hp.data(), nb * sizeof(PointDesc), hipMemcpyHostToDevice, st));
-      RPA_HIP(hipMemcpyAsync(d_amap, vmap, 3 * (size_t)nb * 4, hipMemcpyHostToDevice, st));
-      const int32_t *d_vmap = d_amap, *d_imap = d_amap + nb, *d_emap = d_amap + 2 * nb;
+      RPA_HIP(hipMemcpyAsync(lb.pts, hp.data(), nb * sizeof(PointDesc), hipMemcpyHostToDevice, S));
+      RPA_HIP(hipMemcpyAsync(lb.amap, vmap, 3 * (size_t)nb * 4, hipMemcpyHostToDevice, S));
+      const int32_t *d_vmap = lb.amap, *d_imap = lb.amap + nb, *d_emap = lb.amap + 2 * nb;
+      double *d_w = lb.w, *d_diag = lb.diag, *d_dscr = lb.dscr;
+      unsigned short *d_R = lb.R;
+      float2 *d_part = lb.part;
+      void *d_chi = lb.chi, *d_T = lb.T, *d_tscr = lb.tscr;
+      PointDesc *d_pts = lb.pts;
 
       Chi0Args ca{};
       ca.B = b_direct ? sys->B : d_B;
@@ -464,17 +531,17 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
       ca.ksplit = 1;
       ca.partial = (double2 *)d_T;
       int cfg = 1;   // FP64 tile configuration (the tuner's choice, made after the weights)
-      if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0_AUX));
-      RPA_HIP(launch_chi0_weights(st, ca, nb));
-      if (!mixed) RPA_TRY(tune_chi0_cfg(st, ca, nb, cplx, &cfg));
+      if (prof) RPA_TRY(ctx.prof_begin(S, RPA_K_CHI0_AUX));
+      RPA_HIP(launch_chi0_weights(S, ca, nb));
+      if (!mixed) RPA_TRY(tune_chi0_cfg(S, ca, nb, cplx, &cfg));
       {
         // two-way row split of the contraction when it fills the last round of
-        // workgroups better; the second half's result goes to the T buffer, which is
-        // free until the sandwich
+        // workgroups better (counting the workgroups of a concurrent lane); the second
+        // half's result goes to the T buffer, which is free until the sandwich
         const int64_t tn = mixed ? 64 : chi0_cfg_tile(cfg);
         const int64_t T = (N + tn - 1) / tn;
         const int64_t slots = (mixed ? 2LL : (int64_t)chi0_cfg_slots_per_cu(cfg)) * ncu;
-        ca.ksplit = chi0_pick_ksplit(T * (T + 1) / 2 * nb, slots, M) >= 2 ? 2 : 1;
+        ca.ksplit = chi0_pick_ksplit(T * (T + 1) / 2 * nb * nlanes, slots, M) >= 2 ? 2 : 1;
       }
       if (mixed) {
         // exact FP64 diagonal, one pass per B slab over the batch entries that use it
@@ -484,7 +551,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
           while (i1 < nb && hp[i1].bslot == hp[i0].bslot) ++i1;
           const int64_t slab = b_direct ? job.pq[(size_t)gp[b0 + i0]] : hp[i0].bslot;
           const char *bsrc = (const char *)(b_direct ? sys->B : d_B) + slab * M * N * belem;
-          RPA_HIP(launch_diag_exact(st, bsrc, cplx, M, N, d_w + (int64_t)i0 * M, i1 - i0, d_dscr,
+          RPA_HIP(launch_diag_exact(S, bsrc, cplx, M, N, d_w + (int64_t)i0 * M, i1 - i0, d_dscr,
                                     d_diag + (int64_t)i0 * N));
           i0 = i1;
         }
@@ -499,7 +566,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
               while (i1 < r1 && hp[i1].bslot == hp[i0].bslot) ++i1;
               const int64_t slab = b_direct ? job.pq[(size_t)gp[b0 + i0]] : hp[i0].bslot;
               const char *bsrc = (const char *)(b_direct ? sys->B : d_B) + slab * M * N * belem;
-              RPA_HIP(launch_bf16_prepare(st, bsrc, cplx, M, N, d_w + (int64_t)i0 * M, i1 - i0,
+              RPA_HIP(launch_bf16_prepare(S, bsrc, cplx, M, N, d_w + (int64_t)i0 * M, i1 - i0,
                                           d_R + (int64_t)(i0 - r0) * (prep_bytes / 2)));
               i0 = i1;
             }
@@ -514,7 +581,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
               tg.pts = d_pts + r0;
               tg.part = d_part;
               tg.npts = r1 - r0;
-              RPA_TRY(tune_bf16_tile(st, tg, M, N, ncu, max_part, cplx, &bf16_tn));
+              RPA_TRY(tune_bf16_tile(S, tg, M, N, ncu, max_part, cplx, &bf16_tn));
             }
             Bf16Plan pl;
             bf16_plan(M, N, r1 - r0, ncu, max_part, bf16_tn, &pl);
@@ -527,50 +594,54 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
             grp.part = d_part;
             grp.pl = pl;
             grp.npts = r1 - r0;
-            if (prof) RPA_TRY(ctx.prof_end(st));
-            if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0));
-            RPA_TRY(fused_herk(job.fuser, st, grp, cplx));
-            if (prof) RPA_TRY(ctx.prof_end(st));
-            if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0_AUX));
-            RPA_HIP(launch_bf16_reduce(st, pl, d_part, r1 - r0, N, d_diag + (int64_t)r0 * N,
+            if (prof) RPA_TRY(ctx.prof_end(S));
+            if (prof) RPA_TRY(ctx.prof_begin(S, RPA_K_CHI0));
+            RPA_TRY(fused_herk(job.fuser, S, grp, cplx));
+            if (prof) RPA_TRY(ctx.prof_end(S));
+            if (prof) RPA_TRY(ctx.prof_begin(S, RPA_K_CHI0_AUX));
+            RPA_HIP(launch_bf16_reduce(S, pl, d_part, r1 - r0, N, d_diag + (int64_t)r0 * N,
                                        (double2 *)d_chi + (int64_t)r0 * nn, nn));
-            if (prof) RPA_TRY(ctx.prof_end(st));
-            if (prof && r1 < nb) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0_AUX));
+            if (prof) RPA_TRY(ctx.prof_end(S));
+            if (prof && r1 < nb) RPA_TRY(ctx.prof_begin(S, RPA_K_CHI0_AUX));
           }
         } else {
-          if (prof) RPA_TRY(ctx.prof_end(st));
-          if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0));
-          RPA_HIP(launch_chi0_mixed(st, ca, nb, d_B32, d_diag, (int)job.prec));
+          if (prof) RPA_TRY(ctx.prof_end(S));
+          if (prof) RPA_TRY(ctx.prof_begin(S, RPA_K_CHI0));
+          RPA_HIP(launch_chi0_mixed(S, ca, nb, d_B32, d_diag, (int)job.prec));
         }
       } else {
-        if (prof) RPA_TRY(ctx.prof_end(st));
-        if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0));
-        RPA_HIP(launch_chi0_f64(st, ca, nb, cplx, cfg));
+        if (prof) RPA_TRY(ctx.prof_end(S));
+        if (prof) RPA_TRY(ctx.prof_begin(S, RPA_K_CHI0));
+        RPA_HIP(launch_chi0_f64(S, ca, nb, cplx, cfg));
       }
-      if (prof && !bsplit) RPA_TRY(ctx.prof_end(st));
+      if (prof && !bsplit) RPA_TRY(ctx.prof_end(S));
 
       const double2 *vh = vh_direct ? (const double2 *)sys->vhalf : (const double2 *)d_vh;
       GemmArgs g1{};   // T = chi0 V^(1/2)
       g1.A = (const double2 *)d_chi; g1.a_stride = nn; g1.a_map = d_imap; g1.a_div = 1;
       g1.B = vh; g1.b_stride = nn; g1.b_map = d_vmap; g1.b_div = 1;
       g1.C = (double2 *)d_T; g1.c_stride = nn; g1.N = N; g1.lower_only = 0;
-      if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_PI));
-      RPA_HIP(launch_zgemm_f64(st, g1, nb));
+      if (prof) RPA_TRY(ctx.prof_begin(S, RPA_K_PI));
+      RPA_HIP(launch_zgemm_f64(S, g1, nb));
       GemmArgs g2{};   // Pi = V^(1/2) T, lower triangle, into the chi0 buffer
       g2.A = vh; g2.a_stride = nn; g2.a_map = d_vmap; g2.a_div = 1;
       g2.B = (const double2 *)d_T; g2.b_stride = nn; g2.b_map = d_imap; g2.b_div = 1;
       g2.C = (double2 *)d_chi; g2.c_stride = nn; g2.N = N; g2.lower_only = 1;
       g2.negate = single_wg_trln ? 0 : 1;   // the blocked factorisation takes W = -Pi
-      RPA_HIP(launch_zgemm_f64(st, g2, nb));
-      if (prof) RPA_TRY(ctx.prof_end(st));
-      if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_TRLN));
+      RPA_HIP(launch_zgemm_f64(S, g2, nb));
+      if (prof) RPA_TRY(ctx.prof_end(S));
+      if (prof) RPA_TRY(ctx.prof_begin(S, RPA_K_TRLN));
       if (single_wg_trln) {
-        RPA_HIP(launch_trln_f64(st, (double2 *)d_chi, nn, N, nb, d_eps, d_info, d_emap));
+        RPA_HIP(launch_trln_f64(S, (double2 *)d_chi, nn, N, nb, d_eps, d_info, d_emap));
       } else {
-        RPA_HIP(launch_trln_blocked(st, (double2 *)d_chi, nn, N, nb, d_eps, d_info, d_emap, d_tscr));
+        RPA_HIP(launch_trln_blocked(S, (double2 *)d_chi, nn, N, nb, d_eps, d_info, d_emap, d_tscr));
       }
-      if (prof) RPA_TRY(ctx.prof_end(st));
+      if (prof) RPA_TRY(ctx.prof_end(S));
     }
+  }
+  if (nlanes == 2) {   // everything after this point runs on the caller's stream
+    RPA_HIP(hipEventRecord(ev.e[1], lane_st[1]));
+    RPA_HIP(hipStreamWaitEvent(st, ev.e[1], 0));
   }
   if (job.quadrature) {
     // E = sum_q zeta_q sum_j W_j eps(q, w_j) / (2 pi) over the full q-major grid, on the device

@@ -71,6 +71,10 @@ struct Ctx {
   // After the stream has been synchronised: fold pending event pairs into the totals.
   int prof_collect();
 
+  // second stream of synchronous calls (created on first use; null if that fails)
+  hipStream_t aux_stream();
+  hipStream_t aux = nullptr;
+
   int alloc(DevBuf &b, int64_t bytes, const char *what);
   void release(DevBuf &b);
   // Cached workspace of at least `bytes` (device), reused across synchronous calls.

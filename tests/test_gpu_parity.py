@@ -272,3 +272,19 @@ def test_hbm_limit_is_enforced():
         with pytest.raises(rpa.RpaError) as e:
             c.energy(s)
         assert e.value.code == rpa.RPA_E_NOMEM
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_energy_two_lanes(ctx, monkeypatch, prec):
+    # RPA_LANES=2 runs alternate batches on a second stream with their own buffers
+    say(f"energy on two lanes prec={prec}")
+    s = inputs.slab_3x3_384()
+    E1, eps1 = ctx.energy(s, prec=prec)
+    monkeypatch.setenv("RPA_LANES", "2")
+    E2, eps2 = ctx.energy(s, prec=prec)
+    tol = 1e-10 if prec == 0 else 2e-5
+    assert abs(E2 - E1) <= tol * (abs(E1) if prec == 0 else 1.0)
+    assert np.max(np.abs(eps2 - eps1)) <= (1e-10 if prec == 0 else 1e-6) * np.max(np.abs(eps1))
+    if prec == 0:
+        g = json.load(open(os.path.join(GOLD, "slab3x3_naux384.json")))
+        assert abs(E2 - g["E"]) <= 1e-10 * abs(g["E"])
