@@ -147,6 +147,42 @@ __device__ __forceinline__ void contract(const double2 (*la)[LDP], const double2
   }
 }
 
+// The same K step for the waves of a diagonal tile, where only the blocks in the 4-bit
+// mask `on` (bit 2x + y) are computed.  The mask is uniform over the wave.
+template <int KT>
+__device__ __forceinline__ void contract_masked(const double2 (*la)[LDP], const double2 (*lb)[LDP], int wr,
+                                                int wc, int li, int lk, int on, d4 (&accR)[2][2],
+                                                d4 (&accI)[2][2]) {
+#pragma unroll
+  for (int ks = 0; ks < KT / 4; ++ks) {
+    double2 av[2], bv[2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) av[x] = la[ks * 4 + lk][wr * 32 + x * 16 + li];
+#pragma unroll
+    for (int y = 0; y < 2; ++y) bv[y] = lb[ks * 4 + lk][wc * 32 + y * 16 + li];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+        if (on & (1 << (2 * x + y))) accR[x][y] = mfma(av[x].x, bv[y].x, accR[x][y]);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+        if (on & (1 << (2 * x + y))) accI[x][y] = mfma(av[x].x, bv[y].y, accI[x][y]);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+        if (on & (1 << (2 * x + y))) accR[x][y] = mfma(av[x].y, bv[y].y, accR[x][y]);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+        if (on & (1 << (2 * x + y))) accI[x][y] = mfma(-av[x].y, bv[y].x, accI[x][y]);
+  }
+}
+
 template <bool CPLX_B, int KT>
 __global__ __launch_bounds__(256) void chi0_f64_kernel(Chi0Args a) {
   __shared__ double2 lds[2][2][KT][LDP];
@@ -187,8 +223,24 @@ __global__ __launch_bounds__(256) void chi0_f64_kernel(Chi0Args a) {
   }
 
   const int wave = tid >> 6, lane = tid & 63;
-  const int wr = wave >> 1, wc = wave & 1;
+  int wr = wave >> 1, wc = wave & 1;
   const int li = lane & 15, lk = lane >> 4;
+  // Diagonal tiles: the upper 32 x 32 quadrant mirrors the lower one, so its wave (0, 1)
+  // takes the second 16-column half of the lower quadrant from wave (1, 0), and the two
+  // diagonal quadrants skip their strictly upper 16 x 16 block.  The busiest wave then
+  // issues 3 of 4 blocks' products (each block summed exactly as before).
+  int on = 0xf;   // blocks (x, y) of the wave's quadrant it computes: bit 2x + y
+  if (diag) {
+    if (wr == 0 && wc == 1) {
+      wr = 1;
+      wc = 0;
+      on = 0xa;   // y = 1 of the lower quadrant
+    } else if (wr == 1 && wc == 0) {
+      on = 0x5;   // y = 0 of the lower quadrant
+    } else {
+      on = 0xd;   // diagonal quadrant without block (0, 1)
+    }
+  }
 
   d4 accR[2][2], accI[2][2];
 #pragma unroll
@@ -204,17 +256,30 @@ __global__ __launch_bounds__(256) void chi0_f64_kernel(Chi0Args a) {
   load_stage<CPLX_B, NPASS, RPI>(st, bbase, wrow, mlo, lrow, row_active, M, N, pcol, qcol);
   store_stage<KT, NPASS, RPI>(st, lds[0][0], lds[0][1], lrow, lc, row_active, pok, qok);
   __syncthreads();
-  for (int s = 0; s + 1 < nsteps; ++s) {
-    const int cur = s & 1;
-    load_stage<CPLX_B, NPASS, RPI>(st, bbase, wrow, mlo + (s + 1) * KT, lrow, row_active, M, N, pcol, qcol);
-    // keep the next tile's loads issued ahead of the MFMA block (their latency hides under it)
-    __builtin_amdgcn_sched_barrier(0);
-    contract<KT>(lds[cur][0], lds[cur][1], wr, wc, li, lk, accR, accI);
-    __builtin_amdgcn_sched_barrier(0);
-    store_stage<KT, NPASS, RPI>(st, lds[cur ^ 1][0], lds[cur ^ 1][1], lrow, lc, row_active, pok, qok);
-    __syncthreads();
+  if (!diag) {
+    for (int s = 0; s + 1 < nsteps; ++s) {
+      const int cur = s & 1;
+      load_stage<CPLX_B, NPASS, RPI>(st, bbase, wrow, mlo + (s + 1) * KT, lrow, row_active, M, N, pcol, qcol);
+      // keep the next tile's loads issued ahead of the MFMA block (their latency hides under it)
+      __builtin_amdgcn_sched_barrier(0);
+      contract<KT>(lds[cur][0], lds[cur][1], wr, wc, li, lk, accR, accI);
+      __builtin_amdgcn_sched_barrier(0);
+      store_stage<KT, NPASS, RPI>(st, lds[cur ^ 1][0], lds[cur ^ 1][1], lrow, lc, row_active, pok, qok);
+      __syncthreads();
+    }
+    contract<KT>(lds[(nsteps - 1) & 1][0], lds[(nsteps - 1) & 1][1], wr, wc, li, lk, accR, accI);
+  } else {
+    for (int s = 0; s + 1 < nsteps; ++s) {
+      const int cur = s & 1;
+      load_stage<CPLX_B, NPASS, RPI>(st, bbase, wrow, mlo + (s + 1) * KT, lrow, row_active, M, N, pcol, qcol);
+      __builtin_amdgcn_sched_barrier(0);
+      contract_masked<KT>(lds[cur][0], lds[cur][1], wr, wc, li, lk, on, accR, accI);
+      __builtin_amdgcn_sched_barrier(0);
+      store_stage<KT, NPASS, RPI>(st, lds[cur ^ 1][0], lds[cur ^ 1][1], lrow, lc, row_active, pok, qok);
+      __syncthreads();
+    }
+    contract_masked<KT>(lds[(nsteps - 1) & 1][0], lds[(nsteps - 1) & 1][1], wr, wc, li, lk, on, accR, accI);
   }
-  contract<KT>(lds[(nsteps - 1) & 1][0], lds[(nsteps - 1) & 1][1], wr, wc, li, lk, accR, accI);
 
   double2 *out = (blockIdx.z == 0 ? a.out : a.partial) + (int64_t)blockIdx.y * a.out_stride;
 #pragma unroll
@@ -226,7 +291,7 @@ __global__ __launch_bounds__(256) void chi0_f64_kernel(Chi0Args a) {
         // f64 16x16x4 accumulator layout: register r of lane l holds row l/16 + 4 r, column l%16
         const int P = P0 + wr * 32 + x * 16 + lk + 4 * r;
         const int Q = Q0 + wc * 32 + y * 16 + li;
-        if (P >= N || Q >= N) continue;
+        if (P >= N || Q >= N || !(on & (1 << (2 * x + y)))) continue;
         const double re = accR[x][y][r];
         const double im = accI[x][y][r];
         if (diag) {
