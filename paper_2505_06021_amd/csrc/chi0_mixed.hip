@@ -1,21 +1,21 @@
-// chi0(q, i w) with a reduced-precision contraction: FP32 MFMA, or split-BF16
-// (x = hi + lo with hi = bf16(x), lo = bf16(x - hi); products hi*hi + hi*lo + lo*hi) on
-// the BF16 MFMA with FP32 accumulation.  Both keep what the FP64 path keeps in FP64:
+// chi0(q, i w) with the FP32 matrix cores (v_mfma_f32_16x16x4f32), keeping in FP64
+// what the FP64 path keeps in FP64:
 //  - partial sums are flushed from FP32 into FP64 accumulators every FLUSH_ROWS rows, so
 //    FP32 rounding never runs over long chains;
 //  - the diagonal chi0_PP = sum_m w_m |B_mP|^2, a sum of same-signed terms whose rounding
-//    errors do not cancel, is taken from an exact FP64 pass (diag_exact_kernel) instead
-//    of the MFMA result.
+//    errors do not cancel, is taken from an exact FP64 pass (diag_partial/diag_reduce)
+//    instead of the MFMA result.
 // The contraction reads B in FP32 (the device converts the FP64 coefficients once per
-// q), the right operand is scaled by w_m zeta_k in FP32 before it is rounded to the
-// MFMA precision, and the output is FP64 complex like the FP64 path's.
+// q), the right operand is scaled by w_m zeta_k in FP32 at the LDS store, and the output
+// is FP64 complex like the FP64 path's.  (The split-BF16 contraction is chi0_bf16.hip.)
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace rpa {
 namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int TN = 64;
 constexpr int FLUSH_ROWS = 256;
@@ -141,8 +141,24 @@ __global__ __launch_bounds__(256) void chi0_f32_kernel(Chi0Args a, const float2 
     qcol[c] = qok[c] ? Q : 0;
   }
   const int wave = tid >> 6, lane = tid & 63;
-  const int wr = wave >> 1, wc = wave & 1;
+  int wr = wave >> 1, wc = wave & 1;
   const int li = lane & 15, lk = lane >> 4;
+  // Diagonal tiles: the upper 32 x 32 quadrant mirrors the lower one, so its wave (0, 1)
+  // takes the second 16-column half of the lower quadrant from wave (1, 0), and the two
+  // diagonal quadrants skip their strictly upper 16 x 16 block (each block summed
+  // exactly as before); bit 2x + y of `on` marks the blocks a wave computes.
+  int on = 0xf;
+  if (is_diag) {
+    if (wr == 0 && wc == 1) {
+      wr = 1;
+      wc = 0;
+      on = 0xa;
+    } else if (wr == 1 && wc == 0) {
+      on = 0x5;
+    } else {
+      on = 0xd;
+    }
+  }
 
   f4 accR[2][2], accI[2][2];
   double hR[2][2][4], hI[2][2][4];
@@ -188,7 +204,9 @@ __global__ __launch_bounds__(256) void chi0_f32_kernel(Chi0Args a, const float2 
       }
     }
   };
-  auto contract = [&](int buf) {
+  // MASKED: only the blocks marked in `on` (diagonal tiles)
+  auto contract = [&](int buf, auto masked) {
+    constexpr bool MASKED = decltype(masked)::value;
 #pragma unroll
     for (int ks = 0; ks < KT / 4; ++ks) {
       float2 av[2], bv[2];
@@ -199,19 +217,23 @@ __global__ __launch_bounds__(256) void chi0_f32_kernel(Chi0Args a, const float2 
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) accR[x][y] = mfma32(av[x].x, bv[y].x, accR[x][y]);
+        for (int y = 0; y < 2; ++y)
+          if (!MASKED || (on & (1 << (2 * x + y)))) accR[x][y] = mfma32(av[x].x, bv[y].x, accR[x][y]);
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) accI[x][y] = mfma32(av[x].x, bv[y].y, accI[x][y]);
+        for (int y = 0; y < 2; ++y)
+          if (!MASKED || (on & (1 << (2 * x + y)))) accI[x][y] = mfma32(av[x].x, bv[y].y, accI[x][y]);
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) accR[x][y] = mfma32(av[x].y, bv[y].y, accR[x][y]);
+        for (int y = 0; y < 2; ++y)
+          if (!MASKED || (on & (1 << (2 * x + y)))) accR[x][y] = mfma32(av[x].y, bv[y].y, accR[x][y]);
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) accI[x][y] = mfma32(-av[x].y, bv[y].x, accI[x][y]);
+        for (int y = 0; y < 2; ++y)
+          if (!MASKED || (on & (1 << (2 * x + y)))) accI[x][y] = mfma32(-av[x].y, bv[y].x, accI[x][y]);
     }
   };
   auto flush = [&]() {
@@ -231,21 +253,25 @@ __global__ __launch_bounds__(256) void chi0_f32_kernel(Chi0Args a, const float2 
 
   constexpr int FLUSH_STEPS = FLUSH_ROWS / KT;
   const int nsteps = M > mlo ? (M - mlo + KT - 1) / KT : 1;
-  load(mlo);
-  store(0);
-  __syncthreads();
-  for (int s = 0; s + 1 < nsteps; ++s) {
-    const int cur = s & 1;
-    load(mlo + (s + 1) * KT);
-    __builtin_amdgcn_sched_barrier(0);
-    contract(cur);
-    __builtin_amdgcn_sched_barrier(0);
-    if ((s + 1) % FLUSH_STEPS == 0) flush();
-    store(cur ^ 1);
+  auto run = [&](auto masked) {
+    load(mlo);
+    store(0);
     __syncthreads();
-  }
-  contract((nsteps - 1) & 1);
-  flush();
+    for (int s = 0; s + 1 < nsteps; ++s) {
+      const int cur = s & 1;
+      load(mlo + (s + 1) * KT);
+      __builtin_amdgcn_sched_barrier(0);
+      contract(cur, masked);
+      __builtin_amdgcn_sched_barrier(0);
+      if ((s + 1) % FLUSH_STEPS == 0) flush();
+      store(cur ^ 1);
+      __syncthreads();
+    }
+    contract((nsteps - 1) & 1, masked);
+    flush();
+  };
+  if (is_diag) run(std::integral_constant<bool, true>{});
+  else run(std::integral_constant<bool, false>{});
 
   double2 *out = (blockIdx.z == 0 ? a.out : a.partial) + (int64_t)blockIdx.y * a.out_stride;
   const double *dg = diag + (int64_t)blockIdx.y * N;
@@ -259,220 +285,7 @@ __global__ __launch_bounds__(256) void chi0_f32_kernel(Chi0Args a, const float2 
         // f32 16x16 accumulator layout: register r of lane l holds row 4 (l/16) + r, column l%16
         const int P = P0 + wr * 32 + x * 16 + 4 * lk + r;
         const int Q = Q0 + wc * 32 + y * 16 + li;
-        if (P >= N || Q >= N) continue;
-        const double re = hR[x][y][r], im = hI[x][y][r];
-        if (is_diag) {
-          if (P < Q) continue;
-          if (P == Q) {
-            out[(int64_t)P * N + Q] = make_double2(first ? dg[P] : 0.0, 0.0);
-            continue;
-          }
-        }
-        out[(int64_t)P * N + Q] = make_double2(re, im);
-        out[(int64_t)Q * N + P] = make_double2(re, -im);
-      }
-}
-
-// ------------------------------------------------------------------ split-BF16 MFMA
-// LDS holds, per operand, four planes (re hi, re lo, im hi, im lo) of [64 columns][32
-// rows] with the contraction index contiguous, padded to 40 rows so both the 16-byte
-// stores of the staging threads and the 16-byte fragment reads are conflict-free.
-constexpr int KB = 32;          // rows per K step (the k depth of one 16x16x32 MFMA)
-constexpr int KBP = KB + 8;     // padded plane pitch in bf16 elements
-
-__device__ __forceinline__ f4 mfma_bf16(const bf8 &a, const bf8 &b, f4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-__global__ __launch_bounds__(256) void chi0_bf16x3_kernel(Chi0Args a, const float2 *B32, const double *diag) {
-  // [buf][operand][plane][column][row]
-  __shared__ __attribute__((aligned(16))) unsigned short lds[2][2][4][TN][KBP];
-
-  const PointDesc pd = a.pts[blockIdx.y];
-  int tr, tc;
-  tile_of((int)blockIdx.x, tr, tc);
-  const int N = a.N;
-  const int ms = (int)((((a.M + gridDim.z - 1) / gridDim.z) + KB - 1) / KB) * KB;
-  const int mlo = (int)blockIdx.z * ms;
-  const int M = mlo + ms < (int)a.M ? mlo + ms : (int)a.M;
-  const int P0 = tr * TN, Q0 = tc * TN;
-  const bool is_diag = (tr == tc);
-  const int tid = threadIdx.x;
-  // staging: threads 0..127 stage the left panel (columns P0..), 128..255 the right panel
-  // (Q0.., scaled by w); a thread owns columns 2 cp, 2 cp + 1 of its panel and rows
-  // 8 kg .. 8 kg + 7, loaded as one 16-byte complex pair per row
-  const bool right = tid >= 128;
-  const int st_t = tid & 127;
-  const int cp = st_t & 31, kg = st_t >> 5;
-  const double *wrow = a.wtab + (int64_t)blockIdx.y * a.M;
-  const int c0 = (right ? Q0 : P0) + 2 * cp;
-  // columns past N read a clamped valid column; they are never stored in the output
-  const int col_a = c0 < N ? c0 : 0, col_b = c0 + 1 < N ? c0 + 1 : 0;
-  const int wave = tid >> 6, lane = tid & 63;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int li = lane & 15, lk = lane >> 4;
-
-  // Re += ar br + ai bi and Im += ar bi - ai br, with ai br kept in accJ and subtracted at
-  // the FP64 flush (no sign flips of packed operands in the loop)
-  f4 accR[2][2], accI[2][2], accJ[2][2];
-  double hR[2][2][4], hI[2][2][4];
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y) {
-      accR[x][y] = f4{0.f, 0.f, 0.f, 0.f};
-      accI[x][y] = f4{0.f, 0.f, 0.f, 0.f};
-      accJ[x][y] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int r = 0; r < 4; ++r) hR[x][y][r] = hI[x][y][r] = 0.0;
-    }
-
-  // Raw loads only (rows 8 kg .. 8 kg + 7, clamped to valid rows); masking, scaling and
-  // the split happen at the store after the MFMA block.
-  float2 sva[8], svb[8];
-  double sw[8];
-  const float2 *slab = B32 + (int64_t)pd.bslot * a.b_slot_stride;
-  auto load = [&](int m0) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int m = m0 + 8 * kg + e;
-      const int mc = m < M ? m : 0;
-      sw[e] = wrow[mc];                 // used by the right panel only
-      const float2 *row = slab + (int64_t)mc * N;
-      sva[e] = row[col_a];
-      svb[e] = row[col_b];
-    }
-  };
-  // x = hi + lo for two consecutive rows at once: hi = bf16(x) (v_cvt_pk_bf16_f32, round
-  // to nearest even), lo = bf16(x - hi); the packed dwords are already in the MFMA
-  // fragment order (consecutive contraction rows).
-  auto split2 = [](float x0, float x1, unsigned &hi, unsigned &lo) {
-    typedef float f2v __attribute__((ext_vector_type(2)));
-    typedef __bf16 b2v __attribute__((ext_vector_type(2)));
-    f2v x = {x0, x1};
-    hi = __builtin_bit_cast(unsigned, __builtin_convertvector(x, b2v));
-    f2v h = {__builtin_bit_cast(float, hi << 16), __builtin_bit_cast(float, hi & 0xffff0000u)};
-    lo = __builtin_bit_cast(unsigned, __builtin_convertvector(x - h, b2v));
-  };
-  auto store = [&](int buf, int m0) {
-    // Only the scaled (right) operand is masked (w = 0 on rows past the end): a product
-    // with a zero factor vanishes whatever the clamped left operand holds, and columns
-    // past N are never stored.
-    unsigned h[2][2][4], l[2][2][4];   // [column of the pair][re/im][row pair]
-#pragma unroll
-    for (int pr = 0; pr < 4; ++pr) {
-      const int e0 = 2 * pr, e1 = 2 * pr + 1;
-      const float w0 = !right ? 1.f : ((m0 + 8 * kg + e0 < M) ? (float)sw[e0] : 0.f);
-      const float w1 = !right ? 1.f : ((m0 + 8 * kg + e1 < M) ? (float)sw[e1] : 0.f);
-      split2(w0 * sva[e0].x, w1 * sva[e1].x, h[0][0][pr], l[0][0][pr]);
-      split2(w0 * sva[e0].y, w1 * sva[e1].y, h[0][1][pr], l[0][1][pr]);
-      split2(w0 * svb[e0].x, w1 * svb[e1].x, h[1][0][pr], l[1][0][pr]);
-      split2(w0 * svb[e0].y, w1 * svb[e1].y, h[1][1][pr], l[1][1][pr]);
-    }
-    const int op = right ? 1 : 0;
-#pragma unroll
-    for (int cc = 0; cc < 2; ++cc) {
-      const int col = 2 * cp + cc;
-      *reinterpret_cast<uint4 *>(&lds[buf][op][0][col][8 * kg]) = make_uint4(h[cc][0][0], h[cc][0][1], h[cc][0][2], h[cc][0][3]);
-      *reinterpret_cast<uint4 *>(&lds[buf][op][1][col][8 * kg]) = make_uint4(l[cc][0][0], l[cc][0][1], l[cc][0][2], l[cc][0][3]);
-      *reinterpret_cast<uint4 *>(&lds[buf][op][2][col][8 * kg]) = make_uint4(h[cc][1][0], h[cc][1][1], h[cc][1][2], h[cc][1][3]);
-      *reinterpret_cast<uint4 *>(&lds[buf][op][3][col][8 * kg]) = make_uint4(l[cc][1][0], l[cc][1][1], l[cc][1][2], l[cc][1][3]);
-    }
-  };
-  auto contract = [&](int buf) {
-    // fragments: lane l holds 8 consecutive rows 8 (l/16) .. +7 of column l%16 of a block
-    bf8 A[2][4], Bv[2][4];
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int pl = 0; pl < 4; ++pl)
-        A[x][pl] = *reinterpret_cast<const bf8 *>(&lds[buf][0][pl][wr * 32 + x * 16 + li][8 * lk]);
-#pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int pl = 0; pl < 4; ++pl)
-        Bv[y][pl] = *reinterpret_cast<const bf8 *>(&lds[buf][1][pl][wc * 32 + y * 16 + li][8 * lk]);
-    // conj(a) * b: Re += ar br + ai bi, Im += ar bi - ai br; each real product as
-    // hi*hi + hi*lo + lo*hi
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y) {
-        accR[x][y] = mfma_bf16(A[x][0], Bv[y][0], accR[x][y]);
-        accI[x][y] = mfma_bf16(A[x][0], Bv[y][2], accI[x][y]);
-        accJ[x][y] = mfma_bf16(A[x][2], Bv[y][0], accJ[x][y]);
-      }
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y) {
-        accR[x][y] = mfma_bf16(A[x][0], Bv[y][1], accR[x][y]);
-        accI[x][y] = mfma_bf16(A[x][0], Bv[y][3], accI[x][y]);
-        accJ[x][y] = mfma_bf16(A[x][2], Bv[y][1], accJ[x][y]);
-      }
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y) {
-        accR[x][y] = mfma_bf16(A[x][1], Bv[y][0], accR[x][y]);
-        accI[x][y] = mfma_bf16(A[x][1], Bv[y][2], accI[x][y]);
-        accJ[x][y] = mfma_bf16(A[x][3], Bv[y][0], accJ[x][y]);
-      }
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y) {
-        accR[x][y] = mfma_bf16(A[x][2], Bv[y][2], accR[x][y]);
-        accR[x][y] = mfma_bf16(A[x][2], Bv[y][3], accR[x][y]);
-        accR[x][y] = mfma_bf16(A[x][3], Bv[y][2], accR[x][y]);
-      }
-  };
-  auto flush = [&]() {
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          hR[x][y][r] += (double)accR[x][y][r];
-          hI[x][y][r] += (double)accI[x][y][r] - (double)accJ[x][y][r];
-        }
-        accR[x][y] = f4{0.f, 0.f, 0.f, 0.f};
-        accI[x][y] = f4{0.f, 0.f, 0.f, 0.f};
-        accJ[x][y] = f4{0.f, 0.f, 0.f, 0.f};
-      }
-  };
-
-  constexpr int FLUSH_STEPS = FLUSH_ROWS / KB;
-  const int nsteps = M > mlo ? (M - mlo + KB - 1) / KB : 1;
-  load(mlo);
-  store(0, mlo);
-  __syncthreads();
-  for (int s = 0; s + 1 < nsteps; ++s) {
-    const int cur = s & 1;
-    load(mlo + (s + 1) * KB);
-    __builtin_amdgcn_sched_barrier(0);
-    contract(cur);
-    __builtin_amdgcn_sched_barrier(0);
-    if ((s + 1) % FLUSH_STEPS == 0) flush();
-    store(cur ^ 1, mlo + (s + 1) * KB);
-    __syncthreads();
-  }
-  contract((nsteps - 1) & 1);
-  flush();
-
-  double2 *out = (blockIdx.z == 0 ? a.out : a.partial) + (int64_t)blockIdx.y * a.out_stride;
-  const double *dg = diag + (int64_t)blockIdx.y * N;
-  const bool first = blockIdx.z == 0;   // the exact diagonal enters once
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int P = P0 + wr * 32 + x * 16 + 4 * lk + r;
-        const int Q = Q0 + wc * 32 + y * 16 + li;
-        if (P >= N || Q >= N) continue;
+        if (P >= N || Q >= N || !(on & (1 << (2 * x + y)))) continue;
         const double re = hR[x][y][r], im = hI[x][y][r];
         if (is_diag) {
           if (P < Q) continue;
@@ -531,10 +344,8 @@ hipError_t launch_chi0_mixed(hipStream_t s, const Chi0Args &a, int32_t npts, con
   const int T = (a.N + TN - 1) / TN;
   const int ks = a.ksplit > 1 ? 2 : 1;   // split 0 writes a.out, split 1 writes a.partial
   const dim3 grid((unsigned)(T * (T + 1) / 2), (unsigned)npts, (unsigned)ks);
-  if (prec == 1)
-    hipLaunchKernelGGL(chi0_f32_kernel<16>, grid, dim3(256), 0, s, a, B32, diag);
-  else
-    hipLaunchKernelGGL(chi0_bf16x3_kernel, grid, dim3(256), 0, s, a, B32, diag);
+  if (prec != 1) return hipErrorInvalidValue;   // FP32 only; split-BF16 is chi0_bf16.hip
+  hipLaunchKernelGGL(chi0_f32_kernel<16>, grid, dim3(256), 0, s, a, B32, diag);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || ks == 1) return e;
   return launch_split_add(s, a.partial, (int64_t)npts * a.out_stride, a.out);

@@ -168,8 +168,10 @@ int tune_bf16_tile(hipStream_t st, const Bf16Group &g, int64_t M, int N, int64_t
     *tn_out = it->second;
     return RPA_OK;
   }
-  // time both tile edges on the first 4096 rows as one split, into the group's partial
-  // buffer (which the real launch overwrites wherever the reduction reads)
+  // time both tile edges with their real split count (so the launches fill the GPU as the
+  // real ones do) but at most 32 steps (1024 rows) per split, into the group's partial
+  // buffer (which the real launch overwrites wherever the reduction reads); compare time
+  // per contraction step
   const int cands[2] = {128, 64};
   float best_ms = 1e30f;
   int best = 128;
@@ -180,16 +182,20 @@ int tune_bf16_tile(hipStream_t st, const Bf16Group &g, int64_t M, int N, int64_t
     for (int tn : cands) {
       Bf16Group t = g;
       bf16_plan(M, N, g.npts, slots, max_part, tn, &t.pl);
-      t.pl.nkc = t.pl.nkc < 128 ? t.pl.nkc : 128;
-      t.pl.nsplit = 1;
-      t.pl.kc_per_split = (int)t.pl.nkc;
       if (max_part > 0 && bf16_partial_elems(t.pl, g.npts) > max_part) continue;
+      t.pl.kc_per_split = t.pl.kc_per_split < 32 ? t.pl.kc_per_split : 32;
+      const int64_t steps = (int64_t)t.pl.nsplit * t.pl.kc_per_split;
+      t.pl.nkc = t.pl.nkc < steps ? t.pl.nkc : steps;
       RPA_HIP(hipEventRecord(e0, st));
       RPA_HIP(launch_bf16_herk_groups(st, &t, 1, cplx));
       RPA_HIP(hipEventRecord(e1, st));
       RPA_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
       RPA_HIP(hipEventElapsedTime(&ms, e0, e1));
+      ms /= (float)t.pl.nkc;   // the candidates cover different numbers of steps: per step
+      if (rep == 1 && getenv("RPA_TUNE_VERBOSE"))
+        fprintf(stderr, "[tune] %s t%d: %.6f ms per step (%d splits x %d steps, %d tiles)\n", key.c_str(), tn, ms,
+                t.pl.nsplit, t.pl.kc_per_split, t.pl.ntiles);
       if (rep == 1 && ms < best_ms) {
         best_ms = ms;
         best = tn;
