@@ -25,6 +25,8 @@
 // the MFMA fragment reads from LDS free of bank conflicts (the eight lanes served
 // together read eight columns at one segment index: the XOR spreads them over the
 // 128 bytes the LDS delivers per clock).
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace rpa {
@@ -279,22 +281,90 @@ __global__ __launch_bounds__(4 * TW) void herk_bf16x3_kernel(HerkLaunch hl) {
     }
   };
 
-  if (nsteps > 0) {
+  // Diagonal tiles need only the NLB 16 x 16 blocks on or below the diagonal; they are
+  // dealt out in row-major order, a contiguous run of at most MAXB blocks per wave (so a
+  // wave's blocks share few block rows), each summed exactly as in an off-diagonal tile.
+  constexpr int NB16 = TW / 16, NW = TW / 16;
+  constexpr int NLB = NB16 * (NB16 + 1) / 2, MAXB = (NLB + NW - 1) / NW;
+  const int kb0 = wave * NLB / NW, kb1 = (wave + 1) * NLB / NW;
+  int bxs[MAXB], bys[MAXB];
+#pragma unroll
+  for (int j = 0; j < MAXB; ++j) {
+    const int k = kb0 + j < kb1 ? kb0 + j : kb0;
+    int bx = 0;
+    while ((bx + 1) * (bx + 2) / 2 <= k) ++bx;
+    bxs[j] = bx;
+    bys[j] = k - bx * (bx + 1) / 2;
+  }
+  f4 dR[MAXB], dI[MAXB];
+#pragma unroll
+  for (int j = 0; j < MAXB; ++j) {
+    dR[j] = f4{0.f, 0.f, 0.f, 0.f};
+    dI[j] = f4{0.f, 0.f, 0.f, 0.f};
+  }
+  auto contract_diag = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < MAXB; ++j) {
+      if (kb0 + j >= kb1) break;   // uniform over the wave
+      bf8 A[NPL], Bv[NPL];
+#pragma unroll
+      for (int pl = 0; pl < NPL; ++pl) {
+        A[pl] = frag(lds[buf][0][pl], bxs[j] * 16 + li);
+        Bv[pl] = frag(lds[buf][1][pl], bys[j] * 16 + li);
+      }
+      dR[j] = mfma_bf16(A[0], Bv[0], dR[j]);
+      dR[j] = mfma_bf16(A[0], Bv[1], dR[j]);
+      dR[j] = mfma_bf16(A[1], Bv[0], dR[j]);
+      if (CPLX) {
+        const bf8 nh = negate(A[2]), nl = negate(A[3]);
+        dI[j] = mfma_bf16(A[0], Bv[2], dI[j]);
+        dR[j] = mfma_bf16(A[2], Bv[2], dR[j]);
+        dI[j] = mfma_bf16(A[0], Bv[3], dI[j]);
+        dR[j] = mfma_bf16(A[2], Bv[3], dR[j]);
+        dI[j] = mfma_bf16(A[1], Bv[2], dI[j]);
+        dR[j] = mfma_bf16(A[3], Bv[2], dR[j]);
+        dI[j] = mfma_bf16(nh, Bv[0], dI[j]);
+        dI[j] = mfma_bf16(nh, Bv[1], dI[j]);
+        dI[j] = mfma_bf16(nl, Bv[0], dI[j]);
+      }
+    }
+  };
+  const bool dtile = tr == tc;
+
+  auto run = [&](auto diag_tag) {
+    constexpr bool D = decltype(diag_tag)::value;
+    if (nsteps <= 0) return;
     issue(0, kc0);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     for (int s = 0; s < nsteps; ++s) {
       const int cur = s & 1;
       if (s + 1 < nsteps) issue(cur ^ 1, kc0 + s + 1);
-      contract(cur);
+      if (D) contract_diag(cur);
+      else contract(cur);
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
     }
-  }
+  };
+  if (dtile) run(std::integral_constant<bool, true>{});
+  else run(std::integral_constant<bool, false>{});
 
   // FP32 tile of this split: row i, column j of the TW x TW tile at i * TW + j;
-  // accumulator register r of lane (li, lk) holds row 4 lk + r, column li of a block
+  // accumulator register r of lane (li, lk) holds row 4 lk + r, column li of a block.
+  // Diagonal tiles write only their lower blocks (the reduction reads nothing else).
   float2 *o = h.part + (((int64_t)p * h.nsplit + split) * h.ntiles + tile) * (TW * TW);
+  if (dtile) {
+#pragma unroll
+    for (int j = 0; j < MAXB; ++j) {
+      if (kb0 + j >= kb1) break;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = bxs[j] * 16 + 4 * lk + r, jj = bys[j] * 16 + li;
+        o[i * TW + jj] = make_float2(dR[j][r], CPLX ? dI[j][r] : 0.f);
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int x = 0; x < XB; ++x)
 #pragma unroll
