@@ -182,7 +182,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the (q, w) points shard by q across GPUs, which this build does not do).",
+              "(the (q, w) points would shard by q across GPUs; this library runs on one).",
               file=sys.stderr, flush=True)
         sys.exit(2)
 

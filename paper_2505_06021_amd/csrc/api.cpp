@@ -209,10 +209,9 @@ int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega, rpa_
     RPA_TRY(c.workspace("chi0_bf16_ops", 2 * pe * 2, (void **)&lr));
     RPA_TRY(c.workspace("chi0_bf16_part", max_part * 8, (void **)&part));
     RPA_TRY(c.workspace("chi0_diag", (int64_t)N * 8, (void **)&dg));
-    RPA_TRY(c.workspace("chi0_diag_scratch", diag_exact_scratch_doubles(M, N, 1) * 8, (void **)&scr));
-    RPA_HIP(launch_diag_exact(c.stream, B, cplx, M, N, wt, 1, scr, dg));
+    RPA_TRY(c.workspace("chi0_diag_scratch", bf16_diag_scratch_doubles(M, N) * 8, (void **)&scr));
     RPA_HIP(launch_bf16_prepare(c.stream, B, cplx, M, N, nullptr, 1, lr));
-    RPA_HIP(launch_bf16_prepare(c.stream, B, cplx, M, N, wt, 1, lr + pe));
+    RPA_HIP(launch_bf16_prepare(c.stream, B, cplx, M, N, wt, 1, lr + pe, scr, dg));
     Bf16Group g{};
     g.L = lr;
     g.l_stride = 0;

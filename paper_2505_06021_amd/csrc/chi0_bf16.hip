@@ -66,66 +66,114 @@ __device__ __forceinline__ void split_pair(double x0, double x1, unsigned &hi, u
 }
 
 // ------------------------------------------------------------------ preparation
-// One workgroup: 32 rows (one step) x 64 columns.  B rows are read coalesced into LDS,
-// then thread (c, s) splits rows 8 s .. 8 s + 7 of column c for every point (or once,
-// unscaled, when wtab is null) and writes one 16-byte segment per plane.
+// One workgroup: PREP_STEPS steps of 32 rows x 64 columns.  Each step's B rows are read
+// coalesced into LDS, then thread (c, s) splits rows 8 s .. 8 s + 7 of column c for every
+// point (or once, unscaled, when wtab is null) and writes one 16-byte segment per plane.
+// With dpart set, the workgroup also sums w_m |B_mc|^2 in FP64 over its rows for every
+// point (the exact diagonal of chi0, from the unsplit values it holds anyway): rows in
+// order within a thread, then the four row groups in a fixed order, one partial per
+// (workgroup row chunk, point, column).
+constexpr int PREP_STEPS = 4;
+
 template <bool CPLX>
 __global__ __launch_bounds__(256) void bf16_prepare_kernel(const void *B, int64_t M, int N, int Np,
                                                            const double *wtab, int64_t w_stride, int np,
-                                                           unsigned short *out, int64_t out_stride) {
+                                                           unsigned short *out, int64_t out_stride,
+                                                           double *dpart) {
   __shared__ double2 tb[HK][PREP_COLS + 1];
   __shared__ double wl[PREP_MAXP][HK];
-  const int64_t kc = blockIdx.x;
+  __shared__ double red[4][PREP_MAXP][PREP_COLS];
   const int c0 = blockIdx.y * PREP_COLS;
-  const int64_t m0 = kc * HK;
+  const int64_t nkc = (M + HK - 1) / HK;
   const int tid = threadIdx.x;
-  {
-    const int col = tid & 63, r0 = tid >> 6;
-    const int n = c0 + col;
-#pragma unroll
-    for (int j = 0; j < HK / 4; ++j) {
-      const int r = r0 + 4 * j;
-      const int64_t m = m0 + r;
-      double2 v = make_double2(0.0, 0.0);
-      if (m < M && n < N) {
-        if (CPLX) v = reinterpret_cast<const double2 *>(B)[m * N + n];
-        else v.x = reinterpret_cast<const double *>(B)[m * N + n];
-      }
-      tb[r][col] = v;
-    }
-    if (wtab) {
-      for (int e = tid; e < np * HK; e += 256) {
-        const int p = e / HK, r = e % HK;
-        wl[p][r] = (m0 + r < M) ? wtab[(int64_t)p * w_stride + m0 + r] : 0.0;
-      }
-    }
-  }
-  __syncthreads();
   const int c = tid >> 2, s = tid & 3;
   const int n = c0 + c;
-  double2 v[8];
-#pragma unroll
-  for (int e = 0; e < 8; ++e) v[e] = tb[8 * s + e][c];
   const int64_t unit = seg_pos(s, n);   // 16-byte segment within the column's 64 bytes
   const int reps = wtab ? np : 1;
-  for (int p = 0; p < reps; ++p) {
-    unsigned hr[4], lr[4], hi_[4], li_[4];
+  double dsum[PREP_MAXP];
 #pragma unroll
-    for (int e2 = 0; e2 < 4; ++e2) {
-      const double w0 = wtab ? wl[p][8 * s + 2 * e2] : 1.0;
-      const double w1 = wtab ? wl[p][8 * s + 2 * e2 + 1] : 1.0;
-      split_pair(w0 * v[2 * e2].x, w1 * v[2 * e2 + 1].x, hr[e2], lr[e2]);
-      if (CPLX) split_pair(w0 * v[2 * e2].y, w1 * v[2 * e2 + 1].y, hi_[e2], li_[e2]);
+  for (int p = 0; p < PREP_MAXP; ++p) dsum[p] = 0.0;
+  for (int t = 0; t < PREP_STEPS; ++t) {
+    const int64_t kc = (int64_t)blockIdx.x * PREP_STEPS + t;
+    if (kc >= nkc) break;   // uniform over the workgroup
+    const int64_t m0 = kc * HK;
+    {
+      const int col = tid & 63, r0 = tid >> 6;
+      const int nn = c0 + col;
+#pragma unroll
+      for (int j = 0; j < HK / 4; ++j) {
+        const int r = r0 + 4 * j;
+        const int64_t m = m0 + r;
+        double2 v = make_double2(0.0, 0.0);
+        if (m < M && nn < N) {
+          if (CPLX) v = reinterpret_cast<const double2 *>(B)[m * N + nn];
+          else v.x = reinterpret_cast<const double *>(B)[m * N + nn];
+        }
+        tb[r][col] = v;
+      }
+      if (wtab) {
+        for (int e = tid; e < np * HK; e += 256) {
+          const int p = e / HK, r = e % HK;
+          wl[p][r] = (m0 + r < M) ? wtab[(int64_t)p * w_stride + m0 + r] : 0.0;
+        }
+      }
     }
-    uint4 *o = reinterpret_cast<uint4 *>(out + (int64_t)p * out_stride);
-    // 16-byte units: plane base ((kc * 4 + plane) * Np + n) * 4, then the segment
-    o[((kc * 4 + 0) * Np + n) * 4 + unit] = make_uint4(hr[0], hr[1], hr[2], hr[3]);
-    o[((kc * 4 + 1) * Np + n) * 4 + unit] = make_uint4(lr[0], lr[1], lr[2], lr[3]);
-    if (CPLX) {
-      o[((kc * 4 + 2) * Np + n) * 4 + unit] = make_uint4(hi_[0], hi_[1], hi_[2], hi_[3]);
-      o[((kc * 4 + 3) * Np + n) * 4 + unit] = make_uint4(li_[0], li_[1], li_[2], li_[3]);
+    __syncthreads();
+    double2 v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = tb[8 * s + e][c];
+    double b2[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) b2[e] = v[e].x * v[e].x + v[e].y * v[e].y;
+    for (int p = 0; p < reps; ++p) {
+      unsigned hr[4], lr[4], hi_[4], li_[4];
+#pragma unroll
+      for (int e2 = 0; e2 < 4; ++e2) {
+        const double w0 = wtab ? wl[p][8 * s + 2 * e2] : 1.0;
+        const double w1 = wtab ? wl[p][8 * s + 2 * e2 + 1] : 1.0;
+        split_pair(w0 * v[2 * e2].x, w1 * v[2 * e2 + 1].x, hr[e2], lr[e2]);
+        if (CPLX) split_pair(w0 * v[2 * e2].y, w1 * v[2 * e2 + 1].y, hi_[e2], li_[e2]);
+      }
+      if (dpart) {
+        double d = 0.0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) d += wl[p][8 * s + e] * b2[e];
+#pragma unroll
+        for (int q = 0; q < PREP_MAXP; ++q)
+          if (q == p) dsum[q] += d;
+      }
+      uint4 *o = reinterpret_cast<uint4 *>(out + (int64_t)p * out_stride);
+      // 16-byte units: plane base ((kc * 4 + plane) * Np + n) * 4, then the segment
+      o[((kc * 4 + 0) * Np + n) * 4 + unit] = make_uint4(hr[0], hr[1], hr[2], hr[3]);
+      o[((kc * 4 + 1) * Np + n) * 4 + unit] = make_uint4(lr[0], lr[1], lr[2], lr[3]);
+      if (CPLX) {
+        o[((kc * 4 + 2) * Np + n) * 4 + unit] = make_uint4(hi_[0], hi_[1], hi_[2], hi_[3]);
+        o[((kc * 4 + 3) * Np + n) * 4 + unit] = make_uint4(li_[0], li_[1], li_[2], li_[3]);
+      }
+    }
+    __syncthreads();   // tb and wl are refilled by the next step
+  }
+  if (dpart && wtab) {
+#pragma unroll
+    for (int p = 0; p < PREP_MAXP; ++p) red[s][p][c] = dsum[p];
+    __syncthreads();
+    for (int e = tid; e < np * PREP_COLS; e += 256) {
+      const int p = e / PREP_COLS, cc = e % PREP_COLS;
+      if (c0 + cc < N)
+        dpart[((int64_t)blockIdx.x * np + p) * N + c0 + cc] =
+            ((red[0][p][cc] + red[1][p][cc]) + red[2][p][cc]) + red[3][p][cc];
     }
   }
+}
+
+// diag[p][n] = sum over the row chunks, in order, of the partials
+__global__ __launch_bounds__(256) void prepare_diag_reduce_kernel(const double *dpart, int64_t nchunks, int np, int N,
+                                                                  double *diag) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)np * N) return;
+  double d = 0.0;
+  for (int64_t c = 0; c < nchunks; ++c) d += dpart[c * np * N + i];
+  diag[i] = d;
 }
 
 // ------------------------------------------------------------------ contraction
@@ -461,25 +509,40 @@ int64_t bf16_partial_elems(const Bf16Plan &pl, int npts) {
   return (int64_t)npts * pl.nsplit * pl.ntiles * pl.tn * pl.tn;
 }
 
+int64_t bf16_diag_scratch_doubles(int64_t M, int N) {
+  const int64_t nkc = (M + HK - 1) / HK;
+  return (nkc + PREP_STEPS - 1) / PREP_STEPS * PREP_MAXP * (int64_t)N;
+}
+
 hipError_t launch_bf16_prepare(hipStream_t s, const void *B, bool cplx, int64_t M, int N, const double *wtab,
-                               int npts, unsigned short *out) {
+                               int npts, unsigned short *out, double *dscratch, double *diag) {
   const int64_t nkc = (M + HK - 1) / HK;
   const int Np = (N + HT - 1) / HT * HT;
   const int64_t stride = bf16_prepared_elems(M, N);
   if (nkc <= 0) return hipSuccess;
+  const int64_t nchunks = (nkc + PREP_STEPS - 1) / PREP_STEPS;
+  const bool want_diag = wtab && dscratch && diag;
   const int reps = wtab ? npts : 1;
   for (int p0 = 0; p0 < reps; p0 += PREP_MAXP) {
     const int np = reps - p0 < PREP_MAXP ? reps - p0 : PREP_MAXP;
     const double *w = wtab ? wtab + (int64_t)p0 * M : nullptr;
-    const dim3 grid((unsigned)nkc, (unsigned)(Np / PREP_COLS));
+    const dim3 grid((unsigned)nchunks, (unsigned)(Np / PREP_COLS));
+    double *dp = want_diag ? dscratch : nullptr;
     if (cplx)
       hipLaunchKernelGGL(bf16_prepare_kernel<true>, grid, dim3(256), 0, s, B, M, N, Np, w, M, np,
-                         out + (int64_t)p0 * stride, stride);
+                         out + (int64_t)p0 * stride, stride, dp);
     else
       hipLaunchKernelGGL(bf16_prepare_kernel<false>, grid, dim3(256), 0, s, B, M, N, Np, w, M, np,
-                         out + (int64_t)p0 * stride, stride);
-    const hipError_t e = hipGetLastError();
+                         out + (int64_t)p0 * stride, stride, dp);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (want_diag) {
+      const int64_t tot = (int64_t)np * N;
+      hipLaunchKernelGGL(prepare_diag_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, dscratch,
+                         nchunks, np, N, diag + (int64_t)p0 * N);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }

@@ -113,8 +113,11 @@ void bf16_plan(int64_t M, int N, int npts, int64_t slots, int64_t max_part, int 
 int64_t bf16_partial_elems(const Bf16Plan &pl, int npts);
 // Prepared operands from an FP64 B slab: wtab == nullptr gives the unscaled left operand
 // (one), else one right operand w_p B per point p < npts, at bf16_prepared_elems apart.
+// With dscratch (bf16_diag_scratch_doubles) and diag set, also the exact FP64 diagonal
+// diag[p][P] = sum_m wtab[p][m] |B_mP|^2 of those points.
+int64_t bf16_diag_scratch_doubles(int64_t M, int N);
 hipError_t launch_bf16_prepare(hipStream_t s, const void *B, bool cplx, int64_t M, int N, const double *wtab,
-                               int npts, unsigned short *out);
+                               int npts, unsigned short *out, double *dscratch = nullptr, double *diag = nullptr);
 // One contraction launch's worth of work (a sub-batch of one job).
 constexpr int BF16_MAX_GROUPS = 16;
 struct Bf16Group {

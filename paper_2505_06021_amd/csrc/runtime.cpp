@@ -292,7 +292,8 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
     return r * prep_bytes + bf16_partial_elems(pl, (int)r) * 8 + 512;
   };
   const int64_t per_pt = 2 * nn * 16 + M * 8 + (mixed ? (int64_t)N * 8 : 0) + trln_blocked_scratch_bytes(1) + 64;
-  const int64_t diag_scratch = mixed ? diag_exact_scratch_doubles(M, N, 16) * 8 : 0;
+  const int64_t diag_scratch = bsplit ? bf16_diag_scratch_doubles(M, N) * 8
+                              : mixed ? diag_exact_scratch_doubles(M, N, 16) * 8 : 0;
   const int64_t small = (int64_t)(hs.eps_occ.size() + hs.eps_virt.size() + hs.zeta_k.size()) * 8 +
                         (int64_t)hs.kq.size() * 4 + npts * 32 + 4096 + diag_scratch;
 
@@ -545,7 +546,8 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
       }
       if (mixed) {
         // exact FP64 diagonal, one pass per B slab over the batch entries that use it
-        int i0 = 0;
+        // (split-BF16: computed by the operand preparation instead)
+        int i0 = bsplit ? nb : 0;
         while (i0 < nb) {
           int i1 = i0 + 1;
           while (i1 < nb && hp[i1].bslot == hp[i0].bslot) ++i1;
@@ -567,7 +569,8 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
               const int64_t slab = b_direct ? job.pq[(size_t)gp[b0 + i0]] : hp[i0].bslot;
               const char *bsrc = (const char *)(b_direct ? sys->B : d_B) + slab * M * N * belem;
               RPA_HIP(launch_bf16_prepare(S, bsrc, cplx, M, N, d_w + (int64_t)i0 * M, i1 - i0,
-                                          d_R + (int64_t)(i0 - r0) * (prep_bytes / 2)));
+                                          d_R + (int64_t)(i0 - r0) * (prep_bytes / 2), d_dscr,
+                                          d_diag + (int64_t)i0 * N));
               i0 = i1;
             }
             const int64_t max_part = bf16_partial_elems(rplan, (int)rbatch);

@@ -60,7 +60,8 @@ int64_t Scheduler::footprint(const HostSmall &hs, int nw, rpa_precision prec) {
   const int64_t small = (int64_t)(hs.eps_occ.size() + hs.eps_virt.size() + hs.zeta_k.size()) * 8 +
                         (int64_t)hs.kq.size() * 4 + (int64_t)hs.nq * nw * 32 + 4096 +
                         (int64_t)(hs.nq + nw + 1) * 8 +
-                        (mixed ? diag_exact_scratch_doubles(M, (int)N, 16) * 8 : 0);
+                        (prec == RPA_BF16X3 ? bf16_diag_scratch_doubles(M, (int)N) * 8
+                         : mixed ? diag_exact_scratch_doubles(M, (int)N, 16) * 8 : 0);
   // one q staged at a time: FP64 B (and its FP32 copy, or its prepared split-BF16 copy),
   // V^(1/2), and per point chi0, T, the weight table and the exact diagonal -- the same
   // sizes run_points() budgets
