@@ -264,7 +264,9 @@ def main():
                    "nocc": s.nocc, "nvirt": s.nvirt, "naux": s.naux, "nw": s.nw,
                    "is_complex": s.is_complex, "chi0_precision": args.prec,
                    "B": "Philox4x32-10 on device", "parallelism": "single GPU",
-                   "chi0_tile_config": sorted(set(rpa.tuned().values())) if args.prec == "fp64" else None},
+                   "chi0_tile_config": sorted({v for k, v in rpa.tuned().items()
+                                               if k.startswith({"fp64": "f64_", "fp32": "f32_",
+                                                                "bf16x3": "bf16_"}[args.prec])})},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "kernel": "chi0", "flops_per_launch": issued_launch,

@@ -306,6 +306,172 @@ inline unsigned grid_for(int64_t n) {
   return (unsigned)b;
 }
 
+// The FP32 contraction on 128 x 128 tiles: eight waves of 64 x 32 (4 x 2 blocks), 16-row
+// K steps (32 KB of LDS per stage, double-buffered), one workgroup per CU, FP64 flush
+// every FLUSH_ROWS rows as in the 64-wide kernel, XCD-contiguous (tile, point, split)
+// order (the 8 XCDs take workgroups round-robin).  Twice the MFMA work per loaded byte.
+constexpr int TW32 = 128;
+constexpr int LDPW32 = TW32 + 1;
+constexpr int KTW32 = 16;
+
+__global__ __launch_bounds__(512) void chi0_f32_t128_kernel(Chi0Args a, const float2 *B32, const double *diag,
+                                                            int32_t ntiles, int32_t npts) {
+  __shared__ float2 lds[2][2][KTW32][LDPW32];
+  const int G = gridDim.x, hw = blockIdx.x;
+  const int per = (G + 7) / 8, tall = G % 8 == 0 ? 8 : G % 8;
+  const int xcd = hw % 8, loc = hw / 8;
+  const int lg = xcd < tall ? xcd * per + loc : tall * per + (xcd - tall) * (per - 1) + loc;
+  const int tile = lg % ntiles, p = (lg / ntiles) % npts, split = lg / (ntiles * npts);
+
+  const PointDesc pd = a.pts[p];
+  int tr, tc;
+  tile_of(tile, tr, tc);
+  const int N = a.N;
+  const int ms = (int)((((a.M + a.ksplit - 1) / a.ksplit) + KTW32 - 1) / KTW32) * KTW32;
+  const int mlo = split * ms;
+  const int M = mlo + ms < (int)a.M ? mlo + ms : (int)a.M;
+  const int P0 = tr * TW32, Q0 = tc * TW32;
+  const bool is_diag = (tr == tc);
+  const int tid = threadIdx.x;
+  const int lrow = tid >> 5, lc = tid & 31;
+  const float2 *bb = B32 + (int64_t)pd.bslot * a.b_slot_stride;
+  const double *wrow = a.wtab + (int64_t)p * a.M;
+  int pcol[4], qcol[4];
+  bool pok[4], qok[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int P = P0 + lc + 32 * c, Q = Q0 + lc + 32 * c;
+    pok[c] = P < N;
+    qok[c] = Q < N;
+    pcol[c] = pok[c] ? P : 0;
+    qcol[c] = qok[c] ? Q : 0;
+  }
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = wave >> 2, wc = wave & 3;
+  const int li = lane & 15, lk = lane >> 4;
+
+  f4 accR[4][2], accI[4][2];
+  double hR[4][2][4], hI[4][2][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      accR[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+      accI[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) hR[x][y][r] = hI[x][y][r] = 0.0;
+    }
+
+  float2 sa[4], sb[4];
+  double sw;
+  bool mv;
+  auto load = [&](int m0) {
+    const int m = m0 + lrow;
+    mv = m < M;
+    const int mc = mv ? m : 0;
+    sw = wrow[mc];
+    const int64_t ro = (int64_t)mc * N;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      sa[c] = bb[ro + pcol[c]];
+      sb[c] = bb[ro + qcol[c]];
+    }
+  };
+  auto store = [&](int buf) {
+    const float w = mv ? (float)sw : 0.f;
+    const float2 z = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const float2 x = (mv && pok[c]) ? sa[c] : z;
+      const float2 y = qok[c] ? sb[c] : z;
+      lds[buf][0][lrow][lc + 32 * c] = x;
+      lds[buf][1][lrow][lc + 32 * c] = make_float2(w * y.x, w * y.y);
+    }
+  };
+  auto contract = [&](int buf) {
+#pragma unroll
+    for (int ks = 0; ks < KTW32 / 4; ++ks) {
+      float2 av[4], bv[2];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) av[x] = lds[buf][0][ks * 4 + lk][wr * 64 + x * 16 + li];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bv[y] = lds[buf][1][ks * 4 + lk][wc * 32 + y * 16 + li];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) accR[x][y] = mfma32(av[x].x, bv[y].x, accR[x][y]);
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) accI[x][y] = mfma32(av[x].x, bv[y].y, accI[x][y]);
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) accR[x][y] = mfma32(av[x].y, bv[y].y, accR[x][y]);
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) accI[x][y] = mfma32(-av[x].y, bv[y].x, accI[x][y]);
+    }
+  };
+  auto flush = [&]() {
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          hR[x][y][r] += (double)accR[x][y][r];
+          hI[x][y][r] += (double)accI[x][y][r];
+        }
+        accR[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+        accI[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+      }
+  };
+
+  constexpr int FLUSH_STEPS = FLUSH_ROWS / KTW32;
+  const int nsteps = M > mlo ? (M - mlo + KTW32 - 1) / KTW32 : 1;
+  load(mlo);
+  store(0);
+  __syncthreads();
+  for (int s = 0; s + 1 < nsteps; ++s) {
+    const int cur = s & 1;
+    load(mlo + (s + 1) * KTW32);
+    __builtin_amdgcn_sched_barrier(0);
+    contract(cur);
+    __builtin_amdgcn_sched_barrier(0);
+    if ((s + 1) % FLUSH_STEPS == 0) flush();
+    store(cur ^ 1);
+    __syncthreads();
+  }
+  contract((nsteps - 1) & 1);
+  flush();
+
+  double2 *out = (split == 0 ? a.out : a.partial) + (int64_t)p * a.out_stride;
+  const double *dg = diag + (int64_t)p * N;
+  const bool first = split == 0;   // the exact diagonal enters once
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int P = P0 + wr * 64 + x * 16 + 4 * lk + r;
+        const int Q = Q0 + wc * 32 + y * 16 + li;
+        if (P >= N || Q >= N) continue;
+        const double re = hR[x][y][r], im = hI[x][y][r];
+        if (is_diag) {
+          if (P < Q) continue;
+          if (P == Q) {
+            out[(int64_t)P * N + Q] = make_double2(first ? dg[P] : 0.0, 0.0);
+            continue;
+          }
+        }
+        out[(int64_t)P * N + Q] = make_double2(re, im);
+        out[(int64_t)Q * N + P] = make_double2(re, -im);
+      }
+}
+
 }  // namespace
 
 hipError_t launch_to_f32(hipStream_t s, const void *in, float2 *out, int64_t n, bool cplx) {
@@ -339,13 +505,21 @@ hipError_t launch_diag_exact(hipStream_t s, const void *B, bool cplx, int64_t M,
 }
 
 hipError_t launch_chi0_mixed(hipStream_t s, const Chi0Args &a, int32_t npts, const float2 *B32,
-                             const double *diag, int prec) {
+                             const double *diag, int prec, int tile) {
   if (npts <= 0) return hipSuccess;
-  const int T = (a.N + TN - 1) / TN;
-  const int ks = a.ksplit > 1 ? 2 : 1;   // split 0 writes a.out, split 1 writes a.partial
-  const dim3 grid((unsigned)(T * (T + 1) / 2), (unsigned)npts, (unsigned)ks);
   if (prec != 1) return hipErrorInvalidValue;   // FP32 only; split-BF16 is chi0_bf16.hip
-  hipLaunchKernelGGL(chi0_f32_kernel<16>, grid, dim3(256), 0, s, a, B32, diag);
+  const int ks = a.ksplit > 1 ? 2 : 1;   // split 0 writes a.out, split 1 writes a.partial
+  if (tile == 128) {
+    const int T = (a.N + TW32 - 1) / TW32;
+    const int64_t nwg = (int64_t)T * (T + 1) / 2 * npts * ks;
+    if (nwg > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(chi0_f32_t128_kernel, dim3((unsigned)nwg), dim3(512), 0, s, a, B32, diag, T * (T + 1) / 2,
+                       npts);
+  } else {
+    const int T = (a.N + TN - 1) / TN;
+    const dim3 grid((unsigned)(T * (T + 1) / 2), (unsigned)npts, (unsigned)ks);
+    hipLaunchKernelGGL(chi0_f32_kernel<16>, grid, dim3(256), 0, s, a, B32, diag);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || ks == 1) return e;
   return launch_split_add(s, a.partial, (int64_t)npts * a.out_stride, a.out);

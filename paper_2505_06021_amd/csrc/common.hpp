@@ -87,10 +87,11 @@ hipError_t launch_to_f32(hipStream_t s, const void *in, float2 *out, int64_t n, 
 int64_t diag_exact_scratch_doubles(int64_t M, int N, int npts);
 hipError_t launch_diag_exact(hipStream_t s, const void *B, bool cplx, int64_t M, int N, const double *wtab,
                              int npts, double *scratch, double *diag);
-// chi0 with FP32 (prec 1) or split-BF16 (prec 2) MFMA from the FP32 copy B32 (slab stride
-// a.b_slot_stride), FP64 flush of partial sums and the exact diagonal `diag` [npts][N].
+// chi0 with FP32 MFMA (prec 1) from the FP32 copy B32 (slab stride a.b_slot_stride), FP64
+// flush of partial sums and the exact diagonal `diag` [npts][N], on 64- or 128-wide tiles
+// (tile; both sum the same products in the same order).
 hipError_t launch_chi0_mixed(hipStream_t s, const Chi0Args &a, int32_t npts, const float2 *B32,
-                             const double *diag, int prec);
+                             const double *diag, int prec, int tile = 64);
 
 // ---- split-BF16 chi0 from prepared operands (chi0_bf16.hip) ------------------------
 // No FP32 sum of the contraction runs over more rows than this.

@@ -535,19 +535,10 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
       if (prof) RPA_TRY(ctx.prof_begin(S, RPA_K_CHI0_AUX));
       RPA_HIP(launch_chi0_weights(S, ca, nb));
       if (!mixed) RPA_TRY(tune_chi0_cfg(S, ca, nb, cplx, &cfg));
-      {
-        // two-way row split of the contraction when it fills the last round of
-        // workgroups better (counting the workgroups of a concurrent lane); the second
-        // half's result goes to the T buffer, which is free until the sandwich
-        const int64_t tn = mixed ? 64 : chi0_cfg_tile(cfg);
-        const int64_t T = (N + tn - 1) / tn;
-        const int64_t slots = (mixed ? 2LL : (int64_t)chi0_cfg_slots_per_cu(cfg)) * ncu;
-        ca.ksplit = chi0_pick_ksplit(T * (T + 1) / 2 * nb * nlanes, slots, M) >= 2 ? 2 : 1;
-      }
-      if (mixed) {
-        // exact FP64 diagonal, one pass per B slab over the batch entries that use it
-        // (split-BF16: computed by the operand preparation instead)
-        int i0 = bsplit ? nb : 0;
+      int f32_tile = 64;
+      if (mixed && !bsplit) {
+        // the exact FP64 diagonal first: the tile tuner launches the contraction
+        int i0 = 0;
         while (i0 < nb) {
           int i1 = i0 + 1;
           while (i1 < nb && hp[i1].bslot == hp[i0].bslot) ++i1;
@@ -557,6 +548,19 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
                                     d_diag + (int64_t)i0 * N));
           i0 = i1;
         }
+        RPA_TRY(tune_f32_tile(S, ca, nb, cplx, d_B32, d_diag, &f32_tile));
+      }
+      {
+        // two-way row split of the contraction when it fills the last round of
+        // workgroups better (counting the workgroups of a concurrent lane); the second
+        // half's result goes to the T buffer, which is free until the sandwich
+        const int64_t tn = bsplit ? 64 : mixed ? f32_tile : chi0_cfg_tile(cfg);
+        const int64_t T = (N + tn - 1) / tn;
+        const int64_t slots = (mixed ? (tn == 128 ? 1LL : 2LL) : (int64_t)chi0_cfg_slots_per_cu(cfg)) * ncu;
+        ca.ksplit = chi0_pick_ksplit(T * (T + 1) / 2 * nb * nlanes, slots, M) >= 2 ? 2 : 1;
+      }
+      if (mixed) {
+        // the exact FP64 diagonal: FP32 above, split-BF16 in the operand preparation
         if (bsplit) {
           // sub-launches of up to rbatch points: prepare their right operands (per run of
           // points on one B slab), then contract and reduce
@@ -610,7 +614,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
         } else {
           if (prof) RPA_TRY(ctx.prof_end(S));
           if (prof) RPA_TRY(ctx.prof_begin(S, RPA_K_CHI0));
-          RPA_HIP(launch_chi0_mixed(S, ca, nb, d_B32, d_diag, (int)job.prec));
+          RPA_HIP(launch_chi0_mixed(S, ca, nb, d_B32, d_diag, (int)job.prec, f32_tile));
         }
       } else {
         if (prof) RPA_TRY(ctx.prof_end(S));

@@ -144,6 +144,10 @@ int tune_chi0_cfg(hipStream_t st, const Chi0Args &a, int npts, bool cplx, int *c
 // elements): fixed by RPA_BF16_TILE, else timed once per shape bucket and cached.
 int tune_bf16_tile(hipStream_t st, const Bf16Group &g, int64_t M, int N, int64_t slots, int64_t max_part, bool cplx,
                    int *tn_out);
+// Tile edge (64 or 128) of the FP32 contraction of npts points (a.out holds them; it is
+// overwritten): fixed by RPA_F32_TILE, else timed once per shape bucket and cached.
+int tune_f32_tile(hipStream_t st, const Chi0Args &a, int npts, bool cplx, const float2 *B32, const double *diag,
+                  int *tile_out);
 // "bucket configuration" lines of the choices made so far; returns the full length.
 int tuned_entries(char *buf, int len);
 // RPA_TRLN_SINGLE=1 selects the one-workgroup-per-matrix Cholesky instead of the blocked one.

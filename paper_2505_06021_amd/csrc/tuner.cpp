@@ -1,6 +1,6 @@
 // Autotuner of the chi0 contractions' tile shapes: the FP64 contraction's tile and
-// K-step depth, and the split-BF16 contraction's tile edge (64 or 128; RPA_BF16_TILE
-// fixes it).
+// K-step depth, and the FP32 and split-BF16 contractions' tile edges (64 or 128;
+// RPA_F32_TILE and RPA_BF16_TILE fix them).
 //
 // Candidates (launch_chi0_f64 configurations): 64-wide tiles with 8, 16 or 32 rows per
 // LDS step (two workgroups per CU) and 128-wide tiles with 16-row steps (one per CU).
@@ -47,7 +47,7 @@ void load_cache_locked() {
   std::ifstream f(p);
   std::string key, name;
   while (f >> key >> name) {
-    if (key.compare(0, 5, "bf16_") == 0) {
+    if (key.compare(0, 5, "bf16_") == 0 || key.compare(0, 4, "f32_") == 0) {
       if (name == "t64" || name == "t128") g_tuned[key] = name == "t64" ? 64 : 128;
       continue;
     }
@@ -57,7 +57,7 @@ void load_cache_locked() {
 }
 
 std::string entry_name(const std::string &key, int v) {
-  if (key.compare(0, 5, "bf16_") == 0) return v == 64 ? "t64" : "t128";
+  if (key.compare(0, 5, "bf16_") == 0 || key.compare(0, 4, "f32_") == 0) return v == 64 ? "t64" : "t128";
   return chi0_cfg_name(v);
 }
 
@@ -207,6 +207,66 @@ int tune_bf16_tile(hipStream_t st, const Bf16Group &g, int64_t M, int N, int64_t
   g_tuned[key] = best;
   store_cache_locked();
   *tn_out = best;
+  return RPA_OK;
+}
+
+int tune_f32_tile(hipStream_t st, const Chi0Args &a, int npts, bool cplx, const float2 *B32, const double *diag,
+                  int *tile_out) {
+  if (const char *e = getenv("RPA_F32_TILE")) {
+    const int v = atoi(e);
+    if (v == 64 || v == 128) {
+      *tile_out = v;
+      return RPA_OK;
+    }
+  }
+  if (const char *t = getenv("RPA_TUNE"))
+    if (t[0] == '0') {
+      *tile_out = 64;
+      return RPA_OK;
+    }
+  int mlog = 0;
+  for (int64_t m = a.M; m > 1; m >>= 1) ++mlog;
+  std::ostringstream k;
+  k << "f32_" << (cplx ? "c" : "r") << "_N" << ((a.N + 63) / 64) * 64 << "_p" << (npts > 512 ? 512 : npts) << "_m"
+    << mlog;
+  const std::string key = k.str();
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  load_cache_locked();
+  auto it = g_tuned.find(key);
+  if (it != g_tuned.end()) {
+    *tile_out = it->second;
+    return RPA_OK;
+  }
+  // both tile edges on the first 4096 rows, one row split, into the launch's own output
+  // (overwritten by the real launch)
+  Chi0Args t = a;
+  t.M = a.M < 4096 ? a.M : 4096;
+  t.ksplit = 1;
+  const int cands[2] = {64, 128};
+  float best_ms = 1e30f;
+  int best = 64;
+  hipEvent_t e0, e1;
+  RPA_HIP(hipEventCreate(&e0));
+  RPA_HIP(hipEventCreate(&e1));
+  for (int rep = 0; rep < 2; ++rep) {
+    for (int tile : cands) {
+      RPA_HIP(hipEventRecord(e0, st));
+      RPA_HIP(launch_chi0_mixed(st, t, npts, B32, diag, 1, tile));
+      RPA_HIP(hipEventRecord(e1, st));
+      RPA_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      RPA_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (rep == 1 && ms < best_ms) {
+        best_ms = ms;
+        best = tile;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  g_tuned[key] = best;
+  store_cache_locked();
+  *tile_out = best;
   return RPA_OK;
 }
 

@@ -148,3 +148,43 @@ def test_bf16x3_tile_edges_agree_bitwise_with_one_split(ctx, monkeypatch):
         monkeypatch.setenv("RPA_BF16_TILE", tile)
         got[tile] = ctx.energy(s, prec=BF16X3)
     assert got["64"][0] == got["128"][0] and np.array_equal(got["64"][1], got["128"][1])
+
+
+# ------------------------------------------------ FP32 tile edges
+
+@pytest.mark.parametrize("tile", ["64", "128"])
+@pytest.mark.parametrize("naux,nocc,nvirt", [(1, 2, 5), (127, 3, 7), (128, 4, 9), (129, 3, 7), (256, 8, 150)])
+def test_chi0_fp32_tile_edges(ctx, monkeypatch, naux, nocc, nvirt, tile):
+    # 64- and 128-wide output tiles, 16-row steps with ragged tails and FP64 flushes
+    # every 256 rows (M = 4800 rows for (8, 150))
+    monkeypatch.setenv("RPA_F32_TILE", tile)
+    s = inputs.make_system(f"f32edge{naux}", (2, 2, 1), nocc, nvirt, naux, 2, 91 + naux, is_complex=True)
+    ref = orc.chi0(s, 1, s.omega[1])
+    say(f"chi0 fp32 tile {tile} N={naux} M={4 * nocc * nvirt}")
+    got = ctx.chi0(s, 1, s.omega[1], prec=FP32)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    say(f"  rel Frobenius error {err:.3e}")
+    assert err <= TOL_CHI0[FP32]
+    d_ref = np.real(np.diagonal(ref))
+    assert np.max(np.abs(np.real(np.diagonal(got)) - d_ref) / np.abs(d_ref)) <= 1e-13
+    assert np.abs(got - got.conj().T).max() == 0.0
+
+
+def test_fp32_tile_edges_agree_bitwise(ctx, monkeypatch):
+    # one row split: both tile edges issue the same MFMA and flush sequence per element
+    s = inputs.make_system("f32tiles", (2, 2, 1), 8, 150, 300, 3, 6, is_complex=True)   # M = 4800
+    got = {}
+    for tile in ("64", "128"):
+        monkeypatch.setenv("RPA_F32_TILE", tile)
+        got[tile] = ctx.chi0(s, 2, s.omega[2], prec=FP32)
+    assert np.array_equal(got["64"], got["128"])
+
+
+@pytest.mark.parametrize("tile", ["64", "128"])
+def test_energy_fp32_tile_edges(ctx, monkeypatch, tile):
+    monkeypatch.setenv("RPA_F32_TILE", tile)
+    s = ragged(3)
+    say(f"energy fp32 tile {tile}")
+    E, _ = ctx.energy(s, prec=FP32)
+    E64, _ = ctx.energy(s)
+    assert abs(E - E64) <= TOL_E[FP32]

@@ -96,3 +96,14 @@ def test_tuner_records_and_persists_choice(ctx, monkeypatch, tmp_path):
     if cache.exists():   # written when the bucket was tuned in this test's lifetime
         lines = dict(l.split() for l in cache.read_text().splitlines())
         assert all(v in CFGS for k, v in lines.items() if k.startswith("f64_"))
+
+
+def test_fp32_tile_tuner_records_choice(ctx, monkeypatch):
+    from paper_2505_06021_amd import rpa
+    monkeypatch.delenv("RPA_F32_TILE", raising=False)
+    s = inputs.make_system("tune32", (2, 2, 1), 3, 7, 150, 4, 33, is_complex=True, sigma=0.15)
+    say("energy fp32 with the tile tuner")
+    E, _ = ctx.energy(s, prec=1)
+    choices = {k: v for k, v in rpa.tuned().items() if k.startswith("f32_")}
+    assert choices and all(v in ("t64", "t128") for v in choices.values()), choices
+    assert abs(E - orc.energy(s)[0]) <= 1e-6
