@@ -118,9 +118,9 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(double2 *W, int64_t stri
     v[j] = (r < jb && s <= r) ? A[(int64_t)(j0 + r) * n + j0 + s] : make_double2(0.0, 0.0);
   }
   for (int e = tid; e < NB * NB; e += 256) X[e / NB][e % NB] = make_double2(0.0, 0.0);
-  // the block's log1p terms are summed in a register of thread 0 and stored once: a global
-  // read-modify-write per column would make every barrier wait for memory
-  double lsum = 0.0;
+  // the pivots' d_c are kept in LDS; their square roots and log1p terms are taken after
+  // the loop, in parallel, so no transcendental sits between two barriers
+  __shared__ double dpiv[NB];
   for (int c = 0; c < jb; ++c) {
     double2 *cb = colbuf[c & 1];
     if (s == c) {
@@ -134,10 +134,7 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(double2 *W, int64_t stri
       if (tid == 0) info[b] = j0 + c;
       return;   // uniform: every thread read the same pivot
     }
-    if (tid == 0) {
-      ld[c] = sqrt(piv);
-      lsum += log1p(d);
-    }
+    if (tid == 0) dpiv[c] = d;
     if (s > c && s < jb) {
       // W[r][s] -= W[r][c] conj(W[s][c]) / piv for r >= s
       const double2 ys = cb[s];
@@ -154,8 +151,19 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(double2 *W, int64_t stri
       }
     }
   }
-  if (tid == 0) logacc[b] += lsum;
   __syncthreads();
+  if (tid < jb) {
+    ld[tid] = sqrt(1.0 + dpiv[tid]);
+    dpiv[tid] = log1p(dpiv[tid]);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // summed in column order, once per block: a global read-modify-write per column would
+    // make every barrier wait for memory
+    double lsum = 0.0;
+    for (int c = 0; c < jb; ++c) lsum += dpiv[c];
+    logacc[b] += lsum;
+  }
   // the factor L11 into D: L[r][s] = W[r][s] / l_s below the diagonal, l_s on it
   {
     const double ls = s < jb ? ld[s] : 1.0;
@@ -170,9 +178,11 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(double2 *W, int64_t stri
   // X = L11^{-1}, row by row: X[i][j] = -(sum_{k<i} L[i][k] X[k][j]) / l_i for j < i,
   // X[i][i] = 1 / l_i.  X is zero above its diagonal, so every lane can run over all
   // k < i: L[i][k] is a broadcast read, X[k][j] a conflict-free row read.  The 256
-  // threads split k into four interleaved partitions summed in a fixed order.
+  // threads split k into four interleaved partitions summed in a fixed order; row i is
+  // finished by the thread of partition i % 4, the only one that reads X[i][j] later, so
+  // one barrier per row suffices (the partial sums alternate between two buffers).
   {
-    __shared__ double2 part[4][NB];
+    __shared__ double2 part[2][4][NB];
     const int j = tid & 63, g = tid >> 6;
     if (tid < jb) X[tid][tid] = make_double2(1.0 / ld[tid], 0.0);
     __syncthreads();
@@ -183,16 +193,17 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(double2 *W, int64_t stri
         sr += lv.x * xv.x - lv.y * xv.y;
         si += lv.x * xv.y + lv.y * xv.x;
       }
-      part[g][j] = make_double2(sr, si);
+      double2 (*pp)[NB] = part[i & 1];
+      pp[g][j] = make_double2(sr, si);
       __syncthreads();
-      if (g == 0 && j < i) {
-        const double il = 1.0 / ld[i];
-        const double r = (part[0][j].x + part[1][j].x) + (part[2][j].x + part[3][j].x);
-        const double m = (part[0][j].y + part[1][j].y) + (part[2][j].y + part[3][j].y);
+      if (g == (i & 3) && j < i) {
+        const double il = X[i][i].x;   // 1 / l_i
+        const double r = (pp[0][j].x + pp[1][j].x) + (pp[2][j].x + pp[3][j].x);
+        const double m = (pp[0][j].y + pp[1][j].y) + (pp[2][j].y + pp[3][j].y);
         X[i][j] = make_double2(-r * il, -m * il);
       }
-      __syncthreads();
     }
+    __syncthreads();
   }
   double2 *out = linv + (int64_t)b * NB * NB;
   for (int e = tid; e < NB * NB; e += 256) out[e] = X[e / NB][e % NB];
