@@ -171,8 +171,18 @@ __global__ __launch_bounds__(256) void prepare_diag_reduce_kernel(const double *
                                                                   double *diag) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= (int64_t)np * N) return;
+  // chunks added in order, loads issued 16 at a time (latency-bound: few workgroups)
+  const int64_t st = (int64_t)np * N;
   double d = 0.0;
-  for (int64_t c = 0; c < nchunks; ++c) d += dpart[c * np * N + i];
+  int64_t c = 0;
+  for (; c + 16 <= nchunks; c += 16) {
+    double t[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) t[u] = dpart[(c + u) * st + i];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) d += t[u];
+  }
+  for (; c < nchunks; ++c) d += dpart[c * st + i];
   diag[i] = d;
 }
 

@@ -96,8 +96,19 @@ __global__ __launch_bounds__(256) void diag_reduce_kernel(const double *partial,
                                                           int N, double *diag) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= (int64_t)npts * N) return;
+  // the chunks are added in order; their loads go out 16 at a time (few workgroups: the
+  // loads' latency, not bandwidth, sets the time)
+  const int64_t st = (int64_t)npts * N;
   double s = 0.0;
-  for (int c = 0; c < nchunks; ++c) s += partial[(int64_t)c * npts * N + i];
+  int c = 0;
+  for (; c + 16 <= nchunks; c += 16) {
+    double t[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) t[u] = partial[(int64_t)(c + u) * st + i];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s += t[u];
+  }
+  for (; c < nchunks; ++c) s += partial[(int64_t)c * st + i];
   diag[i] = s;
 }
 

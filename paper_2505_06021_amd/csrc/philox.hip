@@ -32,14 +32,16 @@ __device__ __forceinline__ double uniform52(uint32_t a, uint32_t b) {
 template <bool CPLX>
 __global__ __launch_bounds__(256) void philox_B_kernel(uint64_t seed, double sigma, int32_t nk,
                                                        int32_t iq, int32_t k0, int64_t per_k,
-                                                       int64_t total, void *out) {
+                                                       void *out) {
   const uint32_t key0 = (uint32_t)seed;
   const uint32_t key_hi = (uint32_t)(seed >> 32);
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t kk = g / per_k;
-    const uint64_t e = (uint64_t)(g - kk * per_k);
-    const uint32_t key1 = key_hi + (uint32_t)(iq * nk + k0 + (int32_t)kk);
+  // blockIdx.y is the k of the slab (no 64-bit division per element)
+  const int32_t kk = (int32_t)blockIdx.y;
+  const uint32_t key1 = key_hi + (uint32_t)(iq * nk + k0 + kk);
+  for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < per_k;
+       e0 += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t e = (uint64_t)e0;
+    const int64_t g = (int64_t)kk * per_k + e0;
     const uint4 w = philox4x32_10(make_uint4((uint32_t)e, (uint32_t)(e >> 32), 0u, 0u), key0, key1);
     const double u1 = uniform52(w.x, w.y);
     const double u2 = uniform52(w.z, w.w);
@@ -83,12 +85,16 @@ hipError_t launch_philox_B(hipStream_t s, uint64_t seed, double sigma, int32_t n
   const int64_t per_k = (int64_t)nocc * nvirt * naux;
   const int64_t total = per_k * (k1 - k0);
   if (total <= 0) return hipSuccess;
+  if (k1 - k0 > 65535) return hipErrorInvalidValue;
+  // about 64K workgroups over all k slabs together
+  int64_t bx = (per_k + 255) / 256, cap = 65536 / (k1 - k0);
+  if (cap < 64) cap = 64;
+  if (bx > cap) bx = cap;
+  const dim3 grid((unsigned)bx, (unsigned)(k1 - k0));
   if (cplx)
-    hipLaunchKernelGGL(philox_B_kernel<true>, dim3(grid_for(total)), dim3(256), 0, s, seed, sigma,
-                       nk, iq, k0, per_k, total, out);
+    hipLaunchKernelGGL(philox_B_kernel<true>, grid, dim3(256), 0, s, seed, sigma, nk, iq, k0, per_k, out);
   else
-    hipLaunchKernelGGL(philox_B_kernel<false>, dim3(grid_for(total)), dim3(256), 0, s, seed, sigma,
-                       nk, iq, k0, per_k, total, out);
+    hipLaunchKernelGGL(philox_B_kernel<false>, grid, dim3(256), 0, s, seed, sigma, nk, iq, k0, per_k, out);
   return hipGetLastError();
 }
 
