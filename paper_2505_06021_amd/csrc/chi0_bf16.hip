@@ -80,9 +80,13 @@ __global__ __launch_bounds__(256) void bf16_prepare_kernel(const void *B, int64_
                                                            const double *wtab, int64_t w_stride, int np,
                                                            unsigned short *out, int64_t out_stride,
                                                            double *dpart) {
-  __shared__ double2 tb[HK][PREP_COLS + 1];
+  // the row tile and, after the last step, the diagonal's reduction buffer share one LDS
+  // array (37 KB a workgroup in all: four workgroups per CU)
+  constexpr int TB_BYTES = HK * (PREP_COLS + 1) * 16, RED_BYTES = 4 * PREP_MAXP * PREP_COLS * 8;
+  __shared__ __attribute__((aligned(16))) char lds_raw[TB_BYTES > RED_BYTES ? TB_BYTES : RED_BYTES];
+  double2 (*tb)[PREP_COLS + 1] = reinterpret_cast<double2 (*)[PREP_COLS + 1]>(lds_raw);
+  double (*red)[PREP_MAXP][PREP_COLS] = reinterpret_cast<double (*)[PREP_MAXP][PREP_COLS]>(lds_raw);
   __shared__ double wl[PREP_MAXP][HK];
-  __shared__ double red[4][PREP_MAXP][PREP_COLS];
   const int c0 = blockIdx.y * PREP_COLS;
   const int64_t nkc = (M + HK - 1) / HK;
   const int tid = threadIdx.x;
@@ -154,6 +158,7 @@ __global__ __launch_bounds__(256) void bf16_prepare_kernel(const void *B, int64_
     __syncthreads();   // tb and wl are refilled by the next step
   }
   if (dpart && wtab) {
+    __syncthreads();   // every step's reads of tb are done
 #pragma unroll
     for (int p = 0; p < PREP_MAXP; ++p) red[s][p][c] = dsum[p];
     __syncthreads();

@@ -44,43 +44,58 @@ __global__ __launch_bounds__(256) void to_f32_kernel(const void *in, float2 *out
 // ------------------------------------------------------------------ exact diagonal
 // partial[c][p][P] = sum over the rows m of chunk c of w_p(m) |B_mP|^2 in FP64, for all
 // the points p of a launch that share one B slab; a second pass sums the chunks in
-// order.  A workgroup covers 64 columns x DIAG_ROWS rows: four row groups of 64 lanes
-// (lanes on consecutive columns, so every load instruction reads 1 KB contiguous) whose
-// partial sums are combined in LDS in a fixed order.
-constexpr int DIAG_ROWS = 256;     // rows per chunk
+// order.  A workgroup covers 64 columns x spw * DIAG_ROWS rows (spw sub-chunks, chosen
+// from the shape so that the launch has about 2048 workgroups): four row groups of 64
+// lanes (lanes on consecutive columns, so every load instruction reads 1 KB contiguous)
+// whose partial sums are combined in LDS in a fixed order.  A thread issues all the row
+// loads of a sub-chunk before it accumulates them: the kernel is bound by HBM reads.
+constexpr int DIAG_ROWS = 64;      // rows per sub-chunk
 constexpr int DIAG_MAXP = 16;      // points per pass
 
 __global__ __launch_bounds__(256) void diag_partial_kernel(const void *B, int cplx, int64_t M, int N,
-                                                           const double *wtab, int npts,
+                                                           const double *wtab, int npts, int spw,
                                                            double *partial) {
-  __shared__ double wl[DIAG_MAXP][DIAG_ROWS];   // the chunk's weights, read once
+  __shared__ double wl[DIAG_MAXP][DIAG_ROWS];   // the sub-chunk's weights, read once
   __shared__ double red[4][DIAG_MAXP][64];
+  constexpr int RPG = DIAG_ROWS / 4;            // rows per row group
   const int col = threadIdx.x & 63, grp = threadIdx.x >> 6;
   const int P = blockIdx.x * 64 + col;
   const int c = blockIdx.y;
-  const int64_t m0 = (int64_t)c * DIAG_ROWS;
-  const int rows = (int)(M - m0 < DIAG_ROWS ? M - m0 : DIAG_ROWS);
-  for (int e = threadIdx.x; e < DIAG_MAXP * DIAG_ROWS; e += 256) {
-    const int p = e / DIAG_ROWS, r = e % DIAG_ROWS;
-    wl[p][r] = (p < npts && r < rows) ? wtab[(int64_t)p * M + m0 + r] : 0.0;
-  }
-  __syncthreads();
   const int Pc = P < N ? P : 0;
   double acc[DIAG_MAXP];
 #pragma unroll
   for (int p = 0; p < DIAG_MAXP; ++p) acc[p] = 0.0;
-  for (int r = grp; r < rows; r += 4) {
-    const int64_t m = m0 + r;
-    double b2;
-    if (cplx) {
-      const double2 v = reinterpret_cast<const double2 *>(B)[m * N + Pc];
-      b2 = v.x * v.x + v.y * v.y;
-    } else {
-      const double v = reinterpret_cast<const double *>(B)[m * N + Pc];
-      b2 = v * v;
-    }
+  for (int sc = 0; sc < spw; ++sc) {
+    const int64_t m0 = ((int64_t)c * spw + sc) * DIAG_ROWS;
+    if (m0 >= M) break;   // uniform over the workgroup
+    const int rows = (int)(M - m0 < DIAG_ROWS ? M - m0 : DIAG_ROWS);
+    double b2[RPG];
 #pragma unroll
-    for (int p = 0; p < DIAG_MAXP; ++p) acc[p] += wl[p][r] * b2;
+    for (int j = 0; j < RPG; ++j) {
+      const int r = grp + 4 * j;
+      const int64_t m = m0 + (r < rows ? r : 0);
+      if (cplx) {
+        const double2 v = reinterpret_cast<const double2 *>(B)[m * N + Pc];
+        b2[j] = v.x * v.x + v.y * v.y;
+      } else {
+        const double v = reinterpret_cast<const double *>(B)[m * N + Pc];
+        b2[j] = v * v;
+      }
+    }
+    __syncthreads();   // the previous sub-chunk's weights are no longer read
+    for (int e = threadIdx.x; e < DIAG_MAXP * DIAG_ROWS; e += 256) {
+      const int p = e / DIAG_ROWS, r = e % DIAG_ROWS;
+      wl[p][r] = (p < npts && r < rows) ? wtab[(int64_t)p * M + m0 + r] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RPG; ++j) {
+      const int r = grp + 4 * j;
+      if (r < rows) {
+#pragma unroll
+        for (int p = 0; p < DIAG_MAXP; ++p) acc[p] += wl[p][r] * b2[j];
+      }
+    }
   }
 #pragma unroll
   for (int p = 0; p < DIAG_MAXP; ++p) red[grp][p][col] = acc[p];
@@ -90,6 +105,23 @@ __global__ __launch_bounds__(256) void diag_partial_kernel(const void *B, int cp
       partial[((int64_t)c * npts + p) * N + P] = ((red[0][p][col] + red[1][p][col]) + red[2][p][col]) +
                                                  red[3][p][col];
   }
+}
+
+// sub-chunks per workgroup of the exact-diagonal pass, and the chunk count it gives
+inline int diag_spw(int64_t M, int N) {
+  const int64_t nsub = (M + DIAG_ROWS - 1) / DIAG_ROWS, ncb = (N + 63) / 64;
+  int64_t want = 2048 / ncb;   // chunks for about 2048 workgroups
+  if (want < 1) want = 1;
+  int64_t spw = (nsub + want - 1) / want;
+  if (spw < 1) spw = 1;
+  while ((nsub + spw - 1) / spw > 65535) ++spw;
+  return (int)spw;
+}
+
+inline int64_t diag_nchunks(int64_t M, int N) {
+  const int64_t nsub = (M + DIAG_ROWS - 1) / DIAG_ROWS;
+  const int spw = diag_spw(M, N);
+  return (nsub + spw - 1) / spw;
 }
 
 __global__ __launch_bounds__(256) void diag_reduce_kernel(const double *partial, int nchunks, int npts,
@@ -492,18 +524,20 @@ hipError_t launch_to_f32(hipStream_t s, const void *in, float2 *out, int64_t n, 
 }
 
 int64_t diag_exact_scratch_doubles(int64_t M, int N, int npts) {
-  const int64_t nchunks = (M + DIAG_ROWS - 1) / DIAG_ROWS;
+  const int64_t nchunks = diag_nchunks(M, N);
   const int per = npts < DIAG_MAXP ? npts : DIAG_MAXP;
   return nchunks * per * (int64_t)N;
 }
 
 hipError_t launch_diag_exact(hipStream_t s, const void *B, bool cplx, int64_t M, int N, const double *wtab,
                              int npts, double *scratch, double *diag) {
-  const int nchunks = (int)((M + DIAG_ROWS - 1) / DIAG_ROWS);
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const int nchunks = (int)diag_nchunks(M, N);
+  const int spw = diag_spw(M, N);
   for (int p0 = 0; p0 < npts; p0 += DIAG_MAXP) {
     const int np = npts - p0 < DIAG_MAXP ? npts - p0 : DIAG_MAXP;
     hipLaunchKernelGGL(diag_partial_kernel, dim3((unsigned)((N + 63) / 64), (unsigned)nchunks), dim3(256), 0,
-                       s, B, cplx ? 1 : 0, M, N, wtab + (int64_t)p0 * M, np, scratch);
+                       s, B, cplx ? 1 : 0, M, N, wtab + (int64_t)p0 * M, np, spw, scratch);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t tot = (int64_t)np * N;
