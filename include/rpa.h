@@ -62,9 +62,15 @@ typedef enum { RPA_MEM_HOST = 0, RPA_MEM_DEVICE = 1 } rpa_memspace;
 typedef struct rpa_ctx rpa_ctx;
 
 /*
- * One periodic system (Algorithm 1, "Require: C, eps_n"): regular grids with N_q = N_k.
- *  kq        [nq][nk]  int32: index of k (+) q in the k list.
- *  eps_occ   [nk][nocc], eps_virt [nk][nvirt]: Kohn-Sham band energies (Hartree).
+ * One periodic system (Algorithm 1, "Require: C, eps_n").  The contraction runs over the
+ * nk k-points of the regular grid for each of the nq q-points; Delta_kia(q) =
+ * eps_a(k) - eps_i(k (+) q).
+ *  kq        [nq][nk]  int32: row of eps_occ that holds k (+) q, in [0, nk_occ).
+ *  eps_occ   [nk_occ][nocc]: occupied band energies (Hartree) at every point k (+) q can
+ *            reach; eps_virt [nk][nvirt]: virtual band energies at the regular k.
+ *  nk_occ    rows of eps_occ; 0 means nk (regular grids, Q_G = K_G).  The dual grids of
+ *            Sec. 3.2 (Gamma removed from the q-grid, 2/4/8 displaced q-points added around
+ *            it) reach (N_add + 1) * nk points, so nk_occ = (N_add + 1) * nk there.
  *  zeta_k    [nk], zeta_q [nq]: integration weights; NULL means 1/nk and 1/nq.
  *  B         [nq][nk][nocc][nvirt][naux]: fit coefficients B^P_ia(k,q), P fastest
  *            (the MO-basis PADF coefficients of Sec. 2.2).  NULL means: generate them
@@ -85,6 +91,7 @@ typedef struct {
   uint64_t philox_seed;
   double sigma;
   const void *vhalf;
+  int32_t nk_occ;
 } rpa_system;
 
 /* Imaginary-frequency quadrature (host memory): nodes omega_j and weights W_j that

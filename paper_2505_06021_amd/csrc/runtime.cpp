@@ -172,8 +172,11 @@ int validate_system(const rpa_system *sys, HostSmall &hs) {
     return fail(RPA_E_ARG, "B is NULL (Philox) but sigma = %g is not positive", sys->sigma);
   hs.nk = sys->nk; hs.nq = sys->nq; hs.nocc = sys->nocc; hs.nvirt = sys->nvirt; hs.naux = sys->naux;
   hs.is_complex = sys->is_complex;
+  if (sys->nk_occ < 0 || sys->nk_occ > (1 << 24))
+    return fail(RPA_E_ARG, "nk_occ %d outside [0, 2^24]", sys->nk_occ);
+  const int32_t nk_occ = sys->nk_occ > 0 ? sys->nk_occ : sys->nk;
   hs.kq.resize((size_t)sys->nq * sys->nk);
-  hs.eps_occ.resize((size_t)sys->nk * sys->nocc);
+  hs.eps_occ.resize((size_t)nk_occ * sys->nocc);
   hs.eps_virt.resize((size_t)sys->nk * sys->nvirt);
   RPA_TRY(copy_in(hs.kq.data(), sys->kq, hs.kq.size() * 4, sys->memspace));
   RPA_TRY(copy_in(hs.eps_occ.data(), sys->eps_occ, hs.eps_occ.size() * 8, sys->memspace));
@@ -183,8 +186,8 @@ int validate_system(const rpa_system *sys, HostSmall &hs) {
   if (sys->zeta_k) RPA_TRY(copy_in(hs.zeta_k.data(), sys->zeta_k, (size_t)sys->nk * 8, sys->memspace));
   if (sys->zeta_q) RPA_TRY(copy_in(hs.zeta_q.data(), sys->zeta_q, (size_t)sys->nq * 8, sys->memspace));
   for (size_t i = 0; i < hs.kq.size(); ++i)
-    if (hs.kq[i] < 0 || hs.kq[i] >= sys->nk)
-      return fail(RPA_E_ARG, "kq[%zu] = %d outside [0, nk)", i, hs.kq[i]);
+    if (hs.kq[i] < 0 || hs.kq[i] >= nk_occ)
+      return fail(RPA_E_ARG, "kq[%zu] = %d outside [0, nk_occ = %d)", i, hs.kq[i], nk_occ);
   for (double v : hs.eps_occ) if (!std::isfinite(v)) return fail(RPA_E_ARG, "eps_occ not finite");
   for (double v : hs.eps_virt) if (!std::isfinite(v)) return fail(RPA_E_ARG, "eps_virt not finite");
   for (double v : hs.zeta_k) if (!std::isfinite(v)) return fail(RPA_E_ARG, "zeta_k not finite");

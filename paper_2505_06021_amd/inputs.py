@@ -12,7 +12,10 @@ so slab-shaped synthetic systems of the paper's sizes stand in for them):
 
 * k-grids are regular n1 x n2 x n3 grids in reduced coordinates kappa_d = n_d/N_d,
   and Q_G equals K_G (regular grids, Sec. "Dual grids", the regular-grid case);
-  k (+) q is index addition modulo the grid in every direction.
+  k (+) q is index addition modulo the grid in every direction.  make_dual_system
+  builds the dual grids of that section instead: Gamma removed from the q-grid, 2^D
+  points sum_i (+-d_i) b_i added around it (D directions with more than one point,
+  d_i = frac/N_i), and K_G = {k_j + q}; the occupied energies are then given on K_G.
 * Band energies: eps0_i ~ U[-1.0,-0.3] Ha (occupied), eps0_a ~ U[0.05,3.0] Ha
   (virtual), plus a band-independent dispersion 0.1*cos(2 pi (k1+k2+k3)) for
   periodic systems, so every transition energy is >= 0.15 Ha (insulator, as the
@@ -155,6 +158,54 @@ def kgrid(grid):
     return kappa, kq
 
 
+def dual_grids(grid, frac=0.1):
+    """Dual k/q grids (Sec. 3.2, enhanced sampling around Gamma).
+
+    K_reg is the regular grid.  Q_G is the regular q-grid without Gamma plus N_add = 2^D
+    points sum_i (+-d_i) b_i, D the number of directions with more than one point and
+    d_i = frac / N_i (frac = 0.1 is the one-tenth spacing the paper uses).  K_G holds every
+    k_j + q with k_j in K_reg and q in Q_G (the travel relation k_j + q = k_i), K_reg first:
+    for regular grids that is (N_add + 1) |K_reg| points.
+
+    Returns (kappa_reg [N_k, 3], kappa_q [N_q, 3], kappa_g [N_G, 3], kq [N_q, N_k] rows of
+    kappa_g, zeta_q [N_q]).  Weights: 1/N_k for each regular q and 1/(N_k N_add) for each
+    displaced one, i.e. Gamma's weight shared evenly among the points that replace it (the
+    paper gives no weights; this keeps sum zeta_q = 1).
+    """
+    n = np.array(grid, dtype=np.int64)
+    kappa_reg, _ = kgrid(grid)
+    nk = len(kappa_reg)
+    dirs = [d for d in range(3) if n[d] > 1]
+    if not dirs:
+        raise ValueError("a dual grid needs at least one direction with more than one k-point")
+    disp = []
+    for signs in range(1 << len(dirs)):
+        x = np.zeros(3)
+        for b, d in enumerate(dirs):
+            x[d] = (-1.0 if (signs >> b) & 1 else 1.0) * frac / n[d]
+        disp.append(x)
+    kappa_q = np.concatenate([kappa_reg[1:], np.array(disp)], axis=0)   # row 0 of kgrid is Gamma
+    nadd = len(disp)
+    zeta_q = np.concatenate([np.full(nk - 1, 1.0 / nk), np.full(nadd, 1.0 / (nk * nadd))])
+
+    def key(x):
+        f = np.mod(x, 1.0)
+        f = np.where(np.abs(f - 1.0) < 1e-12, 0.0, f)
+        return tuple(np.round(f, 10))
+
+    pts = [np.mod(k, 1.0) for k in kappa_reg]
+    index = {key(k): i for i, k in enumerate(pts)}
+    kq = np.empty((len(kappa_q), nk), dtype=np.int32)
+    for iq, q in enumerate(kappa_q):
+        for ik, k in enumerate(kappa_reg):
+            t = key(k + q)
+            if t not in index:
+                index[t] = len(pts)
+                pts.append(np.array(t))
+            kq[iq, ik] = index[t]
+    return kappa_reg, kappa_q, np.array(pts), kq, zeta_q
+
+
 def qnorm2(kappa):
     """|q|^2 with the reduced coordinates folded into [-1/2, 1/2) (lattice constant 1)."""
     f = (kappa + 0.5) % 1.0 - 0.5
@@ -214,8 +265,8 @@ class System:
     nvirt: int
     naux: int
     is_complex: bool
-    kq: np.ndarray          # int32 [nq][nk]
-    eps_occ: np.ndarray     # f64 [nk][nocc]
+    kq: np.ndarray          # int32 [nq][nk], rows of eps_occ
+    eps_occ: np.ndarray     # f64 [nk_occ][nocc] (nk_occ = nk on regular grids)
     eps_virt: np.ndarray    # f64 [nk][nvirt]
     zeta_k: np.ndarray      # f64 [nk]
     zeta_q: np.ndarray      # f64 [nq]
@@ -229,6 +280,10 @@ class System:
     @property
     def nw(self):
         return len(self.omega)
+
+    @property
+    def nk_occ(self):
+        return int(self.eps_occ.shape[0])
 
     @property
     def M(self):
@@ -288,6 +343,34 @@ def make_system(name, grid, nocc, nvirt, naux, nw, seed, is_complex=True, sigma=
                   vhalf=vhalf, omega=omega, weight=weight, seed=int(seed), sigma=float(sigma))
 
 
+def make_dual_system(name, grid, nocc, nvirt, naux, nw, seed, frac=0.1, is_complex=True, sigma=None,
+                     vhalf_seed=None):
+    """A seeded synthetic system on the dual grids of dual_grids(grid, frac).
+
+    Band energies follow make_system's recipe (the dispersion evaluated at K_G for the
+    occupied bands, at K_reg for the virtual ones), V^(1/2)(q) is drawn for every q of
+    Q_G with f(q) = 1 + 1/|q|^2 (no Gamma head: Gamma is not in Q_G), and B^P_ia(k,q)
+    comes from the same Philox stream keyed by the Q_G index q and the K_reg index k.
+    """
+    kappa_reg, kappa_q, kappa_g, kq, zeta_q = dual_grids(grid, frac)
+    nk, nq = len(kappa_reg), len(kappa_q)
+    if sigma is None:
+        sigma = math.sqrt(1.61 / (nocc * nvirt))
+    rng = np.random.default_rng(seed)
+    e0_occ = rng.uniform(-1.0, -0.3, size=nocc)
+    e0_virt = rng.uniform(0.05, 3.0, size=nvirt)
+    eps_occ = e0_occ[None, :] + 0.1 * np.cos(2.0 * np.pi * kappa_g.sum(axis=1))[:, None]
+    eps_virt = e0_virt[None, :] + 0.1 * np.cos(2.0 * np.pi * kappa_reg.sum(axis=1))[:, None]
+    vrng = np.random.default_rng(seed + 7919 if vhalf_seed is None else vhalf_seed)
+    vhalf = coulomb_sqrt(vrng, naux, kappa_q, is_complex, True)
+    omega, weight = frequency_grid(nw)
+    return System(name=name, grid=tuple(grid), nk=nk, nq=nq, nocc=nocc, nvirt=nvirt,
+                  naux=naux, is_complex=bool(is_complex), kq=kq,
+                  eps_occ=np.ascontiguousarray(eps_occ), eps_virt=np.ascontiguousarray(eps_virt),
+                  zeta_k=np.full(nk, 1.0 / nk), zeta_q=zeta_q,
+                  vhalf=vhalf, omega=omega, weight=weight, seed=int(seed), sigma=float(sigma))
+
+
 # The five workloads of the benchmark plan, by what they are.
 def gamma_real_128(seed=1234):
     """Gamma-only real system: N_occ 8, N_virt 56, N_aux 128, 8 frequencies, B ~ N(0, 0.05^2)."""
@@ -309,6 +392,13 @@ def slab_6x6_1200(seed=4242):
 def slab_3x3_2400(seed=9001):
     """3x3x1 slab, N_occ 96, N_virt 900, N_aux 2400, 16 frequencies (B streamed)."""
     return make_system("slab3x3_naux2400", (3, 3, 1), 96, 900, 2400, 16, seed)
+
+
+def slab_3x3_dual_384(seed=3031):
+    """The 3x3x1 N_aux 384 slab on dual grids (Gamma replaced by 4 points at 1/10 of the
+    grid step): 12 q-points, 45 k-points for the occupied bands, 12 frequencies."""
+    return make_dual_system("slab3x3_dual_naux384", (3, 3, 1), 16, 112, 384, 12, seed, frac=0.1,
+                            is_complex=True, sigma=0.03)
 
 
 def serving_jobs(njobs=256, rate=4.0, seed=77, naux_range=(200, 1500)):

@@ -37,7 +37,8 @@ class RpaSystemC(C.Structure):
                 ("naux", C.c_int32), ("is_complex", C.c_int32), ("memspace", C.c_int32),
                 ("kq", C.c_void_p), ("eps_occ", C.c_void_p), ("eps_virt", C.c_void_p),
                 ("zeta_k", C.c_void_p), ("zeta_q", C.c_void_p), ("B", C.c_void_p),
-                ("philox_seed", C.c_uint64), ("sigma", C.c_double), ("vhalf", C.c_void_p)]
+                ("philox_seed", C.c_uint64), ("sigma", C.c_double), ("vhalf", C.c_void_p),
+                ("nk_occ", C.c_int32)]
 
 
 class RpaFreqC(C.Structure):
@@ -170,6 +171,7 @@ class _Marshal:
         s.philox_seed = system.seed
         s.sigma = system.sigma
         s.vhalf = put(system.vhalf, vdt)
+        s.nk_occ = int(np.asarray(system.eps_occ).shape[0])
         if device:
             import torch
             torch.cuda.synchronize()   # the uploads ran on torch's stream
