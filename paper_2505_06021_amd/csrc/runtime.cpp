@@ -352,9 +352,11 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
     for (size_t g0 = 0; g0 < qs.size(); g0 += gq) max_group_pts = std::max(max_group_pts, pts_of((int)g0, gq));
     pbatch = std::min<int64_t>(pb_cap, (max_group_pts + nlanes - 1) / nlanes);
     // points per split-BF16 sub-launch: as many as the rest of the budget holds
-    // (one launch for a whole batch where memory allows: fewer row splits, so less partial
-    // traffic, and each B slab is read once per run of its points)
-    rbatch = bsplit ? std::min<int64_t>(pbatch, 128) : 0;
+    // (a synchronous call takes one launch for a whole batch where memory allows: fewer
+    // row splits, so less partial traffic, and each B slab is read once per run of its
+    // points; a served job keeps launches of at most 16 points, which the fuser can merge
+    // with other jobs' and which let concurrent jobs interleave)
+    rbatch = bsplit ? std::min<int64_t>(pbatch, use_cache ? 128 : 16) : 0;
     while (rbatch > 1 && pbatch * per_pt + bsplit_bytes(rbatch) > rest / nlanes) rbatch = rbatch * 3 / 4;
     if (bsplit && rbatch < 1) rbatch = 1;
     break;

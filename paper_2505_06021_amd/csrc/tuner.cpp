@@ -1,6 +1,7 @@
 // Autotuner of the chi0 contractions' tile shapes: the FP64 contraction's tile and
 // K-step depth, and the FP32 and split-BF16 contractions' tile edges (64 or 128;
-// RPA_F32_TILE and RPA_BF16_TILE fix them).
+// RPA_F32_TILE and RPA_BF16_TILE fix them; RPA_TUNE_VERBOSE=1 prints the timings of the
+// reduced-precision candidates).
 //
 // Candidates (launch_chi0_f64 configurations): 64-wide tiles with 8, 16 or 32 rows per
 // LDS step (two workgroups per CU) and 128-wide tiles with 16-row steps (one per CU).
@@ -237,10 +238,11 @@ int tune_f32_tile(hipStream_t st, const Chi0Args &a, int npts, bool cplx, const 
     *tile_out = it->second;
     return RPA_OK;
   }
-  // both tile edges on the first 4096 rows, one row split, into the launch's own output
-  // (overwritten by the real launch)
+  // both tile edges on the first 16384 rows, one row split, into the launch's own output
+  // (overwritten by the real launch); long enough that each workgroup reaches its steady
+  // state (short runs favour the 64-wide tile)
   Chi0Args t = a;
-  t.M = a.M < 4096 ? a.M : 4096;
+  t.M = a.M < 16384 ? a.M : 16384;
   t.ksplit = 1;
   const int cands[2] = {64, 128};
   float best_ms = 1e30f;
@@ -256,6 +258,9 @@ int tune_f32_tile(hipStream_t st, const Chi0Args &a, int npts, bool cplx, const 
       RPA_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
       RPA_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (rep == 1 && getenv("RPA_TUNE_VERBOSE"))
+        fprintf(stderr, "[tune] %s t%d: %.4f ms (%lld rows, %d points)\n", key.c_str(), tile, ms, (long long)t.M,
+                npts);
       if (rep == 1 && ms < best_ms) {
         best_ms = ms;
         best = tile;
