@@ -75,7 +75,7 @@ __device__ __forceinline__ void split_pair(double x0, double x1, unsigned &hi, u
 // (workgroup row chunk, point, column).
 constexpr int PREP_STEPS = 4;
 
-template <bool CPLX>
+template <bool CPLX, bool NTS>
 __global__ __launch_bounds__(256) void bf16_prepare_kernel(const void *B, int64_t M, int N, int Np,
                                                            const double *wtab, int64_t w_stride, int np,
                                                            unsigned short *out, int64_t out_stride,
@@ -147,12 +147,29 @@ __global__ __launch_bounds__(256) void bf16_prepare_kernel(const void *B, int64_
           if (q == p) dsum[q] += d;
       }
       uint4 *o = reinterpret_cast<uint4 *>(out + (int64_t)p * out_stride);
-      // 16-byte units: plane base ((kc * 4 + plane) * Np + n) * 4, then the segment
-      o[((kc * 4 + 0) * Np + n) * 4 + unit] = make_uint4(hr[0], hr[1], hr[2], hr[3]);
-      o[((kc * 4 + 1) * Np + n) * 4 + unit] = make_uint4(lr[0], lr[1], lr[2], lr[3]);
-      if (CPLX) {
-        o[((kc * 4 + 2) * Np + n) * 4 + unit] = make_uint4(hi_[0], hi_[1], hi_[2], hi_[3]);
-        o[((kc * 4 + 3) * Np + n) * 4 + unit] = make_uint4(li_[0], li_[1], li_[2], li_[3]);
+      // 16-byte units: plane base ((kc * 4 + plane) * Np + n) * 4, then the segment.  The
+      // right operands (one per point, far more than the caches hold) are written with
+      // non-temporal stores; the left operand, read again soon, through the caches.
+      typedef unsigned u4v __attribute__((ext_vector_type(4)));
+      u4v *o0 = reinterpret_cast<u4v *>(&o[((kc * 4 + 0) * Np + n) * 4 + unit]);
+      u4v *o1 = reinterpret_cast<u4v *>(&o[((kc * 4 + 1) * Np + n) * 4 + unit]);
+      u4v *o2 = reinterpret_cast<u4v *>(&o[((kc * 4 + 2) * Np + n) * 4 + unit]);
+      u4v *o3 = reinterpret_cast<u4v *>(&o[((kc * 4 + 3) * Np + n) * 4 + unit]);
+      const u4v vhr = {hr[0], hr[1], hr[2], hr[3]}, vlr = {lr[0], lr[1], lr[2], lr[3]};
+      if (NTS) {
+        __builtin_nontemporal_store(vhr, o0);
+        __builtin_nontemporal_store(vlr, o1);
+        if (CPLX) {
+          __builtin_nontemporal_store(u4v{hi_[0], hi_[1], hi_[2], hi_[3]}, o2);
+          __builtin_nontemporal_store(u4v{li_[0], li_[1], li_[2], li_[3]}, o3);
+        }
+      } else {
+        *o0 = vhr;
+        *o1 = vlr;
+        if (CPLX) {
+          *o2 = u4v{hi_[0], hi_[1], hi_[2], hi_[3]};
+          *o3 = u4v{li_[0], li_[1], li_[2], li_[3]};
+        }
       }
     }
     __syncthreads();   // tb and wl are refilled by the next step
@@ -543,12 +560,16 @@ hipError_t launch_bf16_prepare(hipStream_t s, const void *B, bool cplx, int64_t 
     const double *w = wtab ? wtab + (int64_t)p0 * M : nullptr;
     const dim3 grid((unsigned)nchunks, (unsigned)(Np / PREP_COLS));
     double *dp = want_diag ? dscratch : nullptr;
-    if (cplx)
-      hipLaunchKernelGGL(bf16_prepare_kernel<true>, grid, dim3(256), 0, s, B, M, N, Np, w, M, np,
-                         out + (int64_t)p0 * stride, stride, dp);
-    else
-      hipLaunchKernelGGL(bf16_prepare_kernel<false>, grid, dim3(256), 0, s, B, M, N, Np, w, M, np,
-                         out + (int64_t)p0 * stride, stride, dp);
+    // right operands (w set) with non-temporal stores, the left operand through the caches
+#define RPA_PREP_LAUNCH(C, NT)                                                                       \
+  hipLaunchKernelGGL((bf16_prepare_kernel<C, NT>), grid, dim3(256), 0, s, B, M, N, Np, w, M, np, \
+                     out + (int64_t)p0 * stride, stride, dp)
+    if (cplx) {
+      if (w) RPA_PREP_LAUNCH(true, true); else RPA_PREP_LAUNCH(true, false);
+    } else {
+      if (w) RPA_PREP_LAUNCH(false, true); else RPA_PREP_LAUNCH(false, false);
+    }
+#undef RPA_PREP_LAUNCH
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (want_diag) {
