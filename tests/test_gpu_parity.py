@@ -264,6 +264,31 @@ def test_argument_errors(ctx):
     assert e.value.code == rpa.RPA_E_ARG
 
 
+def test_degenerate_and_out_of_range_inputs_are_errors(ctx):
+    # empty frequency grid, a negative node, N_aux beyond the supported 16384, a negative
+    # occupied-row count, a k (+) q row beyond a dual grid's occupied energies
+    from paper_2505_06021_amd import rpa
+    say("degenerate inputs")
+    cases = []
+    s = ragged_system(nw=2)
+    s.omega, s.weight = s.omega[:0], s.weight[:0]
+    cases.append(s)
+    s = ragged_system(nw=2)
+    s.omega = s.omega.copy()
+    s.omega[0] = -1.0
+    cases.append(s)
+    s = ragged_system(nw=2)
+    s.naux = 16385
+    cases.append(s)
+    s = inputs.make_dual_system("dual_err", (2, 2, 1), 2, 3, 8, 2, 5, frac=0.1)
+    s.eps_occ = s.eps_occ[: s.nk]      # only the regular grid's rows: displaced k (+) q out of range
+    cases.append(s)
+    for s in cases:
+        with pytest.raises(rpa.RpaError) as e:
+            ctx.energy(s)
+        assert e.value.code == rpa.RPA_E_ARG, s.name
+
+
 def test_hbm_limit_is_enforced():
     from paper_2505_06021_amd import rpa
     say("hbm limit")
