@@ -106,19 +106,17 @@ def philox_words(seed: int, nk: int, iq: int, ik: int, e0: int, count: int):
     return np.stack(w, axis=-1).astype(np.uint32)
 
 
-def philox_B_rows(seed: int, sigma: float, nk: int, iq: int, ik: int,
-                  nvirt: int, naux: int, is_complex: bool, i0: int, i1: int):
-    """B^P_ia(k,q) for occupied rows i0 <= i < i1 of block (q, k).
-
-    Returns an array of shape [i1-i0, nvirt, naux], complex128 or float64.
-    """
-    per_i = nvirt * naux
-    e = np.arange(i0 * per_i, i1 * per_i, dtype=np.uint64)
+def philox_normals(seed: int, sigma: float, nk: int, iq: int, ik: int, e0: int, e1: int,
+                   is_complex: bool, stream: int = 0):
+    """Elements e0 <= e < e1 of the normal stream of block (q, k): CN(0, sigma^2) or
+    N(0, sigma^2).  The third counter word selects the stream (0: B, 1: pair-fit C)."""
+    e = np.arange(e0, e1, dtype=np.uint64)
     k0, k1 = philox_key(seed, nk, iq, ik)
     zero = np.zeros_like(e)
-    w0, w1, w2, w3 = philox4x32_10((e & _MASK32, e >> np.uint64(32), zero, zero),
+    third = np.full_like(e, np.uint64(stream))
+    w0, w1, w2, w3 = philox4x32_10((e & _MASK32, e >> np.uint64(32), third, zero),
                                    (np.uint64(k0), np.uint64(k1)))
-    del e, zero
+    del e, zero, third
     u1 = _uniform_pair(w0, w1)
     u2 = _uniform_pair(w2, w3)
     del w0, w1, w2, w3
@@ -131,7 +129,26 @@ def philox_B_rows(seed: int, sigma: float, nk: int, iq: int, ik: int,
         out.imag = s * r * np.sin(theta)
     else:
         out = sigma * r * np.cos(theta)
+    return out
+
+
+def philox_B_rows(seed: int, sigma: float, nk: int, iq: int, ik: int,
+                  nvirt: int, naux: int, is_complex: bool, i0: int, i1: int):
+    """B^P_ia(k,q) for occupied rows i0 <= i < i1 of block (q, k).
+
+    Returns an array of shape [i1-i0, nvirt, naux], complex128 or float64.
+    """
+    per_i = nvirt * naux
+    out = philox_normals(seed, sigma, nk, iq, ik, i0 * per_i, i1 * per_i, is_complex, 0)
     return out.reshape(i1 - i0, nvirt, naux)
+
+
+def philox_C_block(seed: int, sigma: float, nk: int, iq: int, ik: int, nbas: int, naux: int):
+    """Pair-fit coefficients C^{mu nu}_gamma(k, q) of block (q, k), complex [nbas, nbas, naux]
+    (mu pairs with the band at k, nu with the band at k (+) q): stream 1 of the same
+    Philox key, element e = (mu * nbas + nu) * naux + gamma."""
+    n = nbas * nbas * naux
+    return philox_normals(seed, sigma, nk, iq, ik, 0, n, True, 1).reshape(nbas, nbas, naux)
 
 
 def philox_B_block(seed, sigma, nk, iq, ik, nocc, nvirt, naux, is_complex):
@@ -276,6 +293,14 @@ class System:
     seed: int
     sigma: float
     B: Optional[np.ndarray] = None   # explicit [nq][nk][nocc][nvirt][naux] or None (Philox)
+    # atomic-orbital data (nbas > 0): B is then the MO transform of Philox pair-fit
+    # coefficients C(k, q) with the projected KS coefficients (see make_ao_system)
+    nbas: int = 0
+    c_occ: Optional[np.ndarray] = None    # projected, [nk_occ][nbas][nocc] (at every k (+) q)
+    c_virt: Optional[np.ndarray] = None   # projected, [nk][nbas][nvirt]
+    S_ao: Optional[np.ndarray] = None     # overlap S(k), [nk][nbas][nbas]
+    c_raw: Optional[np.ndarray] = None    # KS coefficients before the projector, [nk][nbas][nocc+nvirt]
+    eps_d: float = 0.0                    # projector threshold on the eigenvalues of S(k)
 
     @property
     def nw(self):
@@ -291,6 +316,9 @@ class System:
 
     def B_rows(self, iq, ik, i0, i1):
         """B[q][k][i0:i1] from the explicit array or the Philox stream."""
+        if self.nbas > 0:
+            raise ValueError("the B of an atomic-orbital system is the MO transform of its pair-fit "
+                             "coefficients; it is not an input")
         if self.B is not None:
             return self.B[iq, ik, i0:i1]
         return philox_B_rows(self.seed, self.sigma, self.nk, iq, ik, self.nvirt,
@@ -341,6 +369,60 @@ def make_system(name, grid, nocc, nvirt, naux, nw, seed, is_complex=True, sigma=
                   eps_occ=np.ascontiguousarray(eps_occ), eps_virt=np.ascontiguousarray(eps_virt),
                   zeta_k=np.full(nk, 1.0 / nk), zeta_q=np.full(nk, 1.0 / nk),
                   vhalf=vhalf, omega=omega, weight=weight, seed=int(seed), sigma=float(sigma))
+
+
+def make_ao_system(name, grid, nbas, nocc, nvirt, naux, nw, seed, n_lowdep=4, eps_d=1e-4, sigma=None):
+    """A seeded synthetic system given in an atomic-orbital basis.
+
+    Per k: an overlap S(k) = U diag(d) U^H (U Haar unitary) whose n_lowdep lowest
+    eigenvalues are 10^U[-8,-6] (near-linear dependencies, below eps_d) and the rest
+    U[0.5, 2]; KS coefficients c = U_keep d_keep^(-1/2) Q (Q Haar, so c^H S c = 1 on the
+    retained subspace) for the nocc + nvirt bands, handed over with a contamination along
+    the dropped directions (c_raw = c + U_low N, N ~ 0.1 N(0,1)).  The projector of the
+    paper's periodic projector method removes exactly that contamination, so the projected
+    coefficients are c itself; they are stored as c_occ and c_virt.  Band energies follow
+    make_system's recipe; the pair-fit coefficients are Philox stream 1 (philox_C_block).
+    """
+    kappa, kq = kgrid(grid)
+    nk = len(kappa)
+    nkeep = nbas - n_lowdep
+    nband = nocc + nvirt
+    if nkeep < nband:
+        raise ValueError("nbas - n_lowdep must be at least nocc + nvirt")
+    if sigma is None:
+        sigma = math.sqrt(1.61 / (nocc * nvirt))
+    rng = np.random.default_rng(seed)
+    e0_occ = rng.uniform(-1.0, -0.3, size=nocc)
+    e0_virt = rng.uniform(0.05, 3.0, size=nvirt)
+    disp = 0.1 * np.cos(2.0 * np.pi * kappa.sum(axis=1)) if nk > 1 else np.zeros(nk)
+    eps_occ = e0_occ[None, :] + disp[:, None]
+    eps_virt = e0_virt[None, :] + disp[:, None]
+    arng = np.random.default_rng(seed + 104729)
+    S = np.empty((nk, nbas, nbas), dtype=np.complex128)
+    c_clean = np.empty((nk, nbas, nband), dtype=np.complex128)
+    c_raw = np.empty_like(c_clean)
+    for ik in range(nk):
+        U = haar_unitary(arng, nbas, True)
+        d = np.concatenate([np.sort(10.0 ** arng.uniform(-8.0, -6.0, size=n_lowdep)),
+                            np.sort(arng.uniform(0.5, 2.0, size=nkeep))])
+        Sk = (U * d[None, :]) @ U.conj().T
+        S[ik] = 0.5 * (Sk + Sk.conj().T)
+        Q = haar_unitary(arng, nkeep, True)[:, :nband]
+        c = (U[:, n_lowdep:] * (1.0 / np.sqrt(d[n_lowdep:]))[None, :]) @ Q
+        noise = 0.1 * (arng.standard_normal((n_lowdep, nband)) + 1j * arng.standard_normal((n_lowdep, nband)))
+        c_clean[ik] = c
+        c_raw[ik] = c + U[:, :n_lowdep] @ noise
+    vrng = np.random.default_rng(seed + 7919)
+    vhalf = coulomb_sqrt(vrng, naux, kappa, True, nk > 1)
+    omega, weight = frequency_grid(nw)
+    return System(name=name, grid=tuple(grid), nk=nk, nq=nk, nocc=nocc, nvirt=nvirt,
+                  naux=naux, is_complex=True, kq=kq,
+                  eps_occ=np.ascontiguousarray(eps_occ), eps_virt=np.ascontiguousarray(eps_virt),
+                  zeta_k=np.full(nk, 1.0 / nk), zeta_q=np.full(nk, 1.0 / nk),
+                  vhalf=vhalf, omega=omega, weight=weight, seed=int(seed), sigma=float(sigma),
+                  nbas=int(nbas), c_occ=np.ascontiguousarray(c_clean[:, :, :nocc]),
+                  c_virt=np.ascontiguousarray(c_clean[:, :, nocc:]), S_ao=S, c_raw=c_raw,
+                  eps_d=float(eps_d))
 
 
 def make_dual_system(name, grid, nocc, nvirt, naux, nw, seed, frac=0.1, is_complex=True, sigma=None,
@@ -399,6 +481,13 @@ def slab_3x3_dual_384(seed=3031):
     grid step): 12 q-points, 45 k-points for the occupied bands, 12 frequencies."""
     return make_dual_system("slab3x3_dual_naux384", (3, 3, 1), 16, 112, 384, 12, seed, frac=0.1,
                             is_complex=True, sigma=0.03)
+
+
+def slab_3x3_ao_384(seed=5050):
+    """The 3x3x1 N_aux 384 slab given in an atomic-orbital basis of 144 functions (4 of them
+    near-linearly dependent): B is built on the fly from Philox pair-fit coefficients."""
+    return make_ao_system("slab3x3_ao_naux384", (3, 3, 1), 144, 16, 112, 384, 12, seed, n_lowdep=4,
+                          eps_d=1e-4, sigma=0.03)
 
 
 def serving_jobs(njobs=256, rate=4.0, seed=77, naux_range=(200, 1500)):

@@ -18,6 +18,19 @@ import math
 import numpy as np
 
 
+def ao_block(system, iq, ik):
+    """B[i][a][gamma] of an atomic-orbital system, one gamma at a time as the matrix product
+    (c_virt(k)^H C_gamma c_occ(k (+) q))^T, from the generator's projected coefficients."""
+    from paper_2505_06021_amd import inputs
+    C = inputs.philox_C_block(system.seed, system.sigma, system.nk, iq, ik, system.nbas, system.naux)
+    cv = system.c_virt[ik]
+    co = system.c_occ[system.kq[iq, ik]]
+    out = np.empty((system.nocc, system.nvirt, system.naux), dtype=np.complex128)
+    for g in range(system.naux):
+        out[:, :, g] = (cv.conj().T @ C[:, :, g] @ co).T
+    return out
+
+
 def transitions(system, iq):
     """Delta_x, c_x and the [M, N_aux] coefficient matrix B of one q, built directly."""
     rows, deltas, cs = [], [], []
@@ -27,7 +40,8 @@ def transitions(system, iq):
             for a in range(system.nvirt):
                 deltas.append(system.eps_virt[ik, a] - system.eps_occ[kq, i])
                 cs.append(2.0 * system.zeta_k[ik])
-        rows.append(system.B_block(iq, ik).reshape(-1, system.naux))
+        blk = ao_block(system, iq, ik) if system.nbas > 0 else system.B_block(iq, ik)
+        rows.append(blk.reshape(-1, system.naux))
     return np.array(deltas), np.array(cs), np.concatenate(rows, axis=0)
 
 
