@@ -64,8 +64,7 @@ def projected_coefficients(system):
 
 def ao_B_block(system, ct, iq, ik):
     """B[i][a][gamma] of block (q, k) by the MO transform  (step 0b)."""
-    from paper_2505_06021_amd import inputs
-    C = inputs.philox_C_block(system.seed, system.sigma, system.nk, iq, ik, system.nbas, system.naux)
+    C = system.C_block(iq, ik)
     cv = ct[ik][:, system.nocc:]
     co = ct[system.kq[iq, ik]][:, :system.nocc]
     return np.einsum("ma,mng,ni->iag", cv.conj(), C, co, optimize=True)

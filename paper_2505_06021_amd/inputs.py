@@ -327,6 +327,10 @@ class System:
     def B_block(self, iq, ik):
         return self.B_rows(iq, ik, 0, self.nocc)
 
+    def C_block(self, iq, ik):
+        """Pair-fit coefficients C^{mu nu}_gamma(k, q) of an atomic-orbital system."""
+        return philox_C_block(self.seed, self.sigma, self.nk, iq, ik, self.nbas, self.naux)
+
     def materialize_B(self):
         """Attach the explicit B array (small systems only)."""
         dt = np.complex128 if self.is_complex else np.float64
