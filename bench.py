@@ -29,6 +29,7 @@ WORKLOADS = {
     "slab6x6_naux1200": "slab_6x6_1200",
     "slab3x3_naux2400": "slab_3x3_2400",
     "slab3x3_dual_naux384": "slab_3x3_dual_384",
+    "slab3x3_ao_naux384": "slab_3x3_ao_384",
 }
 
 
@@ -261,7 +262,7 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f64"}[args.prec],
         "data": "synthetic (seeded Philox B, Haar-random V, GL frequencies)",
-        "config": {"workload": args.workload, "grid": list(s.grid), "nk": s.nk, "nq": s.nq, "nk_occ": s.nk_occ,
+        "config": {"workload": args.workload, "grid": list(s.grid), "nk": s.nk, "nq": s.nq, "nk_occ": s.nk_occ, "nbas": s.nbas,
                    "nocc": s.nocc, "nvirt": s.nvirt, "naux": s.naux, "nw": s.nw,
                    "is_complex": s.is_complex, "chi0_precision": args.prec,
                    "B": "Philox4x32-10 on device", "parallelism": "single GPU",

@@ -71,6 +71,13 @@ typedef struct rpa_ctx rpa_ctx;
  *  nk_occ    rows of eps_occ; 0 means nk (regular grids, Q_G = K_G).  The dual grids of
  *            Sec. 3.2 (Gamma removed from the q-grid, 2/4/8 displaced q-points added around
  *            it) reach (N_add + 1) * nk points, so nk_occ = (N_add + 1) * nk there.
+ *  nbas      0, or the size of an atomic-orbital basis: B is then built on the device by
+ *            the MO transform of Sec. 2.2, B^P_ia(k,q) = sum_{mu nu} conj(c_virt[k][mu][a])
+ *            C^{mu nu}_P(k,q) c_occ[k (+) q][nu][i], with the pair-fit coefficients C drawn
+ *            from Philox stream 1 of B's key (philox_seed, sigma; element
+ *            e = (mu * nbas + nu) * naux + P).  Requires is_complex = 1 and B = NULL.
+ *  c_occ     [nk_occ][nbas][nocc], c_virt [nk][nbas][nvirt]: KS coefficients (complex)
+ *            after the periodic projector of Sec. 2.3 (T(k) c, applied by the caller).
  *  zeta_k    [nk], zeta_q [nq]: integration weights; NULL means 1/nk and 1/nq.
  *  B         [nq][nk][nocc][nvirt][naux]: fit coefficients B^P_ia(k,q), P fastest
  *            (the MO-basis PADF coefficients of Sec. 2.2).  NULL means: generate them
@@ -92,6 +99,9 @@ typedef struct {
   double sigma;
   const void *vhalf;
   int32_t nk_occ;
+  int32_t nbas;
+  const void *c_occ;
+  const void *c_virt;
 } rpa_system;
 
 /* Imaginary-frequency quadrature (host memory): nodes omega_j and weights W_j that

@@ -149,7 +149,23 @@ int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega, rpa_
   if (!B || sys->memspace == RPA_MEM_HOST) {
     void *buf;
     RPA_TRY(c.workspace("B", M * N * belem, &buf));
-    if (!B) {
+    if (!B && hs.nbas > 0) {
+      // atomic-orbital system: the MO transform of the pair-fit coefficients, per k block
+      void *cbuf, *scr;
+      const int64_t cbytes = (int64_t)(hs.c_occ.size() + hs.c_virt.size()) * 8;
+      RPA_TRY(c.workspace("ao_coeff", cbytes, &cbuf));
+      RPA_TRY(c.workspace("ao_scratch", ao_scratch_bytes(hs.nbas, hs.nocc, N), &scr));
+      double2 *co = reinterpret_cast<double2 *>(cbuf);
+      double2 *cv = co + hs.c_occ.size() / 2;
+      RPA_HIP(hipMemcpyAsync(co, hs.c_occ.data(), hs.c_occ.size() * 8, hipMemcpyHostToDevice, c.stream));
+      RPA_HIP(hipMemcpyAsync(cv, hs.c_virt.data(), hs.c_virt.size() * 8, hipMemcpyHostToDevice, c.stream));
+      const int64_t per_k = (int64_t)hs.nocc * hs.nvirt * N;
+      for (int ik = 0; ik < hs.nk; ++ik)
+        RPA_HIP(launch_ao_B(c.stream, sys->philox_seed, sys->sigma, hs.nk, iq, ik, hs.nbas, hs.nocc, hs.nvirt, N,
+                            co + (int64_t)hs.kq[(size_t)iq * hs.nk + ik] * hs.nbas * hs.nocc,
+                            cv + (int64_t)ik * hs.nbas * hs.nvirt, scr,
+                            reinterpret_cast<double2 *>(buf) + (int64_t)ik * per_k));
+    } else if (!B) {
       RPA_HIP(launch_philox_B(c.stream, sys->philox_seed, sys->sigma, hs.nk, iq, 0, hs.nk, hs.nocc,
                               hs.nvirt, N, cplx, buf));
     } else {

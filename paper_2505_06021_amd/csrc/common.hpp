@@ -52,6 +52,20 @@ struct GemmArgs {
 hipError_t launch_philox_B(hipStream_t s, uint64_t seed, double sigma, int32_t nk, int32_t iq,
                            int32_t k0, int32_t k1, int32_t nocc, int32_t nvirt, int32_t naux,
                            bool cplx, void *out);
+// Pair-fit coefficients C^{mu nu}_gamma(k,q) of block (q, k) of an atomic-orbital system,
+// complex [nbas][nbas][naux]: Philox stream 1 of the key of B's block (q, k), element
+// e = (mu * nbas + nu) * naux + gamma.
+hipError_t launch_philox_C(hipStream_t s, uint64_t seed, double sigma, int32_t nk, int32_t iq, int32_t ik,
+                           int32_t nbas, int32_t naux, void *out);
+// B^gamma_ia(k,q) = sum_{mu nu} conj(cv_{mu a}) C^{mu nu}_gamma cv_{nu i} of one (q, k) block
+// into out ([nocc][nvirt][naux]): C from launch_philox_C into `scratch`
+// (ao_scratch_bytes), then two batched complex FP64 MFMA products.  c_occ points at the
+// projected occupied coefficients of k (+) q ([nbas][nocc]), c_virt at the virtual ones of
+// k ([nbas][nvirt]).
+int64_t ao_scratch_bytes(int32_t nbas, int32_t nocc, int32_t naux);
+hipError_t launch_ao_B(hipStream_t s, uint64_t seed, double sigma, int32_t nk, int32_t iq, int32_t ik, int32_t nbas,
+                       int32_t nocc, int32_t nvirt, int32_t naux, const double2 *c_occ, const double2 *c_virt,
+                       void *scratch, double2 *out);
 hipError_t launch_philox_words(hipStream_t s, uint64_t seed, int32_t nk, int32_t iq, int32_t ik,
                                uint64_t e0, int64_t count, uint32_t *out);
 

@@ -29,10 +29,12 @@ __device__ __forceinline__ double uniform52(uint32_t a, uint32_t b) {
   return ((double)x + 0.5) * 0x1p-52;
 }
 
+// `stream` is the third counter word: 0 for B, 1 for the pair-fit coefficients C of
+// atomic-orbital systems (same key, independent stream).
 template <bool CPLX>
 __global__ __launch_bounds__(256) void philox_B_kernel(uint64_t seed, double sigma, int32_t nk,
                                                        int32_t iq, int32_t k0, int64_t per_k,
-                                                       void *out) {
+                                                       void *out, uint32_t stream) {
   const uint32_t key0 = (uint32_t)seed;
   const uint32_t key_hi = (uint32_t)(seed >> 32);
   // blockIdx.y is the k of the slab (no 64-bit division per element)
@@ -42,7 +44,7 @@ __global__ __launch_bounds__(256) void philox_B_kernel(uint64_t seed, double sig
        e0 += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t e = (uint64_t)e0;
     const int64_t g = (int64_t)kk * per_k + e0;
-    const uint4 w = philox4x32_10(make_uint4((uint32_t)e, (uint32_t)(e >> 32), 0u, 0u), key0, key1);
+    const uint4 w = philox4x32_10(make_uint4((uint32_t)e, (uint32_t)(e >> 32), stream, 0u), key0, key1);
     const double u1 = uniform52(w.x, w.y);
     const double u2 = uniform52(w.z, w.w);
     const double r = sqrt(-2.0 * log(u1));
@@ -92,9 +94,20 @@ hipError_t launch_philox_B(hipStream_t s, uint64_t seed, double sigma, int32_t n
   if (bx > cap) bx = cap;
   const dim3 grid((unsigned)bx, (unsigned)(k1 - k0));
   if (cplx)
-    hipLaunchKernelGGL(philox_B_kernel<true>, grid, dim3(256), 0, s, seed, sigma, nk, iq, k0, per_k, out);
+    hipLaunchKernelGGL(philox_B_kernel<true>, grid, dim3(256), 0, s, seed, sigma, nk, iq, k0, per_k, out, 0u);
   else
-    hipLaunchKernelGGL(philox_B_kernel<false>, grid, dim3(256), 0, s, seed, sigma, nk, iq, k0, per_k, out);
+    hipLaunchKernelGGL(philox_B_kernel<false>, grid, dim3(256), 0, s, seed, sigma, nk, iq, k0, per_k, out, 0u);
+  return hipGetLastError();
+}
+
+hipError_t launch_philox_C(hipStream_t s, uint64_t seed, double sigma, int32_t nk, int32_t iq, int32_t ik,
+                           int32_t nbas, int32_t naux, void *out) {
+  const int64_t per = (int64_t)nbas * nbas * naux;
+  if (per <= 0) return hipSuccess;
+  int64_t bx = (per + 255) / 256;
+  if (bx > 65536) bx = 65536;
+  hipLaunchKernelGGL(philox_B_kernel<true>, dim3((unsigned)bx, 1u), dim3(256), 0, s, seed, sigma, nk, iq, ik, per,
+                     out, 1u);
   return hipGetLastError();
 }
 

@@ -192,6 +192,22 @@ int validate_system(const rpa_system *sys, HostSmall &hs) {
   for (double v : hs.eps_virt) if (!std::isfinite(v)) return fail(RPA_E_ARG, "eps_virt not finite");
   for (double v : hs.zeta_k) if (!std::isfinite(v)) return fail(RPA_E_ARG, "zeta_k not finite");
   for (double v : hs.zeta_q) if (!std::isfinite(v)) return fail(RPA_E_ARG, "zeta_q not finite");
+  hs.nbas = 0;
+  hs.c_occ.clear();
+  hs.c_virt.clear();
+  if (sys->nbas != 0) {
+    if (sys->nbas < 1 || sys->nbas > 4096) return fail(RPA_E_ARG, "nbas %d outside [1, 4096]", sys->nbas);
+    if (!sys->is_complex) return fail(RPA_E_ARG, "atomic-orbital systems must be complex");
+    if (sys->B) return fail(RPA_E_ARG, "an atomic-orbital system builds B itself: B must be NULL");
+    if (!sys->c_occ || !sys->c_virt) return fail(RPA_E_ARG, "c_occ and c_virt must be non-NULL when nbas > 0");
+    hs.nbas = sys->nbas;
+    hs.c_occ.resize((size_t)nk_occ * sys->nbas * sys->nocc * 2);
+    hs.c_virt.resize((size_t)sys->nk * sys->nbas * sys->nvirt * 2);
+    RPA_TRY(copy_in(hs.c_occ.data(), sys->c_occ, hs.c_occ.size() * 8, sys->memspace));
+    RPA_TRY(copy_in(hs.c_virt.data(), sys->c_virt, hs.c_virt.size() * 8, sys->memspace));
+    for (double v : hs.c_occ) if (!std::isfinite(v)) return fail(RPA_E_ARG, "c_occ not finite");
+    for (double v : hs.c_virt) if (!std::isfinite(v)) return fail(RPA_E_ARG, "c_virt not finite");
+  }
   // insulators only (closed-shell occupations 2/0): every transition energy positive
   double min_occ_gap = INFINITY;
   for (int q = 0; q < sys->nq; ++q)
@@ -297,8 +313,12 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   const int64_t per_pt = 2 * nn * 16 + M * 8 + (mixed ? (int64_t)N * 8 : 0) + trln_blocked_scratch_bytes(1) + 64;
   const int64_t diag_scratch = bsplit ? bf16_diag_scratch_doubles(M, N) * 8
                               : mixed ? diag_exact_scratch_doubles(M, N, 16) * 8 : 0;
+  // atomic-orbital systems: the projected coefficients and the transform's scratch
+  const int64_t ao_bytes = hs.nbas > 0 ? (int64_t)(hs.c_occ.size() + hs.c_virt.size()) * 8 + 512 +
+                                             ao_scratch_bytes(hs.nbas, hs.nocc, hs.naux)
+                                       : 0;
   const int64_t small = (int64_t)(hs.eps_occ.size() + hs.eps_virt.size() + hs.zeta_k.size()) * 8 +
-                        (int64_t)hs.kq.size() * 4 + npts * 32 + 4096 + diag_scratch;
+                        (int64_t)hs.kq.size() * 4 + npts * 32 + 4096 + diag_scratch + ao_bytes;
 
   // distinct q's in order of first appearance; points grouped by q
   std::vector<int32_t> qs;
@@ -373,6 +393,13 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   ar.plan((int64_t)hs.kq.size() * 4, (void **)&d_kq);
   ar.plan(npts * 8, (void **)&d_eps);
   ar.plan(npts * 4, (void **)&d_info);
+  double2 *d_cocc = nullptr, *d_cvirt = nullptr;
+  void *d_aoscr = nullptr;
+  if (hs.nbas > 0) {
+    ar.plan((int64_t)hs.c_occ.size() * 8, (void **)&d_cocc);
+    ar.plan((int64_t)hs.c_virt.size() * 8, (void **)&d_cvirt);
+    ar.plan(ao_scratch_bytes(hs.nbas, hs.nocc, hs.naux), &d_aoscr);
+  }
   if (b_slot) ar.plan(gq * b_slot, &d_B);
   if (vh_slot) ar.plan(gq * vh_slot, &d_vh);
   if (vh_slot && !cplx && sys->memspace == RPA_MEM_HOST) ar.plan(nn * 8, &d_vstage);
@@ -428,6 +455,10 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   RPA_HIP(hipMemcpyAsync(d_ev, hs.eps_virt.data(), hs.eps_virt.size() * 8, hipMemcpyHostToDevice, st));
   RPA_HIP(hipMemcpyAsync(d_zk, hs.zeta_k.data(), hs.zeta_k.size() * 8, hipMemcpyHostToDevice, st));
   RPA_HIP(hipMemcpyAsync(d_kq, hs.kq.data(), hs.kq.size() * 4, hipMemcpyHostToDevice, st));
+  if (hs.nbas > 0) {
+    RPA_HIP(hipMemcpyAsync(d_cocc, hs.c_occ.data(), hs.c_occ.size() * 8, hipMemcpyHostToDevice, st));
+    RPA_HIP(hipMemcpyAsync(d_cvirt, hs.c_virt.data(), hs.c_virt.size() * 8, hipMemcpyHostToDevice, st));
+  }
 
   // host copies of every batch's descriptors stay alive until the final synchronisation
   std::deque<std::vector<PointDesc>> keep_pts;
@@ -446,8 +477,19 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
         char *dst = (char *)d_B + (int64_t)s * b_slot;
         if (!sys->B) {
           if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_PHILOX));
-          RPA_HIP(launch_philox_B(st, sys->philox_seed, sys->sigma, hs.nk, q, 0, hs.nk, hs.nocc,
-                                  hs.nvirt, N, cplx, dst));
+          if (hs.nbas > 0) {
+            // the MO transform of the pair-fit coefficients, one k block at a time
+            const int64_t cstride = (int64_t)hs.nbas * hs.nocc, vstride = (int64_t)hs.nbas * hs.nvirt;
+            const int64_t per_k = (int64_t)hs.nocc * hs.nvirt * N;
+            for (int ik = 0; ik < hs.nk; ++ik)
+              RPA_HIP(launch_ao_B(st, sys->philox_seed, sys->sigma, hs.nk, q, ik, hs.nbas, hs.nocc, hs.nvirt, N,
+                                  d_cocc + (int64_t)hs.kq[(size_t)q * hs.nk + ik] * cstride,
+                                  d_cvirt + (int64_t)ik * vstride, d_aoscr,
+                                  reinterpret_cast<double2 *>(dst) + (int64_t)ik * per_k));
+          } else {
+            RPA_HIP(launch_philox_B(st, sys->philox_seed, sys->sigma, hs.nk, q, 0, hs.nk, hs.nocc,
+                                    hs.nvirt, N, cplx, dst));
+          }
           if (prof) RPA_TRY(ctx.prof_end(st));
         } else {
           RPA_HIP(hipMemcpyAsync(dst, (const char *)sys->B + (int64_t)q * b_slot, (size_t)b_slot,

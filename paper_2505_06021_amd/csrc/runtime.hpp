@@ -90,6 +90,10 @@ struct HostSmall {
   int32_t nk, nq, nocc, nvirt, naux, is_complex;
   std::vector<int32_t> kq;
   std::vector<double> eps_occ, eps_virt, zeta_k, zeta_q;
+  // atomic-orbital systems: basis size and the projected KS coefficients (complex,
+  // interleaved), [nk_occ][nbas][nocc] and [nk][nbas][nvirt]
+  int32_t nbas = 0;
+  std::vector<double> c_occ, c_virt;
 };
 
 int validate_system(const rpa_system *sys, HostSmall &hs);

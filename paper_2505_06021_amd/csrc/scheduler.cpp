@@ -61,7 +61,10 @@ int64_t Scheduler::footprint(const HostSmall &hs, int nw, rpa_precision prec) {
                         (int64_t)hs.kq.size() * 4 + (int64_t)hs.nq * nw * 32 + 4096 +
                         (int64_t)(hs.nq + nw + 1) * 8 +
                         (prec == RPA_BF16X3 ? bf16_diag_scratch_doubles(M, (int)N) * 8
-                         : mixed ? diag_exact_scratch_doubles(M, (int)N, 16) * 8 : 0);
+                         : mixed ? diag_exact_scratch_doubles(M, (int)N, 16) * 8 : 0) +
+                        (hs.nbas > 0 ? (int64_t)(hs.c_occ.size() + hs.c_virt.size()) * 8 + 512 +
+                                           ao_scratch_bytes(hs.nbas, hs.nocc, hs.naux)
+                                     : 0);
   // one q staged at a time: FP64 B (and its FP32 copy, or its prepared split-BF16 copy),
   // V^(1/2), and per point chi0, T, the weight table and the exact diagonal -- the same
   // sizes run_points() budgets
@@ -134,6 +137,9 @@ int Scheduler::submit(const rpa_system *sys, const rpa_freq *freq, rpa_precision
   s.zeta_q = j->zeta_q.data();
   s.vhalf = j->vhalf.data();
   s.B = sys->B ? (const void *)j->B.data() : nullptr;
+  // atomic-orbital systems: the job's own copies of the projected coefficients
+  s.c_occ = j->hs.nbas > 0 ? (const void *)j->hs.c_occ.data() : nullptr;
+  s.c_virt = j->hs.nbas > 0 ? (const void *)j->hs.c_virt.data() : nullptr;
   j->prec = prec;
   j->t_submit = now_seconds();
   std::lock_guard<std::mutex> g(mu_);

@@ -38,7 +38,7 @@ class RpaSystemC(C.Structure):
                 ("kq", C.c_void_p), ("eps_occ", C.c_void_p), ("eps_virt", C.c_void_p),
                 ("zeta_k", C.c_void_p), ("zeta_q", C.c_void_p), ("B", C.c_void_p),
                 ("philox_seed", C.c_uint64), ("sigma", C.c_double), ("vhalf", C.c_void_p),
-                ("nk_occ", C.c_int32)]
+                ("nk_occ", C.c_int32), ("nbas", C.c_int32), ("c_occ", C.c_void_p), ("c_virt", C.c_void_p)]
 
 
 class RpaFreqC(C.Structure):
@@ -172,6 +172,10 @@ class _Marshal:
         s.sigma = system.sigma
         s.vhalf = put(system.vhalf, vdt)
         s.nk_occ = int(np.asarray(system.eps_occ).shape[0])
+        s.nbas = int(getattr(system, "nbas", 0))
+        if s.nbas > 0:
+            s.c_occ = put(system.c_occ, np.complex128)
+            s.c_virt = put(system.c_virt, np.complex128)
         if device:
             import torch
             torch.cuda.synchronize()   # the uploads ran on torch's stream
