@@ -10,8 +10,9 @@
 //   T1[mu][i][gamma] = sum_nu c~_{nu i} C[mu][nu][gamma]           (batch over mu)
 //   B[i][a][gamma]   = sum_mu conj(c~_{mu a}) T1[mu][i][gamma]     (batch over i)
 // Both are O[b][m][n] = sum_k op(X[b][k][m]) Y[b][k][n] with the contraction index k
-// slowest in both operands, so a 64 x 64 output tile streams 16-row panels of X and Y
-// through LDS exactly as the chi0 contraction does.
+// slowest in both operands, so an output tile streams 16-row panels of X and Y through
+// LDS exactly as the chi0 contraction does (64 x 64 tiles; 16 x 128 for the thin
+// occupied-index output of the first product).
 #include "common.hpp"
 
 namespace rpa {
@@ -146,9 +147,102 @@ __global__ __launch_bounds__(256) void zgemm_tn_kernel(TnArgs g) {
       }
 }
 
+// The same product for thin outputs (M a few tens, the occupied count): 16 x 128 tiles,
+// each wave a 16 x 32 strip (two 16 x 16 blocks), so no MFMA work is spent on padding rows.
+constexpr int TNW = 128;
+template <bool CONJ>
+__global__ __launch_bounds__(256) void zgemm_tn16_kernel(TnArgs g) {
+  __shared__ double2 la[2][TK][17];
+  __shared__ double2 lb[2][TK][TNW + 1];
+  const int b = blockIdx.z;
+  const int m0 = blockIdx.y * 16, n0 = blockIdx.x * TNW;
+  const double2 *X = g.X + (int64_t)b * g.sxb;
+  const double2 *Y = g.Y + (int64_t)b * g.syb;
+  const int tid = threadIdx.x, lrow = tid >> 4, lc = tid & 15;
+  const bool mok = m0 + lc < g.M;
+  const int mcol = mok ? m0 + lc : 0;
+  int ncol[8];
+  bool nok[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int n = n0 + lc + 16 * c;
+    nok[c] = n < g.N;
+    ncol[c] = nok[c] ? n : 0;
+  }
+  const int wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  d4 accR[2], accI[2];
+#pragma unroll
+  for (int y = 0; y < 2; ++y) {
+    accR[y] = d4{0.0, 0.0, 0.0, 0.0};
+    accI[y] = d4{0.0, 0.0, 0.0, 0.0};
+  }
+  double2 sa, sb[8];
+  bool kv;
+  auto load = [&](int k0) {
+    const int k = k0 + lrow;
+    kv = k < g.K;
+    const int64_t kc = kv ? k : 0;
+    sa = X[kc * g.ldx + mcol];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) sb[c] = Y[kc * g.ldy + ncol[c]];
+  };
+  auto store = [&](int buf) {
+    const double2 z = make_double2(0.0, 0.0);
+    la[buf][lrow][lc] = (kv && mok) ? sa : z;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) lb[buf][lrow][lc + 16 * c] = (kv && nok[c]) ? sb[c] : z;
+  };
+  auto contract = [&](int buf) {
+#pragma unroll
+    for (int ks = 0; ks < TK / 4; ++ks) {
+      const double2 av = la[buf][ks * 4 + lk][li];
+      double2 bv[2];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bv[y] = lb[buf][ks * 4 + lk][wave * 32 + y * 16 + li];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) accR[y] = mfma(av.x, bv[y].x, accR[y]);
+#pragma unroll
+      for (int y = 0; y < 2; ++y) accI[y] = mfma(av.x, bv[y].y, accI[y]);
+#pragma unroll
+      for (int y = 0; y < 2; ++y) accR[y] = mfma(CONJ ? av.y : -av.y, bv[y].y, accR[y]);
+#pragma unroll
+      for (int y = 0; y < 2; ++y) accI[y] = mfma(CONJ ? -av.y : av.y, bv[y].x, accI[y]);
+    }
+  };
+  const int nsteps = g.K > 0 ? (g.K + TK - 1) / TK : 1;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int s = 0; s + 1 < nsteps; ++s) {
+    const int cur = s & 1;
+    load((s + 1) * TK);
+    __builtin_amdgcn_sched_barrier(0);
+    contract(cur);
+    __builtin_amdgcn_sched_barrier(0);
+    store(cur ^ 1);
+    __syncthreads();
+  }
+  contract((nsteps - 1) & 1);
+  double2 *O = g.O + (int64_t)b * g.sob;
+#pragma unroll
+  for (int y = 0; y < 2; ++y)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + lk + 4 * r;
+      const int n = n0 + wave * 32 + y * 16 + li;
+      if (m < g.M && n < g.N) O[(int64_t)m * g.ldo + n] = make_double2(accR[y][r], accI[y][r]);
+    }
+}
+
 hipError_t launch_tn(hipStream_t s, bool conj, const TnArgs &g, int batch) {
   if (batch <= 0 || g.M <= 0 || g.N <= 0) return hipSuccess;
   if (batch > 65535) return hipErrorInvalidValue;
+  if (g.M <= 32) {   // thin output: 16-row tiles
+    const dim3 grid((unsigned)((g.N + TNW - 1) / TNW), (unsigned)((g.M + 15) / 16), (unsigned)batch);
+    if (conj) hipLaunchKernelGGL(zgemm_tn16_kernel<true>, grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL(zgemm_tn16_kernel<false>, grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+  }
   const dim3 grid((unsigned)((g.N + TT - 1) / TT), (unsigned)((g.M + TT - 1) / TT), (unsigned)batch);
   if (conj) hipLaunchKernelGGL(zgemm_tn_kernel<true>, grid, dim3(256), 0, s, g);
   else hipLaunchKernelGGL(zgemm_tn_kernel<false>, grid, dim3(256), 0, s, g);
