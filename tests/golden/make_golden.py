@@ -6,6 +6,7 @@ workload recipe next to the values:
     python tests/golden/make_golden.py small     # Gamma-only and 3x3x1 systems, all points
     python tests/golden/make_golden.py sampled   # sampled points of the two large systems
     python tests/golden/make_golden.py dual      # the 3x3x1 slab on dual k/q grids, all points
+    python tests/golden/make_golden.py sampledao # sampled points of the atomic-orbital slab
 """
 import json
 import math
@@ -60,6 +61,10 @@ if __name__ == "__main__":
         g = full(inputs.slab_3x3_dual_384)
         g["recipe"]["dual_grid_frac"] = 0.1
         write("slab3x3_dual_naux384", g)
+    elif what == "sampledao":
+        g = sampled(inputs.slab_3x3_ao_384, [(0, 0), (4, 7)])
+        g["recipe"].update(nbas=144, n_lowdep=4, eps_d=1e-4)
+        write("slab3x3_ao_naux384_sampled", g)
     elif what == "sampled6x6":
         write("slab6x6_naux1200_sampled", sampled(inputs.slab_6x6_1200, [(0, 0), (0, 7), (17, 0), (17, 7)]))
     elif what == "sampled2400":

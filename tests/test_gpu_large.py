@@ -1,5 +1,6 @@
 """Full-size parity on sampled points: the 6x6x1 N_aux = 1200 and 3x3x1 N_aux = 2400 slabs,
-with B streamed from the device Philox generator, in the launch configuration of the
+with B streamed from the device Philox generator, and the 3x3x1 N_aux = 384 slab given in an
+atomic-orbital basis (N_bas 144, B from the device MO transform), in the launch configuration of the
 full energy (rpa_points groups the sampled points by q exactly like rpa_energy).
 
 The oracle values are stored (tests/golden/*_sampled.json, written by make_golden.py from
@@ -33,7 +34,8 @@ def ctx():
 
 
 CASES = [("slab6x6_naux1200_sampled", inputs.slab_6x6_1200),
-         ("slab3x3_naux2400_sampled", inputs.slab_3x3_2400)]
+         ("slab3x3_naux2400_sampled", inputs.slab_3x3_2400),
+         ("slab3x3_ao_naux384_sampled", inputs.slab_3x3_ao_384)]
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])
