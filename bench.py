@@ -241,6 +241,7 @@ def main():
 
     check = None
     gold = os.path.join(ROOT, "tests", "golden", f"{args.workload}.json")
+    check = {"E": E}   # the energy of the last timed step (Ha per cell)
     if os.path.exists(gold):
         g = json.load(open(gold))
         check = {"E": E, "E_oracle": g["E"], "rel_err": abs(E - g["E"]) / abs(g["E"])}

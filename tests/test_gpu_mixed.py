@@ -5,7 +5,8 @@ Stated tolerances (measured margins are recorded in the test output):
   chi0 FP32      ||d chi0||_F <= 1e-6 ||chi0||_F,  diagonal to 1e-13
   chi0 BF16X3    ||d chi0||_F <= 1e-4 ||chi0||_F,  diagonal to 1e-13
   energy FP32    |E - E_FP64| <= 1e-6 Ha per cell
-  energy BF16X3  |E - E_FP64| <= 2e-5 Ha per cell
+  energy BF16X3  |E - E_FP64| <= 2e-5 Ha per cell on the small test systems, and <= 1e-6 Ha
+                 per cell on the 3x3x1 N_aux 384 slab of the benchmark (measured 3.4e-7)
 """
 import json
 import os
@@ -75,8 +76,8 @@ def test_energy_mixed_slab384(ctx, prec):
     E, eps = ctx.energy(s, prec=prec)
     dE = abs(E - E64)
     say(f"  E64 {E64:.12f}  E {E:.12f}  dE {dE:.3e} Ha  (oracle {g['E']:.12f})")
-    assert dE <= TOL_E[prec]
-    assert abs(E - g["E"]) <= TOL_E[prec] + 1e-10 * abs(g["E"])
+    assert dE <= 1e-6
+    assert abs(E - g["E"]) <= 1e-6 + 1e-10 * abs(g["E"])
 
 
 @pytest.mark.parametrize("prec", [FP32, BF16X3])
