@@ -157,6 +157,9 @@ def serving(args):
                     "fused_sub_batches": st.get("fused_groups"),
                     "unfused_sub_batches": st.get("solo_groups"),
                     "max_abs_dE_vs_fp64_Ha": float(max(dE)), "max_rel_dE_vs_fp64": float(max(rel)),
+                    "p50_abs_dE_vs_fp64_Ha": float(np.percentile(dE, 50)),
+                    "jobs_above_1e-6_Ha": int(sum(1 for x in dE if x > 1e-6)),
+                    "worst_job": {k: jobs[int(np.argmax(dE))][k] for k in ("id", "naux", "nocc", "nvirt", "grid", "nw")},
                     "fifo_fp64": {"p50_s": float(np.percentile(fifo_lat, 50)),
                                   "p99_s": float(np.percentile(fifo_lat, 99)),
                                   "points_per_s": npts / (fin[-1] - arr[0]) if fin else None,
