@@ -281,7 +281,8 @@ __global__ __launch_bounds__(256) void chi0_f64_kernel(Chi0Args a) {
     contract_masked<KT>(lds[(nsteps - 1) & 1][0], lds[(nsteps - 1) & 1][1], wr, wc, li, lk, on, accR, accI);
   }
 
-  double2 *out = (blockIdx.z == 0 ? a.out : a.partial) + (int64_t)blockIdx.y * a.out_stride;
+  double2 *out = (blockIdx.z == 0 ? a.out : a.partial + (int64_t)(blockIdx.z - 1) * a.split_stride) +
+                 (int64_t)blockIdx.y * a.out_stride;
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -304,6 +305,208 @@ __global__ __launch_bounds__(256) void chi0_f64_kernel(Chi0Args a) {
         out[(int64_t)P * N + Q] = make_double2(re, im);
         out[(int64_t)Q * N + P] = make_double2(re, -im);
       }
+}
+
+// Two frequencies of one q per workgroup.  The points of a q read the same coefficient
+// slab and differ only in the weights w_m zeta_k, so a workgroup stages the unweighted
+// panels of a 64 x 64 tile once and contracts them for both points: each lane scales its
+// right-operand fragments by the two points' weights of its row (the same double product
+// w * b the single-point kernel forms before its LDS store, so the sums are bit for bit
+// those of that kernel) and the wave issues the MFMAs of both points.  Per loaded byte and
+// per barrier this does twice the MFMA work of the single-point kernel at the same LDS
+// footprint (two workgroups per CU).  blockIdx.y is a pair of points (a.pairs[2 y],
+// a.pairs[2 y + 1]) with the same slab; a second index of -1 leaves the pair single.
+template <bool CPLX_B>
+__global__ __launch_bounds__(256) void chi0_f64_w2_kernel(Chi0Args a) {
+  constexpr int KT = 16;
+  __shared__ double2 lds[2][2][KT][LDP];
+  __shared__ double lw[2][2][KT];   // [buffer][point of the pair][row]
+
+  const int p0 = a.pairs[2 * blockIdx.y];
+  const int p1s = a.pairs[2 * blockIdx.y + 1];
+  const bool two = p1s >= 0;
+  const int p1 = two ? p1s : p0;
+  const PointDesc pd = a.pts[p0];
+  int tr, tc;
+  tile_of((int)blockIdx.x, tr, tc);
+  const int N = a.N;
+  const int ms = (int)((((a.M + a.ksplit - 1) / a.ksplit) + KT - 1) / KT) * KT;
+  const int mlo = (int)blockIdx.z * ms;
+  const int M = mlo + ms < (int)a.M ? mlo + ms : (int)a.M;
+  const int P0 = tr * TN, Q0 = tc * TN;
+  const bool diag = (tr == tc);
+
+  const int tid = threadIdx.x;
+  const int lrow = tid >> 4;   // 0..15: one row of the K step per 16 lanes
+  const int lc = tid & 15;
+
+  const char *bbase = reinterpret_cast<const char *>(a.B) +
+                      (int64_t)pd.bslot * a.b_slot_stride * (CPLX_B ? 16 : 8);
+  const double *wrow0 = a.wtab + (int64_t)p0 * a.M;
+  const double *wrow1 = a.wtab + (int64_t)p1 * a.M;
+
+  int pcol[4], qcol[4];
+  bool pok[4], qok[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int P = P0 + lc + 16 * c, Q = Q0 + lc + 16 * c;
+    pok[c] = P < N;
+    qok[c] = Q < N;
+    pcol[c] = pok[c] ? P : 0;
+    qcol[c] = qok[c] ? Q : 0;
+  }
+
+  const int wave = tid >> 6, lane = tid & 63;
+  int wr = wave >> 1, wc = wave & 1;
+  const int li = lane & 15, lk = lane >> 4;
+  int on = 0xf;   // the diagonal-tile block assignment of the single-point kernel
+  if (diag) {
+    if (wr == 0 && wc == 1) {
+      wr = 1;
+      wc = 0;
+      on = 0xa;
+    } else if (wr == 1 && wc == 0) {
+      on = 0x5;
+    } else {
+      on = 0xd;
+    }
+  }
+
+  d4 accR[2][2][2], accI[2][2][2];   // [point][x][y]
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        accR[p][x][y] = d4{0.0, 0.0, 0.0, 0.0};
+        accI[p][x][y] = d4{0.0, 0.0, 0.0, 0.0};
+      }
+
+  double2 sa[4], sb[4];
+  double sw0, sw1;
+  bool mv;
+  auto load = [&](int m0) __attribute__((always_inline)) {
+    const int m = m0 + lrow;
+    mv = m < M;
+    const int mc = mv ? m : 0;
+    sw0 = wrow0[mc];
+    sw1 = wrow1[mc];
+    const int64_t rowoff = (int64_t)mc * N;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      sa[c] = load_b<CPLX_B>(bbase, rowoff + pcol[c]);
+      sb[c] = load_b<CPLX_B>(bbase, rowoff + qcol[c]);
+    }
+  };
+  auto store = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double2 av = sa[c], bv = sb[c];
+      const bool aok = mv && pok[c];
+      lds[buf][0][lrow][lc + 16 * c] = make_double2(aok ? av.x : 0.0, aok ? av.y : 0.0);
+      lds[buf][1][lrow][lc + 16 * c] = make_double2(qok[c] ? bv.x : 0.0, qok[c] ? bv.y : 0.0);
+    }
+    if (lc == 0) {
+      lw[buf][0][lrow] = mv ? sw0 : 0.0;
+      lw[buf][1][lrow] = mv ? sw1 : 0.0;
+    }
+  };
+  // one K step for both points; blocks outside `on` are skipped (uniform over the wave)
+  auto contract = [&](int buf, int onm) __attribute__((always_inline)) {
+#pragma unroll
+    for (int ks = 0; ks < KT / 4; ++ks) {
+      const int r = ks * 4 + lk;
+      double2 av[2], bv[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) av[x] = lds[buf][0][r][wr * 32 + x * 16 + li];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bv[y] = lds[buf][1][r][wc * 32 + y * 16 + li];
+      const double wp[2] = {lw[buf][0][r], lw[buf][1][r]};
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        double2 bw[2];
+#pragma unroll
+        for (int y = 0; y < 2; ++y) bw[y] = make_double2(wp[p] * bv[y].x, wp[p] * bv[y].y);
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+            if (onm & (1 << (2 * x + y))) accR[p][x][y] = mfma(av[x].x, bw[y].x, accR[p][x][y]);
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+            if (onm & (1 << (2 * x + y))) accI[p][x][y] = mfma(av[x].x, bw[y].y, accI[p][x][y]);
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+            if (onm & (1 << (2 * x + y))) accR[p][x][y] = mfma(av[x].y, bw[y].y, accR[p][x][y]);
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+            if (onm & (1 << (2 * x + y))) accI[p][x][y] = mfma(-av[x].y, bw[y].x, accI[p][x][y]);
+      }
+    }
+  };
+
+  const int nsteps = M > mlo ? (M - mlo + KT - 1) / KT : 1;
+  load(mlo);
+  store(0);
+  __syncthreads();
+  if (!diag) {
+    for (int s = 0; s + 1 < nsteps; ++s) {
+      const int cur = s & 1;
+      load(mlo + (s + 1) * KT);
+      __builtin_amdgcn_sched_barrier(0);
+      contract(cur, 0xf);
+      __builtin_amdgcn_sched_barrier(0);
+      store(cur ^ 1);
+      __syncthreads();
+    }
+    contract((nsteps - 1) & 1, 0xf);
+  } else {
+    for (int s = 0; s + 1 < nsteps; ++s) {
+      const int cur = s & 1;
+      load(mlo + (s + 1) * KT);
+      __builtin_amdgcn_sched_barrier(0);
+      contract(cur, on);
+      __builtin_amdgcn_sched_barrier(0);
+      store(cur ^ 1);
+      __syncthreads();
+    }
+    contract((nsteps - 1) & 1, on);
+  }
+
+  double2 *base = blockIdx.z == 0 ? a.out : a.partial + (int64_t)(blockIdx.z - 1) * a.split_stride;
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    if (p == 1 && !two) break;
+    double2 *out = base + (int64_t)(p == 0 ? p0 : p1) * a.out_stride;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int P = P0 + wr * 32 + x * 16 + lk + 4 * r;
+          const int Q = Q0 + wc * 32 + y * 16 + li;
+          if (P >= N || Q >= N || !(on & (1 << (2 * x + y)))) continue;
+          const double re = accR[p][x][y][r];
+          const double im = accI[p][x][y][r];
+          if (diag) {
+            if (P < Q) continue;
+            if (P == Q) {
+              out[(int64_t)P * N + Q] = make_double2(re, 0.0);
+              continue;
+            }
+          }
+          out[(int64_t)P * N + Q] = make_double2(re, im);
+          out[(int64_t)Q * N + P] = make_double2(re, -im);
+        }
+  }
 }
 
 // The same contraction on 128 x 128 tiles: eight waves, each a 64 x 32 sub-tile (4 x 2
@@ -431,7 +634,7 @@ __global__ __launch_bounds__(512) void chi0_f64_t128_kernel(Chi0Args a, int32_t 
   }
   contract((nsteps - 1) & 1);
 
-  double2 *out = (split == 0 ? a.out : a.partial) + (int64_t)p * a.out_stride;
+  double2 *out = (split == 0 ? a.out : a.partial + (int64_t)(split - 1) * a.split_stride) + (int64_t)p * a.out_stride;
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
@@ -455,22 +658,28 @@ __global__ __launch_bounds__(512) void chi0_f64_t128_kernel(Chi0Args a, int32_t 
       }
 }
 
-// out += partial (the second row split), full matrices: a fixed order, so repeatable
-__global__ __launch_bounds__(256) void split_reduce_kernel(const double2 *partial, int64_t n, double2 *out) {
+// out += partial_1 + ... (the row splits after the first, planes n apart), added one
+// plane after another in split order, so repeatable
+__global__ __launch_bounds__(256) void split_reduce_kernel(const double2 *partial, int32_t nparts, int64_t n,
+                                                           double2 *out) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const double2 a = out[i], b = partial[i];
-    out[i] = make_double2(a.x + b.x, a.y + b.y);
+    double2 a = out[i];
+    for (int z = 0; z < nparts; ++z) {
+      const double2 b = partial[(int64_t)z * n + i];
+      a = make_double2(a.x + b.x, a.y + b.y);
+    }
+    out[i] = a;
   }
 }
 
 }  // namespace
 
-int32_t chi0_pick_ksplit(int64_t work, int64_t slots, int64_t M) {
-  // fraction of the last round of workgroups that is busy, for 1..4 splits; a split must
-  // keep at least 512 rows and costs ~2% for its extra reduction traffic
+int32_t chi0_pick_ksplit(int64_t work, int64_t slots, int64_t M, int32_t max_split) {
+  // fraction of the last round of workgroups that is busy, for 1..max_split splits; a
+  // split must keep at least 512 rows and costs ~2% for its extra reduction traffic
   int best = 1;
   double best_eff = 0.0;
-  for (int s = 1; s <= 2; ++s) {
+  for (int s = 1; s <= max_split; ++s) {
     if (s > 1 && M / s < 512) break;
     const double rounds = (double)(work * s) / (double)slots;
     const double eff = rounds / std::ceil(rounds) * (1.0 - 0.02 * (s - 1));
@@ -491,17 +700,37 @@ hipError_t launch_chi0_weights(hipStream_t s, const Chi0Args &a, int32_t npts) {
   return hipGetLastError();
 }
 
-int chi0_cfg_count() { return 4; }
+int chi0_cfg_count() { return 5; }
 int chi0_cfg_tile(int cfg) { return cfg == 3 ? TW : TN; }
 int chi0_cfg_slots_per_cu(int cfg) { return cfg == 3 ? 1 : 2; }
+int chi0_cfg_points_per_wg(int cfg) { return cfg == 4 ? 2 : 1; }
 const char *chi0_cfg_name(int cfg) {
-  static const char *names[4] = {"t64k8", "t64k16", "t64k32", "t128k16"};
-  return (cfg >= 0 && cfg < 4) ? names[cfg] : "?";
+  static const char *names[5] = {"t64k8", "t64k16", "t64k32", "t128k16", "t64k16w2"};
+  return (cfg >= 0 && cfg < 5) ? names[cfg] : "?";
 }
 
-hipError_t launch_chi0_f64(hipStream_t s, const Chi0Args &a, int32_t npts, bool cplx_b, int cfg) {
+hipError_t launch_chi0_f64(hipStream_t s, const Chi0Args &args, int32_t npts, bool cplx_b, int cfg) {
   if (npts <= 0) return hipSuccess;
-  const int ks = a.ksplit > 1 ? 2 : 1;   // split 0 writes a.out, split 1 writes a.partial
+  if (args.ksplit > kMaxSplit) return hipErrorInvalidValue;
+  // split 0 writes a.out, split z >= 1 the z-th plane of a.partial (planes npts points apart)
+  const int ks = args.ksplit > 1 ? args.ksplit : 1;
+  Chi0Args a = args;
+  a.ksplit = ks;
+  a.split_stride = (int64_t)npts * a.out_stride;
+  // the paired kernel needs the launch's pair table; without one the single-point kernel
+  // of the same tile and K step computes the same sums
+  if (cfg == 4 && (a.pairs == nullptr || a.npairs <= 0)) cfg = 1;
+  if (cfg == 4) {
+    const int T = (a.N + TN - 1) / TN;
+    const dim3 grid((unsigned)(T * (T + 1) / 2), (unsigned)a.npairs, (unsigned)ks);
+    if (cplx_b)
+      hipLaunchKernelGGL((chi0_f64_w2_kernel<true>), grid, dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((chi0_f64_w2_kernel<false>), grid, dim3(256), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || ks == 1) return e;
+    return launch_split_add(s, a.partial, ks - 1, (int64_t)npts * a.out_stride, a.out);
+  }
   if (cfg == 3) {
     const int T = (a.N + TW - 1) / TW;
     const int64_t nwg = (int64_t)T * (T + 1) / 2 * npts * ks;
@@ -512,7 +741,7 @@ hipError_t launch_chi0_f64(hipStream_t s, const Chi0Args &a, int32_t npts, bool 
       hipLaunchKernelGGL((chi0_f64_t128_kernel<false>), dim3((unsigned)nwg), dim3(512), 0, s, a, T * (T + 1) / 2, npts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || ks == 1) return e;
-    return launch_split_add(s, a.partial, (int64_t)npts * a.out_stride, a.out);
+    return launch_split_add(s, a.partial, ks - 1, (int64_t)npts * a.out_stride, a.out);
   }
   const int kt = cfg == 0 ? 8 : cfg == 2 ? 32 : 16;
   const int T = (a.N + TN - 1) / TN;
@@ -528,14 +757,14 @@ hipError_t launch_chi0_f64(hipStream_t s, const Chi0Args &a, int32_t npts, bool 
 #undef RPA_CHI0_LAUNCH
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || ks == 1) return e;
-  return launch_split_add(s, a.partial, (int64_t)npts * a.out_stride, a.out);
+  return launch_split_add(s, a.partial, ks - 1, (int64_t)npts * a.out_stride, a.out);
 }
 
-hipError_t launch_split_add(hipStream_t s, const double2 *partial, int64_t n, double2 *out) {
+hipError_t launch_split_add(hipStream_t s, const double2 *partial, int32_t nparts, int64_t n, double2 *out) {
   int64_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  if (blocks < 1) return hipSuccess;
-  hipLaunchKernelGGL(split_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, partial, n, out);
+  if (blocks < 1 || nparts < 1) return hipSuccess;
+  hipLaunchKernelGGL(split_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, partial, nparts, n, out);
   return hipGetLastError();
 }
 

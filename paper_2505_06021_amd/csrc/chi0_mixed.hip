@@ -567,7 +567,7 @@ hipError_t launch_chi0_mixed(hipStream_t s, const Chi0Args &a, int32_t npts, con
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || ks == 1) return e;
-  return launch_split_add(s, a.partial, (int64_t)npts * a.out_stride, a.out);
+  return launch_split_add(s, a.partial, 1, (int64_t)npts * a.out_stride, a.out);
 }
 
 }  // namespace rpa

@@ -17,6 +17,8 @@ struct PointDesc {
 };
 
 // Arguments of the chi0 contraction kernels.
+constexpr int kMaxSplit = 4;   // row splits of one FP64 contraction launch
+
 struct Chi0Args {
   const void *B;            // bslot-major slabs of [M][N] coefficients (complex or real)
   int64_t b_slot_stride;    // elements (complex or real) between slabs
@@ -28,11 +30,16 @@ struct Chi0Args {
   double *wtab;             // [npts][M] w_m zeta_k of every contraction row
   double2 *out;             // [npts][N][N] complex
   int64_t out_stride;       // complex elements between outputs
-  int32_t ksplit;           // 2: the contraction rows are split in two halves; the first
-                            // writes out, the second partial, and out += partial follows
-  double2 *partial;         // [npts][N][N] (used when ksplit == 2)
+  int32_t ksplit;           // row splits (FP64: 1..kMaxSplit, reduced precision: 1..2): the
+                            // first writes out, split z >= 1 plane z - 1 of partial, and
+                            // out += the planes in split order follows
+  double2 *partial;         // [ksplit - 1][npts][N][N] (used when ksplit >= 2)
+  int64_t split_stride;     // complex elements between partial planes (set by the launcher)
   int32_t nk, nocc, nvirt, N;
   int64_t M;                // nk * nocc * nvirt
+  const int32_t *pairs;     // [npairs][2] points of one slab contracted together (second
+                            // index -1: none), for the paired FP64 kernel; may be null
+  int32_t npairs;
 };
 
 // Batched complex GEMM C_b = A_{a(b)} * B_{b(b)}, all N x N row-major.
@@ -79,11 +86,13 @@ hipError_t launch_chi0_f64(hipStream_t s, const Chi0Args &a, int32_t npts, bool 
 int chi0_cfg_count();
 int chi0_cfg_tile(int cfg);            // output tile edge of a configuration
 int chi0_cfg_slots_per_cu(int cfg);    // workgroups of it that fit on one CU
+int chi0_cfg_points_per_wg(int cfg);   // points one workgroup contracts (2: paired kernel)
 const char *chi0_cfg_name(int cfg);
 // Number of row splits (1 or 2) that best fills `slots` concurrent workgroups for `work` tiles.
-int32_t chi0_pick_ksplit(int64_t work, int64_t slots, int64_t M);
+int32_t chi0_pick_ksplit(int64_t work, int64_t slots, int64_t M, int32_t max_split);
 // out[i] += partial[i] for n complex elements.
-hipError_t launch_split_add(hipStream_t s, const double2 *partial, int64_t n, double2 *out);
+// out += partial[0] + ... + partial[nparts - 1] (planes of n elements), in that order
+hipError_t launch_split_add(hipStream_t s, const double2 *partial, int32_t nparts, int64_t n, double2 *out);
 
 hipError_t launch_zgemm_f64(hipStream_t s, const GemmArgs &a, int32_t batch);
 

@@ -381,6 +381,9 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
     if (bsplit && rbatch < 1) rbatch = 1;
     break;
   }
+  // FP64: two more partial planes per lane (up to four row splits per contraction launch)
+  // where the budget holds them; one plane (two splits) otherwise
+  const int tplanes = (!mixed && pbatch * per_pt + 2 * pbatch * nn * 16 <= rest / nlanes) ? kMaxSplit - 1 : 1;
 
   Arena ar(ctx, use_cache);
   const bool prof = use_cache && ctx.profile;   // timing only on the synchronous path
@@ -420,7 +423,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   for (int l = 0; l < nlanes; ++l) {
     LaneBufs &lb = lanes[l];
     ar.plan(pbatch * (int64_t)sizeof(PointDesc), (void **)&lb.pts);
-    ar.plan(3 * pbatch * 4, (void **)&lb.amap);
+    ar.plan(5 * pbatch * 4, (void **)&lb.amap);   // three maps and the pair table
     ar.plan(pbatch * nn * 16, &lb.chi);
     ar.plan(pbatch * M * 8, (void **)&lb.w);
     if (mixed) {
@@ -431,7 +434,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
       ar.plan(rbatch * prep_bytes, (void **)&lb.R);
       ar.plan(bf16_partial_elems(rplan, (int)rbatch) * 8, (void **)&lb.part);
     }
-    ar.plan(pbatch * nn * 16, &lb.T);
+    ar.plan(pbatch * nn * 16 * tplanes, &lb.T);
     ar.plan(trln_blocked_scratch_bytes((int32_t)pbatch), &lb.tscr);
   }
   double *d_qw = nullptr;
@@ -539,7 +542,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
       LaneBufs &lb = lanes[lane];
       const int nb = (int)std::min<size_t>((size_t)pbatch, gp.size() - b0);
       keep_pts.emplace_back(nb);
-      keep_maps.emplace_back(3 * (size_t)nb);
+      keep_maps.emplace_back(5 * (size_t)nb);
       std::vector<PointDesc> &hp = keep_pts.back();
       int32_t *vmap = keep_maps.back().data();      // V^(1/2) slot of each batch entry
       int32_t *imap = vmap + nb;                     // identity (chi0 / T slot)
@@ -557,8 +560,19 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
         imap[i] = i;
         emap[i] = (int32_t)p;
       }
+      // consecutive points on one slab (the frequencies of a q) pair up for the paired
+      // FP64 contraction kernel
+      int32_t *pairs = vmap + 3 * nb;
+      int32_t npairs = 0;
+      for (int i = 0; i < nb;) {
+        const bool two = i + 1 < nb && hp[i + 1].bslot == hp[i].bslot;
+        pairs[2 * npairs] = i;
+        pairs[2 * npairs + 1] = two ? i + 1 : -1;
+        ++npairs;
+        i += two ? 2 : 1;
+      }
       RPA_HIP(hipMemcpyAsync(lb.pts, hp.data(), nb * sizeof(PointDesc), hipMemcpyHostToDevice, S));
-      RPA_HIP(hipMemcpyAsync(lb.amap, vmap, 3 * (size_t)nb * 4, hipMemcpyHostToDevice, S));
+      RPA_HIP(hipMemcpyAsync(lb.amap, vmap, (3 * (size_t)nb + 2 * (size_t)npairs) * 4, hipMemcpyHostToDevice, S));
       const int32_t *d_vmap = lb.amap, *d_imap = lb.amap + nb, *d_emap = lb.amap + 2 * nb;
       double *d_w = lb.w, *d_diag = lb.diag, *d_dscr = lb.dscr;
       unsigned short *d_R = lb.R;
@@ -580,10 +594,31 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
       ca.nk = hs.nk; ca.nocc = hs.nocc; ca.nvirt = hs.nvirt; ca.N = N; ca.M = M;
       ca.ksplit = 1;
       ca.partial = (double2 *)d_T;
+      ca.pairs = lb.amap + 3 * nb;
+      ca.npairs = npairs;
       int cfg = 1;   // FP64 tile configuration (the tuner's choice, made after the weights)
       if (prof) RPA_TRY(ctx.prof_begin(S, RPA_K_CHI0_AUX));
       RPA_HIP(launch_chi0_weights(S, ca, nb));
-      if (!mixed) RPA_TRY(tune_chi0_cfg(S, ca, nb, cplx, &cfg));
+      // row splits of the contraction (FP64 up to four, reduced precision two) where they
+      // fill the last round of workgroups better (counting the workgroups of a concurrent
+      // lane); the later splits' results go to the T buffer's planes, which are free
+      // until the sandwich.  RPA_CHI0_KSPLIT fixes the count (tests, timing).
+      auto pick_split = [&](int64_t tn, int64_t slots, int64_t units, int max_split) {
+        const int64_t T = (N + tn - 1) / tn;
+        int ks = chi0_pick_ksplit(T * (T + 1) / 2 * units * nlanes, slots, M, max_split);
+        if (const char *e = getenv("RPA_CHI0_KSPLIT")) {
+          const int v = atoi(e);
+          if (v >= 1) ks = std::min(v, max_split);
+        }
+        return ks;
+      };
+      int ks_of[8] = {1, 1, 1, 1, 1, 1, 1, 1};   // FP64: the split count of each configuration
+      if (!mixed) {
+        for (int c = 0; c < chi0_cfg_count() && c < 8; ++c)
+          ks_of[c] = pick_split(chi0_cfg_tile(c), (int64_t)chi0_cfg_slots_per_cu(c) * ncu,
+                                chi0_cfg_points_per_wg(c) == 2 ? npairs : nb, tplanes + 1);
+        RPA_TRY(tune_chi0_cfg(S, ca, nb, cplx, &cfg, ks_of));
+      }
       int f32_tile = 64;
       if (mixed && !bsplit) {
         // the exact FP64 diagonal first: the tile tuner launches the contraction
@@ -599,14 +634,11 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
         }
         RPA_TRY(tune_f32_tile(S, ca, nb, cplx, d_B32, d_diag, &f32_tile));
       }
-      {
-        // two-way row split of the contraction when it fills the last round of
-        // workgroups better (counting the workgroups of a concurrent lane); the second
-        // half's result goes to the T buffer, which is free until the sandwich
-        const int64_t tn = bsplit ? 64 : mixed ? f32_tile : chi0_cfg_tile(cfg);
-        const int64_t T = (N + tn - 1) / tn;
-        const int64_t slots = (mixed ? (tn == 128 ? 1LL : 2LL) : (int64_t)chi0_cfg_slots_per_cu(cfg)) * ncu;
-        ca.ksplit = chi0_pick_ksplit(T * (T + 1) / 2 * nb * nlanes, slots, M) >= 2 ? 2 : 1;
+      if (mixed) {
+        const int64_t tn = bsplit ? 64 : f32_tile;
+        ca.ksplit = pick_split(tn, (tn == 128 ? 1LL : 2LL) * ncu, nb, 2);
+      } else {
+        ca.ksplit = ks_of[cfg];
       }
       if (mixed) {
         // the exact FP64 diagonal: FP32 above, split-BF16 in the operand preparation

@@ -142,7 +142,10 @@ int run_points(Ctx &ctx, hipStream_t stream, PointJob &job, int64_t mem_budget, 
 // Tile and K-step configuration (launch_chi0_f64's cfg) of the FP64 chi0 contraction for
 // this launch shape: fixed by the environment, else timed once per shape bucket and
 // cached (tuner.cpp).  a.out must hold npts outputs; its contents are overwritten.
-int tune_chi0_cfg(hipStream_t st, const Chi0Args &a, int npts, bool cplx, int *cfg_out);
+// ksplit_of[c] (null: all 1) is the row split count the launch would use with
+// configuration c; the candidates are timed with it (a.partial holds its planes).
+int tune_chi0_cfg(hipStream_t st, const Chi0Args &a, int npts, bool cplx, int *cfg_out,
+                  const int *ksplit_of = nullptr);
 // Tile edge (64 or 128) of the split-BF16 contraction of group g (operands prepared on
 // st, g.part large enough for the candidates' truncated launches: at most max_part
 // elements): fixed by RPA_BF16_TILE, else timed once per shape bucket and cached.

@@ -4,14 +4,16 @@
 // reduced-precision candidates).
 //
 // Candidates (launch_chi0_f64 configurations): 64-wide tiles with 8, 16 or 32 rows per
-// LDS step (two workgroups per CU) and 128-wide tiles with 16-row steps (one per CU).
+// LDS step (two workgroups per CU), 128-wide tiles with 16-row steps (one per CU), and
+// 64-wide tiles with 16-row steps contracting two frequencies of a q per workgroup (only
+// where the launch's pair table pairs some points).
 // The first launch of a shape bucket (real/complex, N rounded up to 64, points per
 // launch, order of magnitude of M) times every candidate on a truncated contraction (the
 // first 4096 rows, one row split) written into the launch's own output, which the real
 // launch then overwrites in full (the kernels store, they never accumulate), so tuning
 // never changes a result; all candidates sum the same products in the same row order.
 // Every later launch of the bucket in the process uses the choice.  RPA_CHI0_CFG=<name>
-// (t64k8, t64k16, t64k32, t128k16) or the older RPA_CHI0_KT=8|16|32 fixes the
+// (t64k8, t64k16, t64k32, t128k16, t64k16w2) or the older RPA_CHI0_KT=8|16|32 fixes the
 // configuration (read on every launch); RPA_TUNE=0 keeps t64k16; RPA_TUNE_CACHE names a
 // text file that keeps the choices across processes ("bucket name" lines).
 #include <cstdio>
@@ -96,7 +98,7 @@ int fixed_cfg() {
 
 }  // namespace
 
-int tune_chi0_cfg(hipStream_t st, const Chi0Args &a, int npts, bool cplx, int *cfg_out) {
+int tune_chi0_cfg(hipStream_t st, const Chi0Args &a, int npts, bool cplx, int *cfg_out, const int *ksplit_of) {
   const int f = fixed_cfg();
   if (f >= 0) {
     *cfg_out = f;
@@ -110,11 +112,10 @@ int tune_chi0_cfg(hipStream_t st, const Chi0Args &a, int npts, bool cplx, int *c
     *cfg_out = it->second;
     return RPA_OK;
   }
-  // time each configuration on the first rows of the contraction (enough K steps for a
-  // steady state, few enough that tuning costs a fraction of one launch)
-  Chi0Args t = a;
-  t.M = a.M < 4096 ? a.M : 4096;
-  t.ksplit = 1;
+  // time each configuration on the first rows of the contraction with the row split
+  // count the launch would use with it (so the candidates fill the GPU as the real
+  // launches do), 4096 rows per split (enough K steps for a steady state, few enough that
+  // tuning costs a fraction of one launch); compare time per row
   float best_ms = 1e30f;
   int best = kDefaultCfg;
   hipEvent_t e0, e1;
@@ -122,12 +123,20 @@ int tune_chi0_cfg(hipStream_t st, const Chi0Args &a, int npts, bool cplx, int *c
   RPA_HIP(hipEventCreate(&e1));
   for (int rep = 0; rep < 2; ++rep) {   // the first round warms code and caches
     for (int c = 0; c < chi0_cfg_count(); ++c) {
+      if (chi0_cfg_points_per_wg(c) == 2 && (a.pairs == nullptr || a.npairs == npts)) continue;
+      Chi0Args t = a;
+      t.ksplit = ksplit_of ? ksplit_of[c] : 1;
+      t.M = a.M < 4096LL * t.ksplit ? a.M : 4096LL * t.ksplit;
       RPA_HIP(hipEventRecord(e0, st));
       RPA_HIP(launch_chi0_f64(st, t, npts, cplx, c));
       RPA_HIP(hipEventRecord(e1, st));
       RPA_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
       RPA_HIP(hipEventElapsedTime(&ms, e0, e1));
+      ms /= (float)t.M;
+      if (rep == 1 && getenv("RPA_TUNE_VERBOSE"))
+        fprintf(stderr, "[tune] %s %s: %.3e ms per row (%d splits, %lld rows)\n", key.c_str(), chi0_cfg_name(c), ms,
+                t.ksplit, (long long)t.M);
       if (rep == 1 && ms < best_ms) {
         best_ms = ms;
         best = c;

@@ -1,10 +1,14 @@
 """The tile configuration of the FP64 chi0 contraction changes speed, never results.
 
 Every configuration (64-wide tiles with 8, 16, 32 rows of B per LDS step; 128-wide tiles
-with 16) runs the same sequence of 4-row MFMA steps in the same row order, so with one
-row split chi0 is bit-for-bit the same for all; each must match the oracle to 1e-12
-(Frobenius, relative).  The tuner must record one choice per shape bucket, persist it
-when asked, and leave E within 1e-12 of a run at the fixed default configuration.
+with 16; 64-wide tiles with 16-row steps contracting two frequencies of a q per
+workgroup) runs the same sequence of 4-row MFMA steps in the same row order on the same
+weighted products, so with one row split chi0 is bit-for-bit the same for all; each must
+match the oracle to 1e-12 (Frobenius, relative).  The paired configuration is checked
+through whole energies (the only calls with several points per launch), with odd
+frequency counts so that pairs are left single at the end of every q.  The tuner must
+record one choice per shape bucket, persist it when asked, and leave E within 1e-12 of a
+run at the fixed default configuration.
 """
 import os
 import sys
@@ -35,7 +39,7 @@ def tall_system():
     return inputs.make_system("tall", (2, 2, 1), 8, 150, 150, 3, 41, is_complex=True)
 
 
-CFGS = ("t64k8", "t64k16", "t64k32", "t128k16")
+CFGS = ("t64k8", "t64k16", "t64k32", "t128k16", "t64k16w2")
 
 
 @pytest.mark.parametrize("naux", [150, 257])
@@ -107,3 +111,45 @@ def test_fp32_tile_tuner_records_choice(ctx, monkeypatch):
     choices = {k: v for k, v in rpa.tuned().items() if k.startswith("f32_")}
     assert choices and all(v in ("t64", "t128") for v in choices.values()), choices
     assert abs(E - orc.energy(s)[0]) <= 1e-6
+
+
+@pytest.mark.parametrize("nw,is_complex", [(3, True), (5, True), (4, False)])
+def test_paired_frequencies_match_single_point_kernel(ctx, monkeypatch, nw, is_complex):
+    # several q with an odd (or even) number of frequencies each: the pair table of a
+    # batch pairs the frequencies of one q and leaves the last one of an odd q single;
+    # these systems are too short for a row split, so the per-point energies equal the
+    # single-point kernel's bit for bit
+    s = inputs.make_system("pair", (2, 2, 1), 3, 9, 150, nw, 37, is_complex=is_complex, sigma=0.15)
+    monkeypatch.setenv("RPA_CHI0_CFG", "t64k16")
+    say(f"energy nw={nw} complex={is_complex}: single-point kernel")
+    e1, g1 = ctx.energy(s)
+    monkeypatch.setenv("RPA_CHI0_CFG", "t64k16w2")
+    say("  paired kernel")
+    e2, g2 = ctx.energy(s)
+    e_ref, g_ref = orc.energy(s)
+    assert abs(e2 - e_ref) <= 1e-10 * abs(e_ref)
+    for q in range(s.nq):
+        assert np.max(np.abs(g2[q] - g_ref[q])) <= 1e-10 * np.max(np.abs(g_ref[q]))
+    assert np.array_equal(g2, g1)
+
+
+@pytest.mark.parametrize("cfg", ["t64k16", "t64k16w2", "t128k16"])
+def test_row_splits_agree(ctx, monkeypatch, cfg):
+    # one to four row splits of every contraction launch (the later splits' sums land in
+    # partial planes added in split order): each equals the oracle, and the per-point
+    # energies of different split counts differ only by the reordered FP64 sums
+    s = inputs.make_system("splits", (2, 2, 1), 8, 150, 200, 3, 43, is_complex=True, sigma=0.15)
+    e_ref, g_ref = orc.energy(s)
+    monkeypatch.setenv("RPA_CHI0_CFG", cfg)
+    base = None
+    for ks in (1, 2, 3, 4):
+        monkeypatch.setenv("RPA_CHI0_KSPLIT", str(ks))
+        say(f"energy {cfg} with {ks} row splits")
+        e, g = ctx.energy(s)
+        assert abs(e - e_ref) <= 1e-10 * abs(e_ref), (ks, e, e_ref)
+        for q in range(s.nq):
+            assert np.max(np.abs(g[q] - g_ref[q])) <= 1e-10 * np.max(np.abs(g_ref[q])), (ks, q)
+        if base is None:
+            base = g
+        else:
+            assert np.max(np.abs(g - base)) <= 1e-12 * np.max(np.abs(base)), ks
