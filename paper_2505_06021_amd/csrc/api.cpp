@@ -249,7 +249,7 @@ int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega, rpa_
     RPA_TRY(c.workspace("chi0_diag_scratch", diag_exact_scratch_doubles(M, N, 1) * 8, (void **)&scr));
     RPA_HIP(launch_to_f32(c.stream, B, b32, M * N, cplx));
     RPA_HIP(launch_diag_exact(c.stream, B, cplx, M, N, wt, 1, scr, dg));
-    int tile = 64;
+    int tile = kF32T64;
     RPA_TRY(tune_f32_tile(c.stream, a, 1, cplx, b32, dg, &tile));
     RPA_HIP(launch_chi0_mixed(c.stream, a, 1, b32, dg, (int)prec, tile));
   } else {

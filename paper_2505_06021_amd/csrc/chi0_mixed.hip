@@ -152,13 +152,33 @@ __device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
 
 constexpr int LDP32 = TN + 1;
 
-template <int KT>
-__global__ __launch_bounds__(256) void chi0_f32_kernel(Chi0Args a, const float2 *B32, const double *diag) {
+// NP = 2: a workgroup contracts two frequencies of one q (a.pairs[2 y], a.pairs[2 y + 1],
+// the second -1 when single): the unweighted FP32 panels are staged once and each lane
+// scales its right-operand fragments by the two points' weights of its row (the same
+// float product w * b the single-point kernel forms at its LDS store, so the sums are bit
+// for bit the same); half the loads, LDS stores and barriers per MFMA.
+template <int KT, int NP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void chi0_f32_kernel(Chi0Args a,
+                                                                                              const float2 *B32,
+                                                                                              const double *diag) {
   __shared__ float2 lds[2][2][KT][LDP32];
+  __shared__ float lw[2][NP][KT];   // per-row weights of the pair (NP = 2 only)
   constexpr int RPI = 16;
   constexpr int NPASS = KT / RPI;
 
-  const PointDesc pd = a.pts[blockIdx.y];
+  int pidx[NP];
+  bool pon[NP];
+  if constexpr (NP == 1) {
+    pidx[0] = (int)blockIdx.y;
+    pon[0] = true;
+  } else {
+    pidx[0] = a.pairs[2 * blockIdx.y];
+    const int p1 = a.pairs[2 * blockIdx.y + 1];
+    pon[0] = true;
+    pon[1] = p1 >= 0;
+    pidx[1] = p1 >= 0 ? p1 : pidx[0];
+  }
+  const PointDesc pd = a.pts[pidx[0]];
   int tr, tc;
   tile_of((int)blockIdx.x, tr, tc);
   const int N = a.N;
@@ -171,7 +191,9 @@ __global__ __launch_bounds__(256) void chi0_f32_kernel(Chi0Args a, const float2 
   const int tid = threadIdx.x;
   const int lrow = tid >> 4, lc = tid & 15;
   const float2 *bb = B32 + (int64_t)pd.bslot * a.b_slot_stride;
-  const double *wrow = a.wtab + (int64_t)blockIdx.y * a.M;
+  const double *wrow[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) wrow[p] = a.wtab + (int64_t)pidx[p] * a.M;
 
   int pcol[4], qcol[4];
   bool pok[4], qok[4];
@@ -203,28 +225,31 @@ __global__ __launch_bounds__(256) void chi0_f32_kernel(Chi0Args a, const float2 
     }
   }
 
-  f4 accR[2][2], accI[2][2];
-  double hR[2][2][4], hI[2][2][4];
+  f4 accR[NP][2][2], accI[NP][2][2];
+  double hR[NP][2][2][4], hI[NP][2][2][4];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int p = 0; p < NP; ++p)
 #pragma unroll
-    for (int y = 0; y < 2; ++y) {
-      accR[x][y] = f4{0.f, 0.f, 0.f, 0.f};
-      accI[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) hR[x][y][r] = hI[x][y][r] = 0.0;
-    }
+      for (int y = 0; y < 2; ++y) {
+        accR[p][x][y] = f4{0.f, 0.f, 0.f, 0.f};
+        accI[p][x][y] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) hR[p][x][y][r] = hI[p][x][y][r] = 0.0;
+      }
 
   float2 sa[NPASS][4], sb[NPASS][4];
-  double sw[NPASS];
+  double sw[NPASS][NP];
   bool smv[NPASS];
-  auto load = [&](int m0) {
+  auto load = [&](int m0) __attribute__((always_inline)) {
 #pragma unroll
     for (int ps = 0; ps < NPASS; ++ps) {
       const int m = m0 + ps * RPI + lrow;
       smv[ps] = m < M;
       const int mc = smv[ps] ? m : 0;
-      sw[ps] = wrow[mc];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) sw[ps][p] = wrow[p][mc];
       const int64_t ro = (int64_t)mc * N;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
@@ -233,70 +258,100 @@ __global__ __launch_bounds__(256) void chi0_f32_kernel(Chi0Args a, const float2 
       }
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
     for (int ps = 0; ps < NPASS; ++ps) {
-      const float w = smv[ps] ? (float)sw[ps] : 0.f;
+      if constexpr (NP == 1) {
+        const float w = smv[ps] ? (float)sw[ps][0] : 0.f;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const float2 z = make_float2(0.f, 0.f);
-        const float2 x = (smv[ps] && pok[c]) ? sa[ps][c] : z;
-        const float2 y = qok[c] ? sb[ps][c] : z;
-        lds[buf][0][ps * RPI + lrow][lc + 16 * c] = x;
-        lds[buf][1][ps * RPI + lrow][lc + 16 * c] = make_float2(w * y.x, w * y.y);
+        for (int c = 0; c < 4; ++c) {
+          const float2 z = make_float2(0.f, 0.f);
+          const float2 x = (smv[ps] && pok[c]) ? sa[ps][c] : z;
+          const float2 y = qok[c] ? sb[ps][c] : z;
+          lds[buf][0][ps * RPI + lrow][lc + 16 * c] = x;
+          lds[buf][1][ps * RPI + lrow][lc + 16 * c] = make_float2(w * y.x, w * y.y);
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const float2 x = sa[ps][c], y = sb[ps][c];
+          const bool aok = smv[ps] && pok[c];
+          lds[buf][0][ps * RPI + lrow][lc + 16 * c] = make_float2(aok ? x.x : 0.f, aok ? x.y : 0.f);
+          lds[buf][1][ps * RPI + lrow][lc + 16 * c] = make_float2(qok[c] ? y.x : 0.f, qok[c] ? y.y : 0.f);
+        }
+        if (lc == 0) {
+#pragma unroll
+          for (int p = 0; p < NP; ++p) lw[buf][p][ps * RPI + lrow] = smv[ps] ? (float)sw[ps][p] : 0.f;
+        }
       }
     }
   };
   // MASKED: only the blocks marked in `on` (diagonal tiles)
-  auto contract = [&](int buf, auto masked) {
+  auto contract = [&](int buf, auto masked) __attribute__((always_inline)) {
     constexpr bool MASKED = decltype(masked)::value;
 #pragma unroll
     for (int ks = 0; ks < KT / 4; ++ks) {
+      const int r = ks * 4 + lk;
       float2 av[2], bv[2];
 #pragma unroll
-      for (int x = 0; x < 2; ++x) av[x] = lds[buf][0][ks * 4 + lk][wr * 32 + x * 16 + li];
+      for (int x = 0; x < 2; ++x) av[x] = lds[buf][0][r][wr * 32 + x * 16 + li];
 #pragma unroll
-      for (int y = 0; y < 2; ++y) bv[y] = lds[buf][1][ks * 4 + lk][wc * 32 + y * 16 + li];
+      for (int y = 0; y < 2; ++y) bv[y] = lds[buf][1][r][wc * 32 + y * 16 + li];
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+      for (int p = 0; p < NP; ++p) {
+        float2 bw[2];
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
-          if (!MASKED || (on & (1 << (2 * x + y)))) accR[x][y] = mfma32(av[x].x, bv[y].x, accR[x][y]);
+        for (int y = 0; y < 2; ++y) {
+          if constexpr (NP == 1) {
+            bw[y] = bv[y];
+          } else {
+            const float wp = lw[buf][p][r];
+            bw[y] = make_float2(wp * bv[y].x, wp * bv[y].y);
+          }
+        }
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+        for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
-          if (!MASKED || (on & (1 << (2 * x + y)))) accI[x][y] = mfma32(av[x].x, bv[y].y, accI[x][y]);
+          for (int y = 0; y < 2; ++y)
+            if (!MASKED || (on & (1 << (2 * x + y)))) accR[p][x][y] = mfma32(av[x].x, bw[y].x, accR[p][x][y]);
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+        for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
-          if (!MASKED || (on & (1 << (2 * x + y)))) accR[x][y] = mfma32(av[x].y, bv[y].y, accR[x][y]);
+          for (int y = 0; y < 2; ++y)
+            if (!MASKED || (on & (1 << (2 * x + y)))) accI[p][x][y] = mfma32(av[x].x, bw[y].y, accI[p][x][y]);
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+        for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
-          if (!MASKED || (on & (1 << (2 * x + y)))) accI[x][y] = mfma32(-av[x].y, bv[y].x, accI[x][y]);
+          for (int y = 0; y < 2; ++y)
+            if (!MASKED || (on & (1 << (2 * x + y)))) accR[p][x][y] = mfma32(av[x].y, bw[y].y, accR[p][x][y]);
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+            if (!MASKED || (on & (1 << (2 * x + y)))) accI[p][x][y] = mfma32(-av[x].y, bw[y].x, accI[p][x][y]);
+      }
     }
   };
-  auto flush = [&]() {
+  auto flush = [&]() __attribute__((always_inline)) {
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int p = 0; p < NP; ++p)
 #pragma unroll
-      for (int y = 0; y < 2; ++y) {
+      for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          hR[x][y][r] += (double)accR[x][y][r];
-          hI[x][y][r] += (double)accI[x][y][r];
+        for (int y = 0; y < 2; ++y) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            hR[p][x][y][r] += (double)accR[p][x][y][r];
+            hI[p][x][y][r] += (double)accI[p][x][y][r];
+          }
+          accR[p][x][y] = f4{0.f, 0.f, 0.f, 0.f};
+          accI[p][x][y] = f4{0.f, 0.f, 0.f, 0.f};
         }
-        accR[x][y] = f4{0.f, 0.f, 0.f, 0.f};
-        accI[x][y] = f4{0.f, 0.f, 0.f, 0.f};
-      }
   };
 
   constexpr int FLUSH_STEPS = FLUSH_ROWS / KT;
   const int nsteps = M > mlo ? (M - mlo + KT - 1) / KT : 1;
-  auto run = [&](auto masked) {
+  auto run = [&](auto masked) __attribute__((always_inline)) {
     load(mlo);
     store(0);
     __syncthreads();
@@ -316,30 +371,35 @@ __global__ __launch_bounds__(256) void chi0_f32_kernel(Chi0Args a, const float2 
   if (is_diag) run(std::integral_constant<bool, true>{});
   else run(std::integral_constant<bool, false>{});
 
-  double2 *out = (blockIdx.z == 0 ? a.out : a.partial) + (int64_t)blockIdx.y * a.out_stride;
-  const double *dg = diag + (int64_t)blockIdx.y * N;
+  double2 *base = blockIdx.z == 0 ? a.out : a.partial + (int64_t)(blockIdx.z - 1) * a.split_stride;
   const bool first = blockIdx.z == 0;   // the exact diagonal enters once
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int p = 0; p < NP; ++p) {
+    if (!pon[p]) continue;
+    double2 *out = base + (int64_t)pidx[p] * a.out_stride;
+    const double *dg = diag + (int64_t)pidx[p] * N;
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        // f32 16x16 accumulator layout: register r of lane l holds row 4 (l/16) + r, column l%16
-        const int P = P0 + wr * 32 + x * 16 + 4 * lk + r;
-        const int Q = Q0 + wc * 32 + y * 16 + li;
-        if (P >= N || Q >= N || !(on & (1 << (2 * x + y)))) continue;
-        const double re = hR[x][y][r], im = hI[x][y][r];
-        if (is_diag) {
-          if (P < Q) continue;
-          if (P == Q) {
-            out[(int64_t)P * N + Q] = make_double2(first ? dg[P] : 0.0, 0.0);
-            continue;
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          // f32 16x16 accumulator layout: register r of lane l holds row 4 (l/16) + r, column l%16
+          const int P = P0 + wr * 32 + x * 16 + 4 * lk + r;
+          const int Q = Q0 + wc * 32 + y * 16 + li;
+          if (P >= N || Q >= N || !(on & (1 << (2 * x + y)))) continue;
+          const double re = hR[p][x][y][r], im = hI[p][x][y][r];
+          if (is_diag) {
+            if (P < Q) continue;
+            if (P == Q) {
+              out[(int64_t)P * N + Q] = make_double2(first ? dg[P] : 0.0, 0.0);
+              continue;
+            }
           }
+          out[(int64_t)P * N + Q] = make_double2(re, im);
+          out[(int64_t)Q * N + P] = make_double2(re, -im);
         }
-        out[(int64_t)P * N + Q] = make_double2(re, im);
-        out[(int64_t)Q * N + P] = make_double2(re, -im);
-      }
+  }
 }
 
 inline unsigned grid_for(int64_t n) {
@@ -490,7 +550,7 @@ __global__ __launch_bounds__(512) void chi0_f32_t128_kernel(Chi0Args a, const fl
   contract((nsteps - 1) & 1);
   flush();
 
-  double2 *out = (split == 0 ? a.out : a.partial) + (int64_t)p * a.out_stride;
+  double2 *out = (split == 0 ? a.out : a.partial + (int64_t)(split - 1) * a.split_stride) + (int64_t)p * a.out_stride;
   const double *dg = diag + (int64_t)p * N;
   const bool first = split == 0;   // the exact diagonal enters once
 #pragma unroll
@@ -549,12 +609,28 @@ hipError_t launch_diag_exact(hipStream_t s, const void *B, bool cplx, int64_t M,
   return hipSuccess;
 }
 
-hipError_t launch_chi0_mixed(hipStream_t s, const Chi0Args &a, int32_t npts, const float2 *B32,
+int f32_cfg_edge(int cfg) { return cfg == kF32T128 ? 128 : 64; }
+int f32_cfg_points_per_wg(int cfg) { return cfg == kF32T64W2 ? 2 : 1; }
+const char *f32_cfg_name(int cfg) { return cfg == kF32T128 ? "t128" : cfg == kF32T64W2 ? "t64w2" : "t64"; }
+
+hipError_t launch_chi0_mixed(hipStream_t s, const Chi0Args &args, int32_t npts, const float2 *B32,
                              const double *diag, int prec, int tile) {
   if (npts <= 0) return hipSuccess;
   if (prec != 1) return hipErrorInvalidValue;   // FP32 only; split-BF16 is chi0_bf16.hip
-  const int ks = a.ksplit > 1 ? 2 : 1;   // split 0 writes a.out, split 1 writes a.partial
-  if (tile == 128) {
+  if (args.ksplit > kMaxSplit) return hipErrorInvalidValue;
+  // split 0 writes a.out, split z >= 1 the z-th plane of a.partial (planes npts points apart)
+  const int ks = args.ksplit > 1 ? args.ksplit : 1;
+  Chi0Args a = args;
+  a.ksplit = ks;
+  a.split_stride = (int64_t)npts * a.out_stride;
+  // the paired kernel needs the launch's pair table; without one the single-point kernel
+  // of the same tile computes the same sums
+  if (tile == kF32T64W2 && (a.pairs == nullptr || a.npairs <= 0)) tile = kF32T64;
+  if (tile == kF32T64W2) {
+    const int T = (a.N + TN - 1) / TN;
+    const dim3 grid((unsigned)(T * (T + 1) / 2), (unsigned)a.npairs, (unsigned)ks);
+    hipLaunchKernelGGL((chi0_f32_kernel<16, 2>), grid, dim3(256), 0, s, a, B32, diag);
+  } else if (tile == kF32T128) {
     const int T = (a.N + TW32 - 1) / TW32;
     const int64_t nwg = (int64_t)T * (T + 1) / 2 * npts * ks;
     if (nwg > 0x7fffffff) return hipErrorInvalidValue;
@@ -563,11 +639,11 @@ hipError_t launch_chi0_mixed(hipStream_t s, const Chi0Args &a, int32_t npts, con
   } else {
     const int T = (a.N + TN - 1) / TN;
     const dim3 grid((unsigned)(T * (T + 1) / 2), (unsigned)npts, (unsigned)ks);
-    hipLaunchKernelGGL(chi0_f32_kernel<16>, grid, dim3(256), 0, s, a, B32, diag);
+    hipLaunchKernelGGL((chi0_f32_kernel<16, 1>), grid, dim3(256), 0, s, a, B32, diag);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || ks == 1) return e;
-  return launch_split_add(s, a.partial, 1, (int64_t)npts * a.out_stride, a.out);
+  return launch_split_add(s, a.partial, ks - 1, (int64_t)npts * a.out_stride, a.out);
 }
 
 }  // namespace rpa

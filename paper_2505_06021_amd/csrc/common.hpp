@@ -30,7 +30,7 @@ struct Chi0Args {
   double *wtab;             // [npts][M] w_m zeta_k of every contraction row
   double2 *out;             // [npts][N][N] complex
   int64_t out_stride;       // complex elements between outputs
-  int32_t ksplit;           // row splits (FP64: 1..kMaxSplit, reduced precision: 1..2): the
+  int32_t ksplit;           // row splits (FP64 and FP32: 1..kMaxSplit): the
                             // first writes out, split z >= 1 plane z - 1 of partial, and
                             // out += the planes in split order follows
   double2 *partial;         // [ksplit - 1][npts][N][N] (used when ksplit >= 2)
@@ -111,10 +111,16 @@ int64_t diag_exact_scratch_doubles(int64_t M, int N, int npts);
 hipError_t launch_diag_exact(hipStream_t s, const void *B, bool cplx, int64_t M, int N, const double *wtab,
                              int npts, double *scratch, double *diag);
 // chi0 with FP32 MFMA (prec 1) from the FP32 copy B32 (slab stride a.b_slot_stride), FP64
-// flush of partial sums and the exact diagonal `diag` [npts][N], on 64- or 128-wide tiles
-// (tile; both sum the same products in the same order).
+// flush of partial sums and the exact diagonal `diag` [npts][N], in one of three
+// configurations (tile): 64- or 128-wide tiles, or 64-wide tiles contracting the two points
+// of each entry of a.pairs per workgroup (without a pair table: the 64-wide kernel); all
+// sum the same products in the same order.  a.ksplit: 1..kMaxSplit row splits.
+constexpr int kF32T64 = 64, kF32T128 = 128, kF32T64W2 = 65;
+int f32_cfg_edge(int cfg);             // output tile edge
+int f32_cfg_points_per_wg(int cfg);    // 2 for the paired kernel
+const char *f32_cfg_name(int cfg);     // t64, t128, t64w2
 hipError_t launch_chi0_mixed(hipStream_t s, const Chi0Args &a, int32_t npts, const float2 *B32,
-                             const double *diag, int prec, int tile = 64);
+                             const double *diag, int prec, int tile = kF32T64);
 
 // ---- split-BF16 chi0 from prepared operands (chi0_bf16.hip) ------------------------
 // No FP32 sum of the contraction runs over more rows than this.

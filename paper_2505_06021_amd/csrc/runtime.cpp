@@ -381,9 +381,9 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
     if (bsplit && rbatch < 1) rbatch = 1;
     break;
   }
-  // FP64: two more partial planes per lane (up to four row splits per contraction launch)
+  // FP64 and FP32: two more partial planes per lane (up to four row splits per launch)
   // where the budget holds them; one plane (two splits) otherwise
-  const int tplanes = (!mixed && pbatch * per_pt + 2 * pbatch * nn * 16 <= rest / nlanes) ? kMaxSplit - 1 : 1;
+  const int tplanes = (!bsplit && pbatch * per_pt + 2 * pbatch * nn * 16 <= rest / nlanes) ? kMaxSplit - 1 : 1;
 
   Arena ar(ctx, use_cache);
   const bool prof = use_cache && ctx.profile;   // timing only on the synchronous path
@@ -619,7 +619,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
                                 chi0_cfg_points_per_wg(c) == 2 ? npairs : nb, tplanes + 1);
         RPA_TRY(tune_chi0_cfg(S, ca, nb, cplx, &cfg, ks_of));
       }
-      int f32_tile = 64;
+      int f32_tile = kF32T64;   // FP32 configuration (64- or 128-wide, or 64-wide paired)
       if (mixed && !bsplit) {
         // the exact FP64 diagonal first: the tile tuner launches the contraction
         int i0 = 0;
@@ -632,11 +632,17 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
                                     d_diag + (int64_t)i0 * N));
           i0 = i1;
         }
-        RPA_TRY(tune_f32_tile(S, ca, nb, cplx, d_B32, d_diag, &f32_tile));
-      }
-      if (mixed) {
-        const int64_t tn = bsplit ? 64 : f32_tile;
-        ca.ksplit = pick_split(tn, (tn == 128 ? 1LL : 2LL) * ncu, nb, 2);
+        const int f32_cfgs[3] = {kF32T64, kF32T128, kF32T64W2};
+        int f32_ks[3];
+        for (int c = 0; c < 3; ++c) {
+          const int e = f32_cfg_edge(f32_cfgs[c]);
+          f32_ks[c] = pick_split(e, (e == 128 ? 1LL : 2LL) * ncu, f32_cfg_points_per_wg(f32_cfgs[c]) == 2 ? npairs : nb,
+                                 tplanes + 1);
+        }
+        RPA_TRY(tune_f32_tile(S, ca, nb, cplx, d_B32, d_diag, &f32_tile, f32_ks));
+        ca.ksplit = f32_ks[f32_tile == kF32T128 ? 1 : f32_tile == kF32T64W2 ? 2 : 0];
+      } else if (bsplit) {
+        ca.ksplit = 1;   // the split-BF16 plan makes its own row splits
       } else {
         ca.ksplit = ks_of[cfg];
       }

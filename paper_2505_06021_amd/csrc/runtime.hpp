@@ -151,10 +151,12 @@ int tune_chi0_cfg(hipStream_t st, const Chi0Args &a, int npts, bool cplx, int *c
 // elements): fixed by RPA_BF16_TILE, else timed once per shape bucket and cached.
 int tune_bf16_tile(hipStream_t st, const Bf16Group &g, int64_t M, int N, int64_t slots, int64_t max_part, bool cplx,
                    int *tn_out);
-// Tile edge (64 or 128) of the FP32 contraction of npts points (a.out holds them; it is
-// overwritten): fixed by RPA_F32_TILE, else timed once per shape bucket and cached.
+// Configuration (kF32T64, kF32T128, kF32T64W2) of the FP32 contraction of npts points
+// (a.out and a.partial hold them; they are overwritten): fixed by RPA_F32_TILE (64, 128,
+// 64w2), else timed once per shape bucket and cached.  ksplit_of (null: all 1) gives the
+// row split count of each configuration in that order; the candidates are timed with it.
 int tune_f32_tile(hipStream_t st, const Chi0Args &a, int npts, bool cplx, const float2 *B32, const double *diag,
-                  int *tile_out);
+                  int *tile_out, const int *ksplit_of = nullptr);
 // "bucket configuration" lines of the choices made so far; returns the full length.
 int tuned_entries(char *buf, int len);
 // RPA_TRLN_SINGLE=1 selects the one-workgroup-per-matrix Cholesky instead of the blocked one.

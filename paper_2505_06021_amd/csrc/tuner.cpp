@@ -1,7 +1,8 @@
 // Autotuner of the chi0 contractions' tile shapes: the FP64 contraction's tile and
-// K-step depth, and the FP32 and split-BF16 contractions' tile edges (64 or 128;
-// RPA_F32_TILE and RPA_BF16_TILE fix them; RPA_TUNE_VERBOSE=1 prints the timings of the
-// reduced-precision candidates).
+// K-step depth, the FP32 contraction's configuration (64- or 128-wide tiles, or 64-wide
+// tiles with two frequencies per workgroup) and the split-BF16 contraction's tile edge
+// (RPA_F32_TILE=64|128|64w2 and RPA_BF16_TILE=64|128 fix them; RPA_TUNE_VERBOSE=1 prints
+// the candidates' timings).
 //
 // Candidates (launch_chi0_f64 configurations): 64-wide tiles with 8, 16 or 32 rows per
 // LDS step (two workgroups per CU), 128-wide tiles with 16-row steps (one per CU), and
@@ -50,8 +51,13 @@ void load_cache_locked() {
   std::ifstream f(p);
   std::string key, name;
   while (f >> key >> name) {
-    if (key.compare(0, 5, "bf16_") == 0 || key.compare(0, 4, "f32_") == 0) {
+    if (key.compare(0, 5, "bf16_") == 0) {
       if (name == "t64" || name == "t128") g_tuned[key] = name == "t64" ? 64 : 128;
+      continue;
+    }
+    if (key.compare(0, 4, "f32_") == 0) {
+      for (int c : {kF32T64, kF32T128, kF32T64W2})
+        if (name == f32_cfg_name(c)) g_tuned[key] = c;
       continue;
     }
     const int c = cfg_by_name(name);
@@ -60,7 +66,8 @@ void load_cache_locked() {
 }
 
 std::string entry_name(const std::string &key, int v) {
-  if (key.compare(0, 5, "bf16_") == 0 || key.compare(0, 4, "f32_") == 0) return v == 64 ? "t64" : "t128";
+  if (key.compare(0, 5, "bf16_") == 0) return v == 64 ? "t64" : "t128";
+  if (key.compare(0, 4, "f32_") == 0) return f32_cfg_name(v);
   return chi0_cfg_name(v);
 }
 
@@ -221,17 +228,17 @@ int tune_bf16_tile(hipStream_t st, const Bf16Group &g, int64_t M, int N, int64_t
 }
 
 int tune_f32_tile(hipStream_t st, const Chi0Args &a, int npts, bool cplx, const float2 *B32, const double *diag,
-                  int *tile_out) {
+                  int *tile_out, const int *ksplit_of) {
   if (const char *e = getenv("RPA_F32_TILE")) {
-    const int v = atoi(e);
-    if (v == 64 || v == 128) {
-      *tile_out = v;
+    const std::string v = e;
+    if (v == "64" || v == "128" || v == "64w2") {
+      *tile_out = v == "64" ? kF32T64 : v == "128" ? kF32T128 : kF32T64W2;
       return RPA_OK;
     }
   }
   if (const char *t = getenv("RPA_TUNE"))
     if (t[0] == '0') {
-      *tile_out = 64;
+      *tile_out = kF32T64;
       return RPA_OK;
     }
   int mlog = 0;
@@ -247,29 +254,33 @@ int tune_f32_tile(hipStream_t st, const Chi0Args &a, int npts, bool cplx, const 
     *tile_out = it->second;
     return RPA_OK;
   }
-  // both tile edges on the first 16384 rows, one row split, into the launch's own output
-  // (overwritten by the real launch); long enough that each workgroup reaches its steady
-  // state (short runs favour the 64-wide tile)
-  Chi0Args t = a;
-  t.M = a.M < 16384 ? a.M : 16384;
-  t.ksplit = 1;
-  const int cands[2] = {64, 128};
+  // the three configurations, each with the row split count the launch would give it and
+  // 8192 rows per split, into the launch's own output and partial planes (overwritten by
+  // the real launch); long enough that each workgroup reaches its steady state (short
+  // runs favour the 64-wide tile); compare time per row
+  const int cands[3] = {kF32T64, kF32T128, kF32T64W2};
   float best_ms = 1e30f;
-  int best = 64;
+  int best = kF32T64;
   hipEvent_t e0, e1;
   RPA_HIP(hipEventCreate(&e0));
   RPA_HIP(hipEventCreate(&e1));
   for (int rep = 0; rep < 2; ++rep) {
-    for (int tile : cands) {
+    for (int ci = 0; ci < 3; ++ci) {
+      const int tile = cands[ci];
+      if (f32_cfg_points_per_wg(tile) == 2 && (a.pairs == nullptr || a.npairs == npts)) continue;
+      Chi0Args t = a;
+      t.ksplit = ksplit_of ? ksplit_of[ci] : 1;
+      t.M = a.M < 8192LL * t.ksplit ? a.M : 8192LL * t.ksplit;
       RPA_HIP(hipEventRecord(e0, st));
       RPA_HIP(launch_chi0_mixed(st, t, npts, B32, diag, 1, tile));
       RPA_HIP(hipEventRecord(e1, st));
       RPA_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
       RPA_HIP(hipEventElapsedTime(&ms, e0, e1));
+      ms /= (float)t.M;
       if (rep == 1 && getenv("RPA_TUNE_VERBOSE"))
-        fprintf(stderr, "[tune] %s t%d: %.4f ms (%lld rows, %d points)\n", key.c_str(), tile, ms, (long long)t.M,
-                npts);
+        fprintf(stderr, "[tune] %s %s: %.3e ms per row (%d splits, %lld rows, %d points)\n", key.c_str(),
+                f32_cfg_name(tile), ms, t.ksplit, (long long)t.M, npts);
       if (rep == 1 && ms < best_ms) {
         best_ms = ms;
         best = tile;

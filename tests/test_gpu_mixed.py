@@ -181,7 +181,7 @@ def test_fp32_tile_edges_agree_bitwise(ctx, monkeypatch):
     assert np.array_equal(got["64"], got["128"])
 
 
-@pytest.mark.parametrize("tile", ["64", "128"])
+@pytest.mark.parametrize("tile", ["64", "128", "64w2"])
 def test_energy_fp32_tile_edges(ctx, monkeypatch, tile):
     monkeypatch.setenv("RPA_F32_TILE", tile)
     s = ragged(3)
@@ -189,3 +189,26 @@ def test_energy_fp32_tile_edges(ctx, monkeypatch, tile):
     E, _ = ctx.energy(s, prec=FP32)
     E64, _ = ctx.energy(s)
     assert abs(E - E64) <= TOL_E[FP32]
+
+
+@pytest.mark.parametrize("nw", [3, 4])
+def test_fp32_configurations_and_row_splits(ctx, monkeypatch, nw):
+    # the FP32 configurations (64-wide, 128-wide, 64-wide with two frequencies of a q per
+    # workgroup) at one to four row splits (later splits into partial planes, added in
+    # split order): every energy within the FP32 bound of the oracle; at equal split
+    # counts the 64-wide kernels sum the same float products in the same order, so the
+    # paired kernel's per-point energies equal the single-point kernel's bit for bit
+    # sigma^2 N_occ N_virt = 1.61 as in the benchmark slabs (|E| of a few hundred Ha)
+    s = inputs.make_system("f32pairs", (2, 2, 1), 8, 150, 200, nw, 47, is_complex=True,
+                           sigma=(1.61 / (8 * 150)) ** 0.5)
+    e_ref, g_ref = orc.energy(s)
+    got = {}
+    for ks in (1, 2, 3, 4):
+        monkeypatch.setenv("RPA_CHI0_KSPLIT", str(ks))
+        for tile in ("64", "128", "64w2"):
+            monkeypatch.setenv("RPA_F32_TILE", tile)
+            say(f"energy fp32 {tile} with {ks} row splits, nw={nw}")
+            E, g = ctx.energy(s, prec=FP32)
+            assert abs(E - e_ref) <= TOL_E[FP32], (tile, ks, E - e_ref)
+            got[(tile, ks)] = g
+        assert np.array_equal(got[("64w2", ks)], got[("64", ks)]), ks

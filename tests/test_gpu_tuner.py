@@ -109,7 +109,7 @@ def test_fp32_tile_tuner_records_choice(ctx, monkeypatch):
     say("energy fp32 with the tile tuner")
     E, _ = ctx.energy(s, prec=1)
     choices = {k: v for k, v in rpa.tuned().items() if k.startswith("f32_")}
-    assert choices and all(v in ("t64", "t128") for v in choices.values()), choices
+    assert choices and all(v in ("t64", "t128", "t64w2") for v in choices.values()), choices
     assert abs(E - orc.energy(s)[0]) <= 1e-6
 
 
