@@ -233,17 +233,21 @@ int rpa_profile_read(rpa_ctx *ctx, rpa_kernel_times *out);
 
 /* Tile configurations of the chi0 contractions chosen so far in this process.
  * FP64 buckets ("f64_...") name the output tile edge and the rows of B staged per LDS
- * step (t64k8, t64k16, t64k32, t128k16); FP32 ("f32_...") and split-BF16 ("bf16_...")
- * buckets name the tile edge (t64, t128).  A choice changes the speed of the
- * contraction, never its FP64 sums (the chi0 equation of the periodic RPA section, summed
- * in the same row order by every FP64 configuration); each shape bucket is timed once on
- * its first launch.  Writes "bucket configuration" lines, NUL-terminated and truncated
- * to len bytes, into buf (caller-owned; may be NULL when len is 0) and the untruncated
- * length into *needed (may be NULL).  Environment: RPA_CHI0_CFG=<name> (or
- * RPA_CHI0_KT=8|16|32) fixes the FP64 configuration, RPA_F32_TILE=64|128 and
- * RPA_BF16_TILE=64|128 the reduced-precision tile edges, RPA_TUNE=0 keeps the defaults
- * (t64k16, t64, t128), RPA_TUNE_CACHE=<file> keeps the choices across processes.  Never
- * fails. */
+ * step (t64k8, t64k16, t64k32, t128k16, and t64k16w2: two frequencies of a q per
+ * workgroup); FP32 buckets ("f32_...") name t64, t128 or t64w2 (the paired 64-wide
+ * kernel), split-BF16 buckets ("bf16_...") the tile edge (t64, t128).  A choice changes
+ * the speed of the contraction, never its sums at a given row split count (the chi0
+ * equation of the periodic RPA section, summed in the same row order by every
+ * configuration of a precision); each shape bucket is timed once on its first launch,
+ * every candidate at the row split count the launch would give it.  Writes "bucket
+ * configuration" lines, NUL-terminated and truncated to len bytes, into buf
+ * (caller-owned; may be NULL when len is 0) and the untruncated length into *needed (may
+ * be NULL).  Environment: RPA_CHI0_CFG=<name> (or RPA_CHI0_KT=8|16|32) fixes the FP64
+ * configuration, RPA_F32_TILE=64|128|64w2 the FP32 one, RPA_BF16_TILE=64|128 the
+ * split-BF16 tile edge, RPA_CHI0_KSPLIT=1..4 the row split count of the FP64 and FP32
+ * contractions (capped by the partial planes the budget holds), RPA_TUNE=0 keeps the
+ * defaults (t64k16, t64, t128), RPA_TUNE_CACHE=<file> keeps the choices across
+ * processes.  Never fails. */
 int rpa_tuned(char *buf, int32_t len, int32_t *needed);
 
 #ifdef __cplusplus

@@ -318,7 +318,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
                                              ao_scratch_bytes(hs.nbas, hs.nocc, hs.naux)
                                        : 0;
   const int64_t small = (int64_t)(hs.eps_occ.size() + hs.eps_virt.size() + hs.zeta_k.size()) * 8 +
-                        (int64_t)hs.kq.size() * 4 + npts * 32 + 4096 + diag_scratch + ao_bytes;
+                        (int64_t)hs.kq.size() * 4 + npts * 32 + 4096 + ao_bytes;
 
   // distinct q's in order of first appearance; points grouped by q
   std::vector<int32_t> qs;
@@ -344,7 +344,8 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
     for (int i = g0; i < g0 + g && i < (int)qs.size(); ++i) c += (int64_t)by_q[qs[i]].size();
     return c;
   };
-  const int64_t one_split = bsplit_bytes(1);
+  // fixed per-lane buffers: one point's split-BF16 operands and the exact-diagonal scratch
+  const int64_t one_split = bsplit_bytes(1) + diag_scratch;
   int nlanes = (use_cache && lanes_wanted() > 1 && npts >= 8) ? 2 : 1;
   hipStream_t lane_st[2] = {st, nullptr};
   if (nlanes == 2) {
@@ -377,13 +378,13 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
     // points; a served job keeps launches of at most 16 points, which the fuser can merge
     // with other jobs' and which let concurrent jobs interleave)
     rbatch = bsplit ? std::min<int64_t>(pbatch, use_cache ? 128 : 16) : 0;
-    while (rbatch > 1 && pbatch * per_pt + bsplit_bytes(rbatch) > rest / nlanes) rbatch = rbatch * 3 / 4;
+    while (rbatch > 1 && pbatch * per_pt + bsplit_bytes(rbatch) + diag_scratch > rest / nlanes) rbatch = rbatch * 3 / 4;
     if (bsplit && rbatch < 1) rbatch = 1;
     break;
   }
   // FP64 and FP32: two more partial planes per lane (up to four row splits per launch)
   // where the budget holds them; one plane (two splits) otherwise
-  const int tplanes = (!bsplit && pbatch * per_pt + 2 * pbatch * nn * 16 <= rest / nlanes) ? kMaxSplit - 1 : 1;
+  const int tplanes = (!bsplit && pbatch * per_pt + one_split + 2 * pbatch * nn * 16 <= rest / nlanes) ? kMaxSplit - 1 : 1;
 
   Arena ar(ctx, use_cache);
   const bool prof = use_cache && ctx.profile;   // timing only on the synchronous path
