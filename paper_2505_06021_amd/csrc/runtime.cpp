@@ -371,7 +371,8 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
     const int64_t pb_cap = (rest / nlanes - one_split) / per_pt;
     int64_t max_group_pts = 0;
     for (size_t g0 = 0; g0 < qs.size(); g0 += gq) max_group_pts = std::max(max_group_pts, pts_of((int)g0, gq));
-    pbatch = std::min<int64_t>(pb_cap, (max_group_pts + nlanes - 1) / nlanes);
+    // at most 16384 points per batch: the point index is a grid dimension of the kernels
+    pbatch = std::min<int64_t>({pb_cap, (max_group_pts + nlanes - 1) / nlanes, (int64_t)16384});
     // points per split-BF16 sub-launch: as many as the rest of the budget holds
     // (a synchronous call takes one launch for a whole batch where memory allows: fewer
     // row splits, so less partial traffic, and each B slab is read once per run of its
