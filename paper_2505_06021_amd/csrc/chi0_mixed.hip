@@ -6,8 +6,10 @@
 //    errors do not cancel, is taken from an exact FP64 pass (diag_partial/diag_reduce)
 //    instead of the MFMA result.
 // The contraction reads B in FP32 (the device converts the FP64 coefficients once per
-// q), the right operand is scaled by w_m zeta_k in FP32 at the LDS store, and the output
-// is FP64 complex like the FP64 path's.  (The split-BF16 contraction is chi0_bf16.hip.)
+// q), the right operand is scaled by w_m zeta_k in FP32 (at the LDS store, or per lane
+// after the LDS read in the kernel that contracts two frequencies per workgroup), and the
+// output is FP64 complex like the FP64 path's.  (The split-BF16 contraction is
+// chi0_bf16.hip.)
 #include <type_traits>
 
 #include "common.hpp"

@@ -79,19 +79,21 @@ hipError_t launch_philox_words(hipStream_t s, uint64_t seed, int32_t nk, int32_t
 // Fill a.wtab for the npts points of a launch (must precede the contraction launch).
 hipError_t launch_chi0_weights(hipStream_t s, const Chi0Args &a, int32_t npts);
 // cfg selects the tile and K step: 0, 1, 2 = 64-wide tiles with 8, 16, 32-row steps,
-// 3 = 128-wide tiles with 16-row steps (all give the same sums in the same row order).
-// With a.ksplit == 2 the launch also adds the second half's result into a.out (fixed
-// order, repeatable).
+// 3 = 128-wide tiles with 16-row steps, 4 = 64-wide tiles with 16-row steps contracting
+// the two points of each a.pairs entry per workgroup (without a pair table: cfg 1); all
+// give the same sums in the same row order.  With a.ksplit = s > 1 (at most kMaxSplit)
+// splits 1..s-1 write planes of a.partial (npts points apart) and the launch then adds
+// them into a.out in split order (repeatable).
 hipError_t launch_chi0_f64(hipStream_t s, const Chi0Args &a, int32_t npts, bool cplx_b, int cfg);
 int chi0_cfg_count();
 int chi0_cfg_tile(int cfg);            // output tile edge of a configuration
 int chi0_cfg_slots_per_cu(int cfg);    // workgroups of it that fit on one CU
 int chi0_cfg_points_per_wg(int cfg);   // points one workgroup contracts (2: paired kernel)
 const char *chi0_cfg_name(int cfg);
-// Number of row splits (1 or 2) that best fills `slots` concurrent workgroups for `work` tiles.
+// Number of row splits (1..max_split) that best fills `slots` concurrent workgroups for
+// `work` workgroups of one split.
 int32_t chi0_pick_ksplit(int64_t work, int64_t slots, int64_t M, int32_t max_split);
-// out[i] += partial[i] for n complex elements.
-// out += partial[0] + ... + partial[nparts - 1] (planes of n elements), in that order
+// out += partial[0] + ... + partial[nparts - 1] (planes of n complex elements), in that order
 hipError_t launch_split_add(hipStream_t s, const double2 *partial, int32_t nparts, int64_t n, double2 *out);
 
 hipError_t launch_zgemm_f64(hipStream_t s, const GemmArgs &a, int32_t batch);
