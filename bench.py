@@ -39,9 +39,23 @@ def chi0_flops_per_point(s):
     return (4.0 if s.is_complex else 1.0) * M * N * (N + 1)
 
 
+def code_hash(text):
+    """Hash of a source text's code: // comments, trailing blanks and empty lines are left
+    out, so a change of comments alone keeps the counter records of a kernel valid."""
+    lines = []
+    for ln in text.splitlines():
+        i = ln.find("//")
+        if i >= 0:
+            ln = ln[:i]
+        ln = ln.rstrip()
+        if ln:
+            lines.append(ln)
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()[:16]
+
+
 def kernel_source_hash(name):
     p = os.path.join(ROOT, "paper_2505_06021_amd", "csrc", name)
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    return code_hash(open(p).read())
 
 
 def traffic_from_profiles(workload, prec):
