@@ -198,6 +198,9 @@ def main():
                     help="run a plain 1 GiB device copy first (scale reference for HBM counters)")
     ap.add_argument("--hbm-limit-gb", type=float, default=200.0,
                     help="device-memory admission limit of the serving context")
+    ap.add_argument("--host-inputs", action="store_true",
+                    help="hand the inputs over as host buffers, so each step includes their "
+                         "host-to-device copies (a PCIe-inclusive rate; the default keeps them in HBM)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -225,7 +228,7 @@ def main():
     s = make()
     npts = s.nq * s.nw
     ctx = rpa.Context(0)
-    m = rpa._Marshal(s, device=True)          # inputs resident in HBM before timing
+    m = rpa._Marshal(s, device=not args.host_inputs)   # inputs resident in HBM before timing
     prec = PREC_CODE[args.prec]
     print(f"[bench] {args.workload} prec={args.prec} points/step={npts} warmup={args.warmup} "
           f"steps={args.steps}", file=sys.stderr, flush=True)
@@ -279,7 +282,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f64"}[args.prec],
-        "data": "synthetic (seeded Philox B, Haar-random V, GL frequencies)",
+        "data": "synthetic (seeded Philox B, Haar-random V, GL frequencies)" +
+                ("; inputs handed over as host buffers (PCIe-inclusive)" if args.host_inputs else ""),
         "config": {"workload": args.workload, "grid": list(s.grid), "nk": s.nk, "nq": s.nq, "nk_occ": s.nk_occ, "nbas": s.nbas,
                    "nocc": s.nocc, "nvirt": s.nvirt, "naux": s.naux, "nw": s.nw,
                    "is_complex": s.is_complex, "chi0_precision": args.prec,

@@ -153,3 +153,20 @@ def test_row_splits_agree(ctx, monkeypatch, cfg):
             base = g
         else:
             assert np.max(np.abs(g - base)) <= 1e-12 * np.max(np.abs(base)), ks
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_paired_kernels_on_device_inputs(ctx, monkeypatch, prec):
+    # B and V^(1/2) resident on the device (the contraction reads the caller's slab of
+    # each q directly): the paired FP64 and FP32 kernels give the single-point kernels'
+    # energies bit for bit
+    s = inputs.make_system("pairdev", (2, 2, 1), 3, 9, 150, 5, 53, is_complex=True, sigma=0.15)
+    var, single, paired = ("RPA_CHI0_CFG", "t64k16", "t64k16w2") if prec == 0 else ("RPA_F32_TILE", "64", "64w2")
+    monkeypatch.setenv(var, single)
+    say(f"device inputs prec={prec}: single-point kernel")
+    e1, g1 = ctx.energy(s, prec=prec, device=True)
+    monkeypatch.setenv(var, paired)
+    say("  paired kernel")
+    e2, g2 = ctx.energy(s, prec=prec, device=True)
+    assert np.array_equal(g1, g2)
+    assert abs(e2 - orc.energy(s)[0]) <= (1e-10 * abs(e2) if prec == 0 else 1e-6)
