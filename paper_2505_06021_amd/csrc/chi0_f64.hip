@@ -307,6 +307,43 @@ __global__ __launch_bounds__(256) void chi0_f64_kernel(Chi0Args a) {
       }
 }
 
+// Diagonal tiles of the paired kernel: the ten 16 x 16 blocks on or below the diagonal
+// of a 64 x 64 tile, split five and five between two waves per point ("roles"); block u
+// of role R is (DIAG_BX[R][u], DIAG_BY[R][u]) in 16-row/column units.  Each block takes
+// the single-point kernel's four products per 4-row sub-step in the same order.
+__device__ constexpr int DIAG_BX[2][5] = {{0, 1, 1, 2, 3}, {2, 2, 3, 3, 3}};
+__device__ constexpr int DIAG_BY[2][5] = {{0, 0, 1, 0, 0}, {1, 2, 1, 2, 3}};
+
+template <int ROLE>
+__device__ __forceinline__ void contract_diag5(const double2 (*la)[LDP], const double2 (*lb)[LDP], const double *lwp,
+                                               int li, int lk, d4 (&dR)[5], d4 (&dI)[5]) {
+  constexpr bool needA[4] = {ROLE == 0, ROLE == 0, true, true};
+  constexpr bool needB[4] = {ROLE == 0, true, ROLE == 1, ROLE == 1};
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    const int r = ks * 4 + lk;
+    double2 av[4], bw[4];
+    const double w = lwp[r];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+      if (needA[x]) av[x] = la[r][x * 16 + li];
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+      if (needB[y]) {
+        const double2 b = lb[r][y * 16 + li];
+        bw[y] = make_double2(w * b.x, w * b.y);
+      }
+#pragma unroll
+    for (int u = 0; u < 5; ++u) dR[u] = mfma(av[DIAG_BX[ROLE][u]].x, bw[DIAG_BY[ROLE][u]].x, dR[u]);
+#pragma unroll
+    for (int u = 0; u < 5; ++u) dI[u] = mfma(av[DIAG_BX[ROLE][u]].x, bw[DIAG_BY[ROLE][u]].y, dI[u]);
+#pragma unroll
+    for (int u = 0; u < 5; ++u) dR[u] = mfma(av[DIAG_BX[ROLE][u]].y, bw[DIAG_BY[ROLE][u]].y, dR[u]);
+#pragma unroll
+    for (int u = 0; u < 5; ++u) dI[u] = mfma(-av[DIAG_BX[ROLE][u]].y, bw[DIAG_BY[ROLE][u]].x, dI[u]);
+  }
+}
+
 // Two frequencies of one q per workgroup.  The points of a q read the same coefficient
 // slab and differ only in the weights w_m zeta_k, so a workgroup stages the unweighted
 // panels of a 64 x 64 tile once and contracts them for both points: each lane scales its
@@ -316,6 +353,8 @@ __global__ __launch_bounds__(256) void chi0_f64_kernel(Chi0Args a) {
 // per barrier this does twice the MFMA work of the single-point kernel at the same LDS
 // footprint (two workgroups per CU).  blockIdx.y is a pair of points (a.pairs[2 y],
 // a.pairs[2 y + 1]) with the same slab; a second index of -1 leaves the pair single.
+// In diagonal tiles waves 0 and 1 take point 0's ten lower blocks, five each, and waves
+// 2 and 3 point 1's, so the busiest wave issues 5/8 of an off-diagonal tile's products.
 template <bool CPLX_B>
 __global__ __launch_bounds__(256) void chi0_f64_w2_kernel(Chi0Args a) {
   constexpr int KT = 16;
@@ -357,20 +396,8 @@ __global__ __launch_bounds__(256) void chi0_f64_w2_kernel(Chi0Args a) {
   }
 
   const int wave = tid >> 6, lane = tid & 63;
-  int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave >> 1, wc = wave & 1;
   const int li = lane & 15, lk = lane >> 4;
-  int on = 0xf;   // the diagonal-tile block assignment of the single-point kernel
-  if (diag) {
-    if (wr == 0 && wc == 1) {
-      wr = 1;
-      wc = 0;
-      on = 0xa;
-    } else if (wr == 1 && wc == 0) {
-      on = 0x5;
-    } else {
-      on = 0xd;
-    }
-  }
 
   d4 accR[2][2][2], accI[2][2][2];   // [point][x][y]
 #pragma unroll
@@ -412,8 +439,8 @@ __global__ __launch_bounds__(256) void chi0_f64_w2_kernel(Chi0Args a) {
       lw[buf][1][lrow] = mv ? sw1 : 0.0;
     }
   };
-  // one K step for both points; blocks outside `on` are skipped (uniform over the wave)
-  auto contract = [&](int buf, int onm) __attribute__((always_inline)) {
+  // one K step of an off-diagonal tile for both points
+  auto contract = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
     for (int ks = 0; ks < KT / 4; ++ks) {
       const int r = ks * 4 + lk;
@@ -432,27 +459,28 @@ __global__ __launch_bounds__(256) void chi0_f64_w2_kernel(Chi0Args a) {
         for (int x = 0; x < 2; ++x)
 #pragma unroll
           for (int y = 0; y < 2; ++y)
-            if (onm & (1 << (2 * x + y))) accR[p][x][y] = mfma(av[x].x, bw[y].x, accR[p][x][y]);
+            accR[p][x][y] = mfma(av[x].x, bw[y].x, accR[p][x][y]);
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
           for (int y = 0; y < 2; ++y)
-            if (onm & (1 << (2 * x + y))) accI[p][x][y] = mfma(av[x].x, bw[y].y, accI[p][x][y]);
+            accI[p][x][y] = mfma(av[x].x, bw[y].y, accI[p][x][y]);
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
           for (int y = 0; y < 2; ++y)
-            if (onm & (1 << (2 * x + y))) accR[p][x][y] = mfma(av[x].y, bw[y].y, accR[p][x][y]);
+            accR[p][x][y] = mfma(av[x].y, bw[y].y, accR[p][x][y]);
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
           for (int y = 0; y < 2; ++y)
-            if (onm & (1 << (2 * x + y))) accI[p][x][y] = mfma(-av[x].y, bw[y].x, accI[p][x][y]);
+            accI[p][x][y] = mfma(-av[x].y, bw[y].x, accI[p][x][y]);
       }
     }
   };
 
   const int nsteps = M > mlo ? (M - mlo + KT - 1) / KT : 1;
+  double2 *base = blockIdx.z == 0 ? a.out : a.partial + (int64_t)(blockIdx.z - 1) * a.split_stride;
   load(mlo);
   store(0);
   __syncthreads();
@@ -461,51 +489,78 @@ __global__ __launch_bounds__(256) void chi0_f64_w2_kernel(Chi0Args a) {
       const int cur = s & 1;
       load(mlo + (s + 1) * KT);
       __builtin_amdgcn_sched_barrier(0);
-      contract(cur, 0xf);
+      contract(cur);
       __builtin_amdgcn_sched_barrier(0);
       store(cur ^ 1);
       __syncthreads();
     }
-    contract((nsteps - 1) & 1, 0xf);
+    contract((nsteps - 1) & 1);
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      if (p == 1 && !two) break;
+      double2 *out = base + (int64_t)(p == 0 ? p0 : p1) * a.out_stride;
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int P = P0 + wr * 32 + x * 16 + lk + 4 * r;
+            const int Q = Q0 + wc * 32 + y * 16 + li;
+            if (P >= N || Q >= N) continue;
+            const double re = accR[p][x][y][r];
+            const double im = accI[p][x][y][r];
+            out[(int64_t)P * N + Q] = make_double2(re, im);
+            out[(int64_t)Q * N + P] = make_double2(re, -im);
+          }
+    }
   } else {
+    // wave (point pp, role): five of the point's ten lower blocks; a single point's
+    // second pair of waves only keeps the loads and barriers going
+    const int pp = wave >> 1, role = wave & 1;
+    const bool act = pp == 0 || two;
+    d4 dR[5], dI[5];
+#pragma unroll
+    for (int u = 0; u < 5; ++u) dR[u] = dI[u] = d4{0.0, 0.0, 0.0, 0.0};
+    auto cdiag = [&](int buf) __attribute__((always_inline)) {
+      if (!act) return;
+      if (role == 0)
+        contract_diag5<0>(lds[buf][0], lds[buf][1], lw[buf][pp], li, lk, dR, dI);
+      else
+        contract_diag5<1>(lds[buf][0], lds[buf][1], lw[buf][pp], li, lk, dR, dI);
+    };
     for (int s = 0; s + 1 < nsteps; ++s) {
       const int cur = s & 1;
       load(mlo + (s + 1) * KT);
       __builtin_amdgcn_sched_barrier(0);
-      contract(cur, on);
+      cdiag(cur);
       __builtin_amdgcn_sched_barrier(0);
       store(cur ^ 1);
       __syncthreads();
     }
-    contract((nsteps - 1) & 1, on);
-  }
-
-  double2 *base = blockIdx.z == 0 ? a.out : a.partial + (int64_t)(blockIdx.z - 1) * a.split_stride;
+    cdiag((nsteps - 1) & 1);
+    if (act) {
+      double2 *out = base + (int64_t)(pp == 0 ? p0 : p1) * a.out_stride;
 #pragma unroll
-  for (int p = 0; p < 2; ++p) {
-    if (p == 1 && !two) break;
-    double2 *out = base + (int64_t)(p == 0 ? p0 : p1) * a.out_stride;
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y)
+      for (int u = 0; u < 5; ++u) {
+        const int bx = role == 0 ? DIAG_BX[0][u] : DIAG_BX[1][u];
+        const int by = role == 0 ? DIAG_BY[0][u] : DIAG_BY[1][u];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int P = P0 + wr * 32 + x * 16 + lk + 4 * r;
-          const int Q = Q0 + wc * 32 + y * 16 + li;
-          if (P >= N || Q >= N || !(on & (1 << (2 * x + y)))) continue;
-          const double re = accR[p][x][y][r];
-          const double im = accI[p][x][y][r];
-          if (diag) {
-            if (P < Q) continue;
-            if (P == Q) {
-              out[(int64_t)P * N + Q] = make_double2(re, 0.0);
-              continue;
-            }
+          const int P = P0 + bx * 16 + lk + 4 * r;
+          const int Q = Q0 + by * 16 + li;
+          if (P >= N || Q >= N || P < Q) continue;
+          const double re = dR[u][r];
+          const double im = dI[u][r];
+          if (P == Q) {
+            out[(int64_t)P * N + Q] = make_double2(re, 0.0);
+            continue;
           }
           out[(int64_t)P * N + Q] = make_double2(re, im);
           out[(int64_t)Q * N + P] = make_double2(re, -im);
         }
+      }
+    }
   }
 }
 
