@@ -154,11 +154,49 @@ __device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
 
 constexpr int LDP32 = TN + 1;
 
+// Diagonal tiles of the paired kernel: the ten 16 x 16 blocks on or below the diagonal
+// of a 64 x 64 tile, split five and five between two waves per point ("roles"); block u
+// of role R is (DIAG_BX[R][u], DIAG_BY[R][u]) in 16-row/column units.  Each block takes
+// the single-point kernel's four products per 4-row sub-step in the same order.
+__device__ constexpr int DIAG_BX[2][5] = {{0, 1, 1, 2, 3}, {2, 2, 3, 3, 3}};
+__device__ constexpr int DIAG_BY[2][5] = {{0, 0, 1, 0, 0}, {1, 2, 1, 2, 3}};
+
+template <int KT, int ROLE>
+__device__ __forceinline__ void contract_diag5_f32(const float2 (*la)[LDP32], const float2 (*lb)[LDP32],
+                                                   const float *lwp, int li, int lk, f4 (&dR)[5], f4 (&dI)[5]) {
+  constexpr bool needA[4] = {ROLE == 0, ROLE == 0, true, true};
+  constexpr bool needB[4] = {ROLE == 0, true, ROLE == 1, ROLE == 1};
+#pragma unroll
+  for (int ks = 0; ks < KT / 4; ++ks) {
+    const int r = ks * 4 + lk;
+    float2 av[4], bw[4];
+    const float w = lwp[r];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+      if (needA[x]) av[x] = la[r][x * 16 + li];
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+      if (needB[y]) {
+        const float2 b = lb[r][y * 16 + li];
+        bw[y] = make_float2(w * b.x, w * b.y);
+      }
+#pragma unroll
+    for (int u = 0; u < 5; ++u) dR[u] = mfma32(av[DIAG_BX[ROLE][u]].x, bw[DIAG_BY[ROLE][u]].x, dR[u]);
+#pragma unroll
+    for (int u = 0; u < 5; ++u) dI[u] = mfma32(av[DIAG_BX[ROLE][u]].x, bw[DIAG_BY[ROLE][u]].y, dI[u]);
+#pragma unroll
+    for (int u = 0; u < 5; ++u) dR[u] = mfma32(av[DIAG_BX[ROLE][u]].y, bw[DIAG_BY[ROLE][u]].y, dR[u]);
+#pragma unroll
+    for (int u = 0; u < 5; ++u) dI[u] = mfma32(-av[DIAG_BX[ROLE][u]].y, bw[DIAG_BY[ROLE][u]].x, dI[u]);
+  }
+}
+
 // NP = 2: a workgroup contracts two frequencies of one q (a.pairs[2 y], a.pairs[2 y + 1],
 // the second -1 when single): the unweighted FP32 panels are staged once and each lane
 // scales its right-operand fragments by the two points' weights of its row (the same
 // float product w * b the single-point kernel forms at its LDS store, so the sums are bit
-// for bit the same); half the loads, LDS stores and barriers per MFMA.
+// for bit the same); half the loads, LDS stores and barriers per MFMA.  In diagonal tiles
+// waves 0 and 1 take point 0's ten lower blocks, five each, and waves 2 and 3 point 1's.
 template <int KT, int NP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void chi0_f32_kernel(Chi0Args a,
                                                                                               const float2 *B32,
@@ -353,6 +391,79 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
 
   constexpr int FLUSH_STEPS = FLUSH_ROWS / KT;
   const int nsteps = M > mlo ? (M - mlo + KT - 1) / KT : 1;
+  if constexpr (NP == 2) {
+    if (is_diag) {
+      // wave (point pp, role): five of the point's ten lower blocks, flushed to FP64 at
+      // the same rows as the single-point kernel; a single point's second pair of waves
+      // only keeps the loads and barriers going
+      const int pp = wave >> 1, role = wave & 1;
+      const bool act = pon[pp];
+      f4 dR[5], dI[5];
+      double gR[5][4], gI[5][4];
+#pragma unroll
+      for (int u = 0; u < 5; ++u) {
+        dR[u] = dI[u] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) gR[u][r] = gI[u][r] = 0.0;
+      }
+      auto cdiag = [&](int buf) __attribute__((always_inline)) {
+        if (!act) return;
+        if (role == 0)
+          contract_diag5_f32<KT, 0>(lds[buf][0], lds[buf][1], lw[buf][pp], li, lk, dR, dI);
+        else
+          contract_diag5_f32<KT, 1>(lds[buf][0], lds[buf][1], lw[buf][pp], li, lk, dR, dI);
+      };
+      auto dflush = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < 5; ++u) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            gR[u][r] += (double)dR[u][r];
+            gI[u][r] += (double)dI[u][r];
+          }
+          dR[u] = dI[u] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+      };
+      load(mlo);
+      store(0);
+      __syncthreads();
+      for (int s = 0; s + 1 < nsteps; ++s) {
+        const int cur = s & 1;
+        load(mlo + (s + 1) * KT);
+        __builtin_amdgcn_sched_barrier(0);
+        cdiag(cur);
+        __builtin_amdgcn_sched_barrier(0);
+        if ((s + 1) % FLUSH_STEPS == 0) dflush();
+        store(cur ^ 1);
+        __syncthreads();
+      }
+      cdiag((nsteps - 1) & 1);
+      dflush();
+      if (!act) return;
+      double2 *out = (blockIdx.z == 0 ? a.out : a.partial + (int64_t)(blockIdx.z - 1) * a.split_stride) +
+                     (int64_t)pidx[pp] * a.out_stride;
+      const double *dg = diag + (int64_t)pidx[pp] * N;
+      const bool first = blockIdx.z == 0;   // the exact diagonal enters once
+#pragma unroll
+      for (int u = 0; u < 5; ++u) {
+        const int bx = role == 0 ? DIAG_BX[0][u] : DIAG_BX[1][u];
+        const int by = role == 0 ? DIAG_BY[0][u] : DIAG_BY[1][u];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int P = P0 + bx * 16 + 4 * lk + r;
+          const int Q = Q0 + by * 16 + li;
+          if (P >= N || Q >= N || P < Q) continue;
+          if (P == Q) {
+            out[(int64_t)P * N + Q] = make_double2(first ? dg[P] : 0.0, 0.0);
+            continue;
+          }
+          out[(int64_t)P * N + Q] = make_double2(gR[u][r], gI[u][r]);
+          out[(int64_t)Q * N + P] = make_double2(gR[u][r], -gI[u][r]);
+        }
+      }
+      return;
+    }
+  }
   auto run = [&](auto masked) __attribute__((always_inline)) {
     load(mlo);
     store(0);
