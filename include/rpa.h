@@ -167,7 +167,11 @@ int rpa_trln(rpa_ctx *ctx, int32_t n, int32_t batch, int32_t is_complex, int32_t
 
 /* RPA correlation energy per cell: E (host double) and, if eps_qw != NULL, the integrand
  * eps(q, omega_j) [nq][nw] (host memory).  All steps run on the GPU; the q/omega sum is
- * taken on the device in a fixed order (q outer, omega inner).
+ * taken on the device in a fixed order (q outer, omega inner).  Environment: RPA_LANES=2
+ * splits the points into two batches on two streams, so one batch's sandwich and
+ * Cholesky overlap the other's contraction (a few percent faster; the two batches'
+ * contractions then also run side by side); RPA_TRLN_SINGLE=1 takes the
+ * one-workgroup-per-matrix Cholesky instead of the blocked one.
  * Errors: RPA_E_ARG, RPA_E_NOMEM, RPA_E_NOTSPD, RPA_E_DEVICE. */
 int rpa_energy(rpa_ctx *ctx, const rpa_system *sys, const rpa_freq *freq,
                rpa_precision prec, double *E, double *eps_qw);
@@ -201,6 +205,8 @@ int rpa_philox_words(rpa_ctx *ctx, uint64_t seed, int32_t nk, int32_t iq, int32_
  * rpa_poll waits up to timeout_ms (0 = do not wait, < 0 = forever) and returns
  * RPA_PENDING, or the job's final status with *out filled and, if eps_qw != NULL,
  * its [nq][nw] integrand; a finished job is consumed by the successful poll.
+ * Environment: RPA_SERVE_WORKERS (concurrent jobs, 1..16, default 4) and RPA_FUSE_WINDOW_US
+ * (how long the fuser waits for other jobs' small split-BF16 launches, default 300).
  * Errors: RPA_E_ARG, RPA_E_NOMEM, RPA_E_UNKNOWN_JOB, or the job's own error. */
 int rpa_submit(rpa_ctx *ctx, const rpa_system *sys, const rpa_freq *freq,
                rpa_precision prec, uint64_t *job_id);
