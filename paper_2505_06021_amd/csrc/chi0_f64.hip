@@ -361,16 +361,38 @@ __global__ __launch_bounds__(256) void chi0_f64_w2_kernel(Chi0Args a) {
   __shared__ double2 lds[2][2][KT][LDP];
   __shared__ double lw[2][2][KT];   // [buffer][point of the pair][row]
 
-  const int p0 = a.pairs[2 * blockIdx.y];
-  const int p1s = a.pairs[2 * blockIdx.y + 1];
+  // one-dimensional grid, off-diagonal tiles of every (pair, split) first and the shorter
+  // diagonal tiles last, so the last round of workgroups is made of short ones
+  const int T = (a.N + TN - 1) / TN;
+  const int noff = T * (T - 1) / 2;
+  const int64_t nunits = (int64_t)a.npairs * a.ksplit;
+  const int64_t g = blockIdx.x;
+  int tr, tc, pair, split;
+  if (g < (int64_t)noff * nunits) {
+    const int k = (int)(g % noff);               // strictly lower tile k: row r > column c
+    const int64_t u = g / noff;
+    int r = (int)((1.0 + sqrt(1.0 + 8.0 * (double)k)) * 0.5);
+    while (r * (r - 1) / 2 > k) --r;
+    while ((r + 1) * r / 2 <= k) ++r;
+    tr = r;
+    tc = k - r * (r - 1) / 2;
+    pair = (int)(u % a.npairs);
+    split = (int)(u / a.npairs);
+  } else {
+    const int64_t h = g - (int64_t)noff * nunits;
+    tr = tc = (int)(h % T);
+    const int64_t u = h / T;
+    pair = (int)(u % a.npairs);
+    split = (int)(u / a.npairs);
+  }
+  const int p0 = a.pairs[2 * pair];
+  const int p1s = a.pairs[2 * pair + 1];
   const bool two = p1s >= 0;
   const int p1 = two ? p1s : p0;
   const PointDesc pd = a.pts[p0];
-  int tr, tc;
-  tile_of((int)blockIdx.x, tr, tc);
   const int N = a.N;
   const int ms = (int)((((a.M + a.ksplit - 1) / a.ksplit) + KT - 1) / KT) * KT;
-  const int mlo = (int)blockIdx.z * ms;
+  const int mlo = split * ms;
   const int M = mlo + ms < (int)a.M ? mlo + ms : (int)a.M;
   const int P0 = tr * TN, Q0 = tc * TN;
   const bool diag = (tr == tc);
@@ -480,7 +502,7 @@ __global__ __launch_bounds__(256) void chi0_f64_w2_kernel(Chi0Args a) {
   };
 
   const int nsteps = M > mlo ? (M - mlo + KT - 1) / KT : 1;
-  double2 *base = blockIdx.z == 0 ? a.out : a.partial + (int64_t)(blockIdx.z - 1) * a.split_stride;
+  double2 *base = split == 0 ? a.out : a.partial + (int64_t)(split - 1) * a.split_stride;
   load(mlo);
   store(0);
   __syncthreads();
@@ -777,7 +799,9 @@ hipError_t launch_chi0_f64(hipStream_t s, const Chi0Args &args, int32_t npts, bo
   if (cfg == 4 && (a.pairs == nullptr || a.npairs <= 0)) cfg = 1;
   if (cfg == 4) {
     const int T = (a.N + TN - 1) / TN;
-    const dim3 grid((unsigned)(T * (T + 1) / 2), (unsigned)a.npairs, (unsigned)ks);
+    const int64_t nwg = (int64_t)T * (T + 1) / 2 * a.npairs * ks;
+    if (nwg > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)nwg);
     if (cplx_b)
       hipLaunchKernelGGL((chi0_f64_w2_kernel<true>), grid, dim3(256), 0, s, a);
     else
