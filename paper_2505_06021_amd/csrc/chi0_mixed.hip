@@ -206,25 +206,55 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
   constexpr int RPI = 16;
   constexpr int NPASS = KT / RPI;
 
+  // NP = 1: grid (tile, point, split).  NP = 2: a one-dimensional grid with the
+  // off-diagonal tiles of every (pair, split) first and the shorter diagonal tiles last,
+  // so the last round of workgroups is made of short ones.
+  int tr, tc, unit, split, nsplit;
+  if constexpr (NP == 1) {
+    tile_of((int)blockIdx.x, tr, tc);
+    unit = (int)blockIdx.y;
+    split = (int)blockIdx.z;
+    nsplit = (int)gridDim.z;
+  } else {
+    const int T = (a.N + TN - 1) / TN;
+    const int noff = T * (T - 1) / 2;
+    const int64_t nunits = (int64_t)a.npairs * a.ksplit;
+    const int64_t g = blockIdx.x;
+    int64_t u;
+    if (g < (int64_t)noff * nunits) {
+      const int k = (int)(g % noff);   // strictly lower tile k: row r > column c
+      u = g / noff;
+      int r = (int)((1.0 + sqrt(1.0 + 8.0 * (double)k)) * 0.5);
+      while (r * (r - 1) / 2 > k) --r;
+      while ((r + 1) * r / 2 <= k) ++r;
+      tr = r;
+      tc = k - r * (r - 1) / 2;
+    } else {
+      const int64_t h = g - (int64_t)noff * nunits;
+      tr = tc = (int)(h % T);
+      u = h / T;
+    }
+    unit = (int)(u % a.npairs);
+    split = (int)(u / a.npairs);
+    nsplit = a.ksplit;
+  }
   int pidx[NP];
   bool pon[NP];
   if constexpr (NP == 1) {
-    pidx[0] = (int)blockIdx.y;
+    pidx[0] = unit;
     pon[0] = true;
   } else {
-    pidx[0] = a.pairs[2 * blockIdx.y];
-    const int p1 = a.pairs[2 * blockIdx.y + 1];
+    pidx[0] = a.pairs[2 * unit];
+    const int p1 = a.pairs[2 * unit + 1];
     pon[0] = true;
     pon[1] = p1 >= 0;
     pidx[1] = p1 >= 0 ? p1 : pidx[0];
   }
   const PointDesc pd = a.pts[pidx[0]];
-  int tr, tc;
-  tile_of((int)blockIdx.x, tr, tc);
   const int N = a.N;
-  // rows [mlo, mhi) of the contraction belong to split blockIdx.z
-  const int ms = (int)((((a.M + gridDim.z - 1) / gridDim.z) + KT - 1) / KT) * KT;
-  const int mlo = (int)blockIdx.z * ms;
+  // rows [mlo, mhi) of the contraction belong to split `split`
+  const int ms = (int)((((a.M + nsplit - 1) / nsplit) + KT - 1) / KT) * KT;
+  const int mlo = split * ms;
   const int M = mlo + ms < (int)a.M ? mlo + ms : (int)a.M;
   const int P0 = tr * TN, Q0 = tc * TN;
   const bool is_diag = (tr == tc);
@@ -440,10 +470,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
       cdiag((nsteps - 1) & 1);
       dflush();
       if (!act) return;
-      double2 *out = (blockIdx.z == 0 ? a.out : a.partial + (int64_t)(blockIdx.z - 1) * a.split_stride) +
+      double2 *out = (split == 0 ? a.out : a.partial + (int64_t)(split - 1) * a.split_stride) +
                      (int64_t)pidx[pp] * a.out_stride;
       const double *dg = diag + (int64_t)pidx[pp] * N;
-      const bool first = blockIdx.z == 0;   // the exact diagonal enters once
+      const bool first = split == 0;   // the exact diagonal enters once
 #pragma unroll
       for (int u = 0; u < 5; ++u) {
         const int bx = role == 0 ? DIAG_BX[0][u] : DIAG_BX[1][u];
@@ -484,8 +514,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
   if (is_diag) run(std::integral_constant<bool, true>{});
   else run(std::integral_constant<bool, false>{});
 
-  double2 *base = blockIdx.z == 0 ? a.out : a.partial + (int64_t)(blockIdx.z - 1) * a.split_stride;
-  const bool first = blockIdx.z == 0;   // the exact diagonal enters once
+  double2 *base = split == 0 ? a.out : a.partial + (int64_t)(split - 1) * a.split_stride;
+  const bool first = split == 0;   // the exact diagonal enters once
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
     if (!pon[p]) continue;
@@ -741,8 +771,9 @@ hipError_t launch_chi0_mixed(hipStream_t s, const Chi0Args &args, int32_t npts, 
   if (tile == kF32T64W2 && (a.pairs == nullptr || a.npairs <= 0)) tile = kF32T64;
   if (tile == kF32T64W2) {
     const int T = (a.N + TN - 1) / TN;
-    const dim3 grid((unsigned)(T * (T + 1) / 2), (unsigned)a.npairs, (unsigned)ks);
-    hipLaunchKernelGGL((chi0_f32_kernel<16, 2>), grid, dim3(256), 0, s, a, B32, diag);
+    const int64_t nwg = (int64_t)T * (T + 1) / 2 * a.npairs * ks;
+    if (nwg > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((chi0_f32_kernel<16, 2>), dim3((unsigned)nwg), dim3(256), 0, s, a, B32, diag);
   } else if (tile == kF32T128) {
     const int T = (a.N + TW32 - 1) / TW32;
     const int64_t nwg = (int64_t)T * (T + 1) / 2 * npts * ks;
