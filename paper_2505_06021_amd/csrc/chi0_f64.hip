@@ -351,8 +351,9 @@ __device__ __forceinline__ void contract_diag5(const double2 (*la)[LDP], const d
 // w * b the single-point kernel forms before its LDS store, so the sums are bit for bit
 // those of that kernel) and the wave issues the MFMAs of both points.  Per loaded byte and
 // per barrier this does twice the MFMA work of the single-point kernel at the same LDS
-// footprint (two workgroups per CU).  blockIdx.y is a pair of points (a.pairs[2 y],
-// a.pairs[2 y + 1]) with the same slab; a second index of -1 leaves the pair single.
+// footprint (two workgroups per CU).  A workgroup serves pair j of the launch's pair
+// table (points a.pairs[2 j] and a.pairs[2 j + 1], on the same slab; a second index of
+// -1 leaves the pair single).
 // In diagonal tiles waves 0 and 1 take point 0's ten lower blocks, five each, and waves
 // 2 and 3 point 1's, so the busiest wave issues 5/8 of an off-diagonal tile's products.
 template <bool CPLX_B>

@@ -191,8 +191,8 @@ __device__ __forceinline__ void contract_diag5_f32(const float2 (*la)[LDP32], co
   }
 }
 
-// NP = 2: a workgroup contracts two frequencies of one q (a.pairs[2 y], a.pairs[2 y + 1],
-// the second -1 when single): the unweighted FP32 panels are staged once and each lane
+// NP = 2: a workgroup contracts two frequencies of one q (pair j of the launch's pair
+// table: a.pairs[2 j] and a.pairs[2 j + 1], the second -1 when single): the unweighted FP32 panels are staged once and each lane
 // scales its right-operand fragments by the two points' weights of its row (the same
 // float product w * b the single-point kernel forms at its LDS store, so the sums are bit
 // for bit the same); half the loads, LDS stores and barriers per MFMA.  In diagonal tiles
