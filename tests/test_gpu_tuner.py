@@ -170,3 +170,22 @@ def test_paired_kernels_on_device_inputs(ctx, monkeypatch, prec):
     e2, g2 = ctx.energy(s, prec=prec, device=True)
     assert np.array_equal(g1, g2)
     assert abs(e2 - orc.energy(s)[0]) <= (1e-10 * abs(e2) if prec == 0 else 1e-6)
+
+
+@pytest.mark.parametrize("naux", [40, 64, 65, 129])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_paired_kernels_small_and_ragged_tile_grids(ctx, monkeypatch, naux, prec):
+    # one tile (N <= 64: no off-diagonal tile at all), a ragged second tile row, and a
+    # one-column third tile row: the paired kernels' workgroup order (off-diagonal tiles
+    # first, diagonal tiles last) must cover every tile of every pair once
+    s = inputs.make_system("pairgrid", (2, 2, 1), 3, 7, naux, 3, 59, is_complex=True, sigma=0.15)
+    var, single, paired = ("RPA_CHI0_CFG", "t64k16", "t64k16w2") if prec == 0 else ("RPA_F32_TILE", "64", "64w2")
+    monkeypatch.setenv(var, single)
+    say(f"N_aux {naux} prec={prec}: single-point kernel")
+    e1, g1 = ctx.energy(s, prec=prec)
+    monkeypatch.setenv(var, paired)
+    say("  paired kernel")
+    e2, g2 = ctx.energy(s, prec=prec)
+    assert np.array_equal(g1, g2)
+    e_ref = orc.energy(s)[0]
+    assert abs(e2 - e_ref) <= (1e-10 * abs(e_ref) if prec == 0 else 1e-6)
