@@ -172,13 +172,14 @@ def test_paired_kernels_on_device_inputs(ctx, monkeypatch, prec):
     assert abs(e2 - orc.energy(s)[0]) <= (1e-10 * abs(e2) if prec == 0 else 1e-6)
 
 
+@pytest.mark.parametrize("is_complex", [True, False])
 @pytest.mark.parametrize("naux", [40, 64, 65, 129])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_paired_kernels_small_and_ragged_tile_grids(ctx, monkeypatch, naux, prec):
+def test_paired_kernels_small_and_ragged_tile_grids(ctx, monkeypatch, naux, prec, is_complex):
     # one tile (N <= 64: no off-diagonal tile at all), a ragged second tile row, and a
     # one-column third tile row: the paired kernels' workgroup order (off-diagonal tiles
     # first, diagonal tiles last) must cover every tile of every pair once
-    s = inputs.make_system("pairgrid", (2, 2, 1), 3, 7, naux, 3, 59, is_complex=True, sigma=0.15)
+    s = inputs.make_system("pairgrid", (2, 2, 1), 3, 7, naux, 3, 59, is_complex=is_complex, sigma=0.15)
     var, single, paired = ("RPA_CHI0_CFG", "t64k16", "t64k16w2") if prec == 0 else ("RPA_F32_TILE", "64", "64w2")
     monkeypatch.setenv(var, single)
     say(f"N_aux {naux} prec={prec}: single-point kernel")
