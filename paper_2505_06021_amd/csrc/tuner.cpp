@@ -17,6 +17,7 @@
 // (t64k8, t64k16, t64k32, t128k16, t64k16w2) or the older RPA_CHI0_KT=8|16|32 fixes the
 // configuration (read on every launch); RPA_TUNE=0 keeps t64k16; RPA_TUNE_CACHE names a
 // text file that keeps the choices across processes ("bucket name" lines).
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -25,6 +26,7 @@
 #include <mutex>
 #include <sstream>
 #include <string>
+#include <vector>
 
 #include "runtime.hpp"
 
@@ -32,6 +34,9 @@ namespace rpa {
 namespace {
 
 constexpr int kDefaultCfg = 1;   // 64-wide tiles, 16-row steps
+constexpr int kTuneReps = 4;     // timing rounds per candidate (the first one warms up)
+constexpr int kBf16TuneReps = 3;           // split-BF16: fewer, longer rounds
+constexpr double kBf16TuneMs = 5.0;        // split-BF16: time budget of one timed launch
 
 std::mutex g_tune_mu;
 std::map<std::string, int> g_tuned;
@@ -123,13 +128,15 @@ int tune_chi0_cfg(hipStream_t st, const Chi0Args &a, int npts, bool cplx, int *c
   // count the launch would use with it (so the candidates fill the GPU as the real
   // launches do), 4096 rows per split (enough K steps for a steady state, few enough that
   // tuning costs a fraction of one launch); compare time per row
-  float best_ms = 1e30f;
-  int best = kDefaultCfg;
+  // kTuneReps rounds, the first to warm code and caches, the candidates in alternating
+  // order; each candidate keeps its best time (clock and power drift between rounds)
+  std::vector<float> tmin(chi0_cfg_count(), 1e30f);
   hipEvent_t e0, e1;
   RPA_HIP(hipEventCreate(&e0));
   RPA_HIP(hipEventCreate(&e1));
-  for (int rep = 0; rep < 2; ++rep) {   // the first round warms code and caches
-    for (int c = 0; c < chi0_cfg_count(); ++c) {
+  for (int rep = 0; rep < kTuneReps; ++rep) {
+    for (int ci = 0; ci < chi0_cfg_count(); ++ci) {
+      const int c = rep % 2 ? chi0_cfg_count() - 1 - ci : ci;
       if (chi0_cfg_points_per_wg(c) == 2 && (a.pairs == nullptr || a.npairs == npts)) continue;
       Chi0Args t = a;
       t.ksplit = ksplit_of ? ksplit_of[c] : 1;
@@ -141,17 +148,17 @@ int tune_chi0_cfg(hipStream_t st, const Chi0Args &a, int npts, bool cplx, int *c
       float ms = 0.f;
       RPA_HIP(hipEventElapsedTime(&ms, e0, e1));
       ms /= (float)t.M;
-      if (rep == 1 && getenv("RPA_TUNE_VERBOSE"))
-        fprintf(stderr, "[tune] %s %s: %.3e ms per row (%d splits, %lld rows)\n", key.c_str(), chi0_cfg_name(c), ms,
-                t.ksplit, (long long)t.M);
-      if (rep == 1 && ms < best_ms) {
-        best_ms = ms;
-        best = c;
-      }
+      if (rep > 0 && ms < tmin[c]) tmin[c] = ms;
+      if (rep == kTuneReps - 1 && getenv("RPA_TUNE_VERBOSE"))
+        fprintf(stderr, "[tune] %s %s: %.3e ms per row (%d splits, %lld rows)\n", key.c_str(), chi0_cfg_name(c),
+                tmin[c], t.ksplit, (long long)t.M);
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  int best = kDefaultCfg;
+  for (int c = 0; c < chi0_cfg_count(); ++c)
+    if (tmin[c] < tmin[best]) best = c;
   g_tuned[key] = best;
   store_cache_locked();
   *cfg_out = best;
@@ -185,42 +192,46 @@ int tune_bf16_tile(hipStream_t st, const Bf16Group &g, int64_t M, int N, int64_t
     *tn_out = it->second;
     return RPA_OK;
   }
-  // time both tile edges with their real split count (so the launches fill the GPU as the
-  // real ones do) but at most 32 steps (1024 rows) per split, into the group's partial
+  // time both tile edges with their real plan (split count and full split length: a
+  // 128-wide tile writes a four times larger partial tile at the end of its split, so
+  // shortened splits favour the 64-wide one) on the group's first npts_t points: all of
+  // them when the launch is short (its last round of workgroups then weighs as in the
+  // real launch), else as many as take about kBf16TuneMs.  Into the group's partial
   // buffer (which the real launch overwrites wherever the reduction reads); compare time
-  // per contraction step
+  // per point.
+  const double issued_pt = (cplx ? 4.0 : 1.0) * 3.0 * (double)M * N * (N + 1.0);
+  const double est_ms = issued_pt * g.npts / 1.0e12;   // at about 1 PFLOP/s issued
+  int npts_t = g.npts;
+  if (est_ms > kBf16TuneMs) npts_t = std::max(1, (int)(g.npts * kBf16TuneMs / est_ms));
   const int cands[2] = {128, 64};
-  float best_ms = 1e30f;
-  int best = 128;
+  float tmin[2] = {1e30f, 1e30f};
   hipEvent_t e0, e1;
   RPA_HIP(hipEventCreate(&e0));
   RPA_HIP(hipEventCreate(&e1));
-  for (int rep = 0; rep < 2; ++rep) {
-    for (int tn : cands) {
+  for (int rep = 0; rep < kBf16TuneReps; ++rep) {
+    for (int cj = 0; cj < 2; ++cj) {
+      const int ci = rep % 2 ? 1 - cj : cj;
+      const int tn = cands[ci];
       Bf16Group t = g;
       bf16_plan(M, N, g.npts, slots, max_part, tn, &t.pl);
       if (max_part > 0 && bf16_partial_elems(t.pl, g.npts) > max_part) continue;
-      t.pl.kc_per_split = t.pl.kc_per_split < 32 ? t.pl.kc_per_split : 32;
-      const int64_t steps = (int64_t)t.pl.nsplit * t.pl.kc_per_split;
-      t.pl.nkc = t.pl.nkc < steps ? t.pl.nkc : steps;
+      t.npts = npts_t;
       RPA_HIP(hipEventRecord(e0, st));
       RPA_HIP(launch_bf16_herk_groups(st, &t, 1, cplx));
       RPA_HIP(hipEventRecord(e1, st));
       RPA_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
       RPA_HIP(hipEventElapsedTime(&ms, e0, e1));
-      ms /= (float)t.pl.nkc;   // the candidates cover different numbers of steps: per step
-      if (rep == 1 && getenv("RPA_TUNE_VERBOSE"))
-        fprintf(stderr, "[tune] %s t%d: %.6f ms per step (%d splits x %d steps, %d tiles)\n", key.c_str(), tn, ms,
-                t.pl.nsplit, t.pl.kc_per_split, t.pl.ntiles);
-      if (rep == 1 && ms < best_ms) {
-        best_ms = ms;
-        best = tn;
-      }
+      ms /= (float)npts_t;
+      if (rep > 0 && ms < tmin[ci]) tmin[ci] = ms;
+      if (rep == kBf16TuneReps - 1 && getenv("RPA_TUNE_VERBOSE"))
+        fprintf(stderr, "[tune] %s t%d: %.4f ms per point (%d of %d points, %d splits x %d steps, %d tiles)\n",
+                key.c_str(), tn, tmin[ci], npts_t, g.npts, t.pl.nsplit, t.pl.kc_per_split, t.pl.ntiles);
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  const int best = tmin[1] < tmin[0] ? cands[1] : cands[0];
   g_tuned[key] = best;
   store_cache_locked();
   *tn_out = best;
@@ -259,13 +270,13 @@ int tune_f32_tile(hipStream_t st, const Chi0Args &a, int npts, bool cplx, const 
   // the real launch); long enough that each workgroup reaches its steady state (short
   // runs favour the 64-wide tile); compare time per row
   const int cands[3] = {kF32T64, kF32T128, kF32T64W2};
-  float best_ms = 1e30f;
-  int best = kF32T64;
+  float tmin[3] = {1e30f, 1e30f, 1e30f};
   hipEvent_t e0, e1;
   RPA_HIP(hipEventCreate(&e0));
   RPA_HIP(hipEventCreate(&e1));
-  for (int rep = 0; rep < 2; ++rep) {
-    for (int ci = 0; ci < 3; ++ci) {
+  for (int rep = 0; rep < kTuneReps; ++rep) {
+    for (int cj = 0; cj < 3; ++cj) {
+      const int ci = rep % 2 ? 2 - cj : cj;
       const int tile = cands[ci];
       if (f32_cfg_points_per_wg(tile) == 2 && (a.pairs == nullptr || a.npairs == npts)) continue;
       Chi0Args t = a;
@@ -278,17 +289,18 @@ int tune_f32_tile(hipStream_t st, const Chi0Args &a, int npts, bool cplx, const 
       float ms = 0.f;
       RPA_HIP(hipEventElapsedTime(&ms, e0, e1));
       ms /= (float)t.M;
-      if (rep == 1 && getenv("RPA_TUNE_VERBOSE"))
+      if (rep > 0 && ms < tmin[ci]) tmin[ci] = ms;
+      if (rep == kTuneReps - 1 && getenv("RPA_TUNE_VERBOSE"))
         fprintf(stderr, "[tune] %s %s: %.3e ms per row (%d splits, %lld rows, %d points)\n", key.c_str(),
-                f32_cfg_name(tile), ms, t.ksplit, (long long)t.M, npts);
-      if (rep == 1 && ms < best_ms) {
-        best_ms = ms;
-        best = tile;
-      }
+                f32_cfg_name(tile), tmin[ci], t.ksplit, (long long)t.M, npts);
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  int bi = 0;
+  for (int ci = 1; ci < 3; ++ci)
+    if (tmin[ci] < tmin[bi]) bi = ci;
+  const int best = cands[bi];
   g_tuned[key] = best;
   store_cache_locked();
   *tile_out = best;
