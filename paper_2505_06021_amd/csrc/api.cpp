@@ -208,9 +208,24 @@ int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega, rpa_
   a.wtab = wt;
   a.ksplit = 1;
   a.out = out;
-  a.out_stride = 0;
+  a.out_stride = (int64_t)N * N;   // one point; also the stride of the partial planes
   a.nk = hs.nk; a.nocc = hs.nocc; a.nvirt = hs.nvirt; a.N = N; a.M = M;
   RPA_HIP(launch_chi0_weights(c.stream, a, 1));
+  // one point fills few workgroups: the FP64 and FP32 contractions split their rows (up
+  // to kMaxSplit ways, each split at least 512 rows) so that the launch fills the GPU;
+  // the later splits go to partial planes summed in split order.  RPA_CHI0_KSPLIT fixes
+  // the count.
+  int ncu_all = 0;
+  if (hipDeviceGetAttribute(&ncu_all, hipDeviceAttributeMultiprocessorCount, c.device) != hipSuccess) ncu_all = 256;
+  auto split_for = [&](int64_t tn, int64_t slots_per_cu) {
+    const int64_t T = (N + tn - 1) / tn;
+    int ks = chi0_pick_ksplit(T * (T + 1) / 2, slots_per_cu * ncu_all, M, kMaxSplit);
+    if (const char *e = getenv("RPA_CHI0_KSPLIT")) {
+      const int v = atoi(e);
+      if (v >= 1) ks = std::min(v, kMaxSplit);
+    }
+    return ks;
+  };
   if (prec == RPA_BF16X3) {
     // prepared left (unscaled) and right (scaled) operands, then the split contraction
     double *dg, *scr;
@@ -249,12 +264,28 @@ int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega, rpa_
     RPA_TRY(c.workspace("chi0_diag_scratch", diag_exact_scratch_doubles(M, N, 1) * 8, (void **)&scr));
     RPA_HIP(launch_to_f32(c.stream, B, b32, M * N, cplx));
     RPA_HIP(launch_diag_exact(c.stream, B, cplx, M, N, wt, 1, scr, dg));
+    const int f32_cfgs[3] = {kF32T64, kF32T128, kF32T64W2};
+    int ks_of[3], ks_max = 1;
+    for (int ci = 0; ci < 3; ++ci) {
+      const int e = f32_cfg_edge(f32_cfgs[ci]);
+      ks_of[ci] = split_for(e, e == 128 ? 1 : 2);
+      ks_max = std::max(ks_max, ks_of[ci]);
+    }
+    if (ks_max > 1) RPA_TRY(c.workspace("chi0_partial", (int64_t)(ks_max - 1) * N * N * 16, (void **)&a.partial));
     int tile = kF32T64;
-    RPA_TRY(tune_f32_tile(c.stream, a, 1, cplx, b32, dg, &tile));
+    RPA_TRY(tune_f32_tile(c.stream, a, 1, cplx, b32, dg, &tile, ks_of));
+    a.ksplit = ks_of[tile == kF32T128 ? 1 : tile == kF32T64W2 ? 2 : 0];
     RPA_HIP(launch_chi0_mixed(c.stream, a, 1, b32, dg, (int)prec, tile));
   } else {
+    int ks_of[8] = {1, 1, 1, 1, 1, 1, 1, 1}, ks_max = 1;
+    for (int cf = 0; cf < chi0_cfg_count() && cf < 8; ++cf) {
+      ks_of[cf] = split_for(chi0_cfg_tile(cf), chi0_cfg_slots_per_cu(cf));
+      ks_max = std::max(ks_max, ks_of[cf]);
+    }
+    if (ks_max > 1) RPA_TRY(c.workspace("chi0_partial", (int64_t)(ks_max - 1) * N * N * 16, (void **)&a.partial));
     int cfg = 1;
-    RPA_TRY(tune_chi0_cfg(c.stream, a, 1, cplx, &cfg));
+    RPA_TRY(tune_chi0_cfg(c.stream, a, 1, cplx, &cfg, ks_of));
+    a.ksplit = ks_of[cfg];
     RPA_HIP(launch_chi0_f64(c.stream, a, 1, cplx, cfg));
   }
   if (!direct) RPA_TRY(deliver_complex(c, chi0, out, (int64_t)N * N, hs.is_complex, sys->memspace));

@@ -17,7 +17,9 @@ struct PointDesc {
 };
 
 // Arguments of the chi0 contraction kernels.
-constexpr int kMaxSplit = 4;   // row splits of one FP64 contraction launch
+constexpr int kMaxSplit = 16;    // row splits of one FP64/FP32 contraction launch
+constexpr int kBatchSplits = 4;  // at most this many in the batched point pipeline (its
+                                 // partial planes hold a whole batch of points each)
 
 struct Chi0Args {
   const void *B;            // bslot-major slabs of [M][N] coefficients (complex or real)

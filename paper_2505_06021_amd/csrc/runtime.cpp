@@ -385,7 +385,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   }
   // FP64 and FP32: two more partial planes per lane (up to four row splits per launch)
   // where the budget holds them; one plane (two splits) otherwise
-  const int tplanes = (!bsplit && pbatch * per_pt + one_split + 2 * pbatch * nn * 16 <= rest / nlanes) ? kMaxSplit - 1 : 1;
+  const int tplanes = (!bsplit && pbatch * per_pt + one_split + 2 * pbatch * nn * 16 <= rest / nlanes) ? kBatchSplits - 1 : 1;
 
   Arena ar(ctx, use_cache);
   const bool prof = use_cache && ctx.profile;   // timing only on the synchronous path

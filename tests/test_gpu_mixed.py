@@ -174,6 +174,7 @@ def test_chi0_fp32_tile_edges(ctx, monkeypatch, naux, nocc, nvirt, tile):
 def test_fp32_tile_edges_agree_bitwise(ctx, monkeypatch):
     # one row split: both tile edges issue the same MFMA and flush sequence per element
     s = inputs.make_system("f32tiles", (2, 2, 1), 8, 150, 300, 3, 6, is_complex=True)   # M = 4800
+    monkeypatch.setenv("RPA_CHI0_KSPLIT", "1")
     got = {}
     for tile in ("64", "128"):
         monkeypatch.setenv("RPA_F32_TILE", tile)

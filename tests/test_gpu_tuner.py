@@ -47,6 +47,7 @@ def test_chi0_every_configuration_identical_and_exact(ctx, monkeypatch, naux):
     # N = 150 and 257: ragged 64- and 128-wide tiles (257 leaves a one-column tile)
     s = inputs.make_system("tall", (2, 2, 1), 8, 150, naux, 3, 41, is_complex=True)
     ref = orc.chi0(s, 1, s.omega[1])
+    monkeypatch.setenv("RPA_CHI0_KSPLIT", "1")   # the configurations' own split counts differ
     got = {}
     for cfg in CFGS:
         say(f"chi0 configuration {cfg} N={naux}")
@@ -190,3 +191,26 @@ def test_paired_kernels_small_and_ragged_tile_grids(ctx, monkeypatch, naux, prec
     assert np.array_equal(g1, g2)
     e_ref = orc.energy(s)[0]
     assert abs(e2 - e_ref) <= (1e-10 * abs(e_ref) if prec == 0 else 1e-6)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_single_point_chi0_row_splits(ctx, monkeypatch, prec):
+    # rpa_chi0 splits the rows of its one point so that the launch fills the GPU (up to
+    # 16 splits of at least 512 rows; the later splits' sums go to partial planes added
+    # in split order): every split count agrees with the oracle and with one split
+    s = inputs.make_system("chi0split", (2, 2, 1), 8, 150, 200, 3, 61, is_complex=True)   # M = 4800
+    ref = orc.chi0(s, 1, s.omega[1])
+    tol = 1e-12 if prec == 0 else 1e-6
+    monkeypatch.setenv("RPA_CHI0_KSPLIT", "1")
+    one = ctx.chi0(s, 1, s.omega[1], prec=prec)
+    for ks in ("2", "5", "9", "16"):
+        monkeypatch.setenv("RPA_CHI0_KSPLIT", ks)
+        say(f"chi0 prec={prec} with {ks} row splits")
+        got = ctx.chi0(s, 1, s.omega[1], prec=prec)
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= tol, ks
+        assert np.linalg.norm(got - one) / np.linalg.norm(one) <= (1e-14 if prec == 0 else 1e-6), ks
+        assert np.abs(got - got.conj().T).max() == 0.0
+    monkeypatch.delenv("RPA_CHI0_KSPLIT")
+    say("  the launch's own split count")
+    got = ctx.chi0(s, 1, s.omega[1], prec=prec)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= tol
