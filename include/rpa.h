@@ -250,8 +250,9 @@ int rpa_profile_read(rpa_ctx *ctx, rpa_kernel_times *out);
  * (caller-owned; may be NULL when len is 0) and the untruncated length into *needed (may
  * be NULL).  Environment: RPA_CHI0_CFG=<name> (or RPA_CHI0_KT=8|16|32) fixes the FP64
  * configuration, RPA_F32_TILE=64|128|64w2 the FP32 one, RPA_BF16_TILE=64|128 the
- * split-BF16 tile edge, RPA_CHI0_KSPLIT=1..4 the row split count of the FP64 and FP32
- * contractions (capped by the partial planes the budget holds), RPA_TUNE=0 keeps the
+ * split-BF16 tile edge, RPA_CHI0_KSPLIT=n the row split count of the FP64 and FP32
+ * contractions (at most 16 in rpa_chi0, 4 in the batched calls, and 2 where the budget
+ * holds no more partial planes), RPA_TUNE=0 keeps the
  * defaults (t64k16, t64, t128), RPA_TUNE_CACHE=<file> keeps the choices across
  * processes.  Never fails. */
 int rpa_tuned(char *buf, int32_t len, int32_t *needed);
