@@ -146,7 +146,10 @@ const char *rpa_last_error(const rpa_ctx *ctx);
 int rpa_set_stream(rpa_ctx *ctx, void *hip_stream);
 
 /* chi0(q = iq, i omega) of Sec. 2.2 into chi0 [naux][naux] (complex, or real if
- * is_complex = 0), in sys->memspace.  The full Hermitian matrix is written.
+ * is_complex = 0), in sys->memspace.  The full Hermitian matrix is written.  The FP64
+ * and FP32 contractions split the rows of this one point up to 16 ways so that the
+ * launch fills the GPU; the context's workspace then holds up to 15 partial planes of
+ * naux x naux complex doubles (summed in split order, so a call is repeatable).
  * Errors: RPA_E_ARG, RPA_E_NOMEM, RPA_E_DEVICE. */
 int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega,
              rpa_precision prec, void *chi0);
