@@ -226,6 +226,17 @@ int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega, rpa_
     }
     return ks;
   };
+  // the partial planes of the largest split count that the HBM limit still holds (an
+  // existing buffer of the same name is reused); every count is capped to it
+  auto plan_planes = [&](int *ks_of, int n) -> int {
+    int ks_max = 1;
+    for (int i = 0; i < n; ++i) ks_max = std::max(ks_max, ks_of[i]);
+    const int64_t plane = (int64_t)N * N * 16;
+    while (ks_max > 1 && !c.would_fit((int64_t)(ks_max - 1) * plane)) --ks_max;
+    for (int i = 0; i < n; ++i) ks_of[i] = std::min(ks_of[i], ks_max);
+    if (ks_max > 1) return c.workspace("chi0_partial", (int64_t)(ks_max - 1) * plane, (void **)&a.partial);
+    return RPA_OK;
+  };
   if (prec == RPA_BF16X3) {
     // prepared left (unscaled) and right (scaled) operands, then the split contraction
     double *dg, *scr;
@@ -265,24 +276,21 @@ int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega, rpa_
     RPA_HIP(launch_to_f32(c.stream, B, b32, M * N, cplx));
     RPA_HIP(launch_diag_exact(c.stream, B, cplx, M, N, wt, 1, scr, dg));
     const int f32_cfgs[3] = {kF32T64, kF32T128, kF32T64W2};
-    int ks_of[3], ks_max = 1;
+    int ks_of[3];
     for (int ci = 0; ci < 3; ++ci) {
       const int e = f32_cfg_edge(f32_cfgs[ci]);
       ks_of[ci] = split_for(e, e == 128 ? 1 : 2);
-      ks_max = std::max(ks_max, ks_of[ci]);
     }
-    if (ks_max > 1) RPA_TRY(c.workspace("chi0_partial", (int64_t)(ks_max - 1) * N * N * 16, (void **)&a.partial));
+    RPA_TRY(plan_planes(ks_of, 3));
     int tile = kF32T64;
     RPA_TRY(tune_f32_tile(c.stream, a, 1, cplx, b32, dg, &tile, ks_of));
     a.ksplit = ks_of[tile == kF32T128 ? 1 : tile == kF32T64W2 ? 2 : 0];
     RPA_HIP(launch_chi0_mixed(c.stream, a, 1, b32, dg, (int)prec, tile));
   } else {
-    int ks_of[8] = {1, 1, 1, 1, 1, 1, 1, 1}, ks_max = 1;
-    for (int cf = 0; cf < chi0_cfg_count() && cf < 8; ++cf) {
-      ks_of[cf] = split_for(chi0_cfg_tile(cf), chi0_cfg_slots_per_cu(cf));
-      ks_max = std::max(ks_max, ks_of[cf]);
-    }
-    if (ks_max > 1) RPA_TRY(c.workspace("chi0_partial", (int64_t)(ks_max - 1) * N * N * 16, (void **)&a.partial));
+    int ks_of[8] = {1, 1, 1, 1, 1, 1, 1, 1};
+    const int ncfg = std::min(chi0_cfg_count(), 8);
+    for (int cf = 0; cf < ncfg; ++cf) ks_of[cf] = split_for(chi0_cfg_tile(cf), chi0_cfg_slots_per_cu(cf));
+    RPA_TRY(plan_planes(ks_of, ncfg));
     int cfg = 1;
     RPA_TRY(tune_chi0_cfg(c.stream, a, 1, cplx, &cfg, ks_of));
     a.ksplit = ks_of[cfg];
