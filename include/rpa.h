@@ -8,7 +8,11 @@
  *   chi0_PQ(q, i w) = sum_k zeta_k sum_ia conj(B^P_ia(k,q)) w_ia(w) B^Q_ia(k,q)
  *       with w_ia(w) = -4 Delta / (Delta^2 + w^2), Delta = eps_a(k) - eps_i(k (+) q)
  *       (Sec. 2.2, the fit-basis polarizability equation; the -2 is the closed-shell
- *        occupation factor and the complex-conjugate term doubles the real part)
+ *        occupation factor and the complex-conjugate term doubles the real part).
+ *       B is the complex conjugate of the paper's pair coefficient: B^P_ia(k,q) =
+ *       conj(C^{ai}_P(k+q,k)), C^{ai}_P being the coefficient of f_P in the expansion of
+ *       psi*_a(k) psi_i(k+q), so that conj(B^P) B^Q = C^{ai}_P conj(C^{ai}_Q) keeps the
+ *       index order of that equation.
  *   Pi  = V^(1/2) chi0 V^(1/2)                 (working equation; Algorithm 1)
  *   eps(q, w) = ln det(1 - Pi) + Re Tr Pi      (Eq. 1 summed as -ln(1 - Z) - Z)
  *   E   = sum_q zeta_q sum_j W_j eps(q, w_j) / (2 pi)
@@ -72,17 +76,19 @@ typedef struct rpa_ctx rpa_ctx;
  *            Sec. 3.2 (Gamma removed from the q-grid, 2/4/8 displaced q-points added around
  *            it) reach (N_add + 1) * nk points, so nk_occ = (N_add + 1) * nk there.
  *  nbas      0, or the size of an atomic-orbital basis: B is then built on the device by
- *            the MO transform of Sec. 2.2, B^P_ia(k,q) = sum_{mu nu} conj(c_virt[k][mu][a])
- *            C^{mu nu}_P(k,q) c_occ[k (+) q][nu][i], with the pair-fit coefficients C drawn
- *            from Philox stream 1 of B's key (philox_seed, sigma; element
- *            e = (mu * nbas + nu) * naux + P).  Requires is_complex = 1 and B = NULL.
+ *            the MO transform of Sec. 2.2, C^{ai}_P(k+q,k) = sum_{mu nu} conj(c_virt[k][mu][a])
+ *            C^{mu nu}_P(k,q) c_occ[k (+) q][nu][i] and B^P_ia(k,q) = conj(C^{ai}_P), with
+ *            the pair-fit coefficients C^{mu nu}_P drawn from Philox stream 1 of B's key
+ *            (philox_seed, sigma; element e = (mu * nbas + nu) * naux + P).  Requires
+ *            is_complex = 1 and B = NULL.
  *  c_occ     [nk_occ][nbas][nocc], c_virt [nk][nbas][nvirt]: KS coefficients (complex)
  *            after the periodic projector of Sec. 2.3 (T(k) c, applied by the caller).
  *  zeta_k    [nk], zeta_q [nq]: integration weights; NULL means 1/nk and 1/nq.
- *  B         [nq][nk][nocc][nvirt][naux]: fit coefficients B^P_ia(k,q), P fastest
- *            (the MO-basis PADF coefficients of Sec. 2.2).  NULL means: generate them
- *            on the device from Philox4x32-10 with philox_seed and sigma (the stream
- *            definition is that of rpa_philox_B).
+ *  B         [nq][nk][nocc][nvirt][naux]: fit coefficients B^P_ia(k,q), P fastest: the
+ *            complex conjugates of the MO-basis PADF coefficients C^{ai}_P(k+q,k) of
+ *            Sec. 2.2 (a caller holding C passes conj(C); for real systems B = C).  NULL
+ *            means: generate them on the device from Philox4x32-10 with philox_seed and
+ *            sigma (the stream definition is that of rpa_philox_B).
  *  vhalf     [nq][naux][naux]: V^(1/2)(q), Hermitian (symmetric if real).
  * All arrays live in `memspace`.
  */

@@ -14,7 +14,11 @@ Steps (the paper's notation; "the paper" is arXiv:2505.06021):
    the closed-shell occupations times the resonant term 1/(Delta - i omega) plus its
    complex conjugate (same equation).
 3. polarizability       chi0_PQ(q, i omega) = sum_k zeta_k sum_ia conj(B^P_ia) w_ia B^Q_ia
-   (same equation, with B^P_ia(k,q) the fit coefficients in the KS basis).
+   (same equation).  The paper writes P_{gamma gamma'} with C^{ai}_gamma C^{*ai}_{gamma'},
+   C^{ai}_gamma(k+q,k) being the coefficient of f_gamma in the pair expansion of
+   psi*_a(k) psi_i(k+q) (Sec. 2.2); B is the complex conjugate of that coefficient,
+   B^P_ia = conj(C^{ai}_P), so that conj(B^P) B^Q = C^{ai}_P conj(C^{ai}_Q) keeps the
+   paper's index order.  For synthetic coefficients B is the input itself.
 4. Pi = V^(1/2) chi0 V^(1/2)   (working equation, Z = v^(1/2) P^(0) v^(1/2); Algorithm 1).
 5. eps(q, omega) = ln det(1 - Pi) + Re Tr Pi, with ln det from the Cholesky factor of the
    Hermitian positive definite 1 - Pi: ln det = 2 sum ln L_ii.  The sign follows Eq. 1
@@ -29,9 +33,9 @@ first (Sec. 2.2 and the periodic projector method of Sec. 2.3):
 0a. projector  S(k) = U D U^H; R(k) keeps the eigen-directions with D_ii >= eps_d; the
     cumulative mask is the product of the R(k) over all k (eigenvalues in ascending
     order); T(k) = U R U^H and the KS coefficients become c~ = T c.
-0b. MO transform  B^gamma_ia(k,q) = sum_{mu nu} conj(c~_{mu a}(k)) C^{mu nu}_gamma(k,q)
+0b. MO transform  C^{ai}_gamma(k+q,k) = sum_{mu nu} conj(c~_{mu a}(k)) C^{mu nu}_gamma(k,q)
     c~_{nu i}(k (+) q): the pair-fit expansion of psi*_a(k) psi_i(k+q) from that of the
-    basis-function products.
+    basis-function products; B^gamma_ia(k,q) = conj(C^{ai}_gamma) (step 3).
 
 Every function here is pinned by tests against closed forms and library routines
 (plasmon formula, second-order ring limit, eigenvalue route of Tr ln, invariants).
@@ -62,12 +66,18 @@ def projected_coefficients(system):
     return np.array([T[k] @ system.c_raw[k] for k in range(len(T))])
 
 
-def ao_B_block(system, ct, iq, ik):
-    """B[i][a][gamma] of block (q, k) by the MO transform  (step 0b)."""
+def ao_pair_coefficients(system, ct, iq, ik):
+    """C^{ai}_gamma(k+q, k) of block (q, k), as [i][a][gamma]: the MO transform of the
+    pair-fit coefficients  (step 0b)."""
     C = system.C_block(iq, ik)
     cv = ct[ik][:, system.nocc:]
     co = ct[system.kq[iq, ik]][:, :system.nocc]
     return np.einsum("ma,mng,ni->iag", cv.conj(), C, co, optimize=True)
+
+
+def ao_B_block(system, ct, iq, ik):
+    """B[i][a][gamma] of block (q, k) = conj(C^{ai}_gamma)  (steps 0b and 3)."""
+    return ao_pair_coefficients(system, ct, iq, ik).conj()
 
 
 def transition_energies(eps_occ, eps_virt, kq, iq):

@@ -2,13 +2,16 @@
 // the pair-fit coefficients (Sec. 2.2, the expansion of psi*_a(k) psi_i(k+q) from that of
 // the basis-function products),
 //
-//   B^gamma_ia(k,q) = sum_{mu nu} conj(c~_{mu a}(k)) C^{mu nu}_gamma(k,q) c~_{nu i}(k (+) q),
+//   C^{ai}_gamma(k+q,k) = sum_{mu nu} conj(c~_{mu a}(k)) C^{mu nu}_gamma(k,q) c~_{nu i}(k (+) q),
 //
 // with c~ the KS coefficients after the periodic projector (Sec. 2.3; applied by the
-// caller).  Per (q, k) block: C from the Philox generator (stream 1), then two batched
-// complex FP64 MFMA products, the occupied index first (the cheaper order):
-//   T1[mu][i][gamma] = sum_nu c~_{nu i} C[mu][nu][gamma]           (batch over mu)
-//   B[i][a][gamma]   = sum_mu conj(c~_{mu a}) T1[mu][i][gamma]     (batch over i)
+// caller).  The library's B is the complex conjugate, B^gamma_ia = conj(C^{ai}_gamma), so
+// that chi0_PQ = sum conj(B^P) w B^Q is the fit-basis polarizability of Sec. 2.2 with its
+// C_gamma C*_gamma' index order.  Per (q, k) block: C from the Philox generator (stream 1),
+// then two batched complex FP64 MFMA products, the occupied index first (the cheaper order):
+//   T1[mu][i][gamma] = sum_nu c~_{nu i} C[mu][nu][gamma]                 (batch over mu)
+//   B[i][a][gamma]   = conj(sum_mu conj(c~_{mu a}) T1[mu][i][gamma])     (batch over i;
+//                      the conjugate taken at the store)
 // Both are O[b][m][n] = sum_k op(X[b][k][m]) Y[b][k][n] with the contraction index k
 // slowest in both operands, so an output tile streams 16-row panels of X and Y through
 // LDS exactly as the chi0 contraction does (64 x 64 tiles; 16 x 128 for the thin
@@ -34,6 +37,7 @@ struct TnArgs {
   double2 *O;         // O[b][m][n] at O + b * sob + m * ldo + n
   int64_t ldo, sob;
   int32_t M, N, K;
+  int32_t conj_out;   // store conj(O) instead of O
 };
 
 // O[b][m][n] = sum_k op(X[b][k][m]) Y[b][k][n], op = complex conjugation when CONJ.
@@ -143,7 +147,8 @@ __global__ __launch_bounds__(256) void zgemm_tn_kernel(TnArgs g) {
         // f64 16x16x4 accumulator layout: register r of lane l holds row l/16 + 4 r, column l%16
         const int m = m0 + wr * 32 + x * 16 + lk + 4 * r;
         const int n = n0 + wc * 32 + y * 16 + li;
-        if (m < g.M && n < g.N) O[(int64_t)m * g.ldo + n] = make_double2(accR[x][y][r], accI[x][y][r]);
+        if (m < g.M && n < g.N)
+          O[(int64_t)m * g.ldo + n] = make_double2(accR[x][y][r], g.conj_out ? -accI[x][y][r] : accI[x][y][r]);
       }
 }
 
@@ -230,7 +235,8 @@ __global__ __launch_bounds__(256) void zgemm_tn16_kernel(TnArgs g) {
     for (int r = 0; r < 4; ++r) {
       const int m = m0 + lk + 4 * r;
       const int n = n0 + wave * 32 + y * 16 + li;
-      if (m < g.M && n < g.N) O[(int64_t)m * g.ldo + n] = make_double2(accR[y][r], accI[y][r]);
+      if (m < g.M && n < g.N)
+        O[(int64_t)m * g.ldo + n] = make_double2(accR[y][r], g.conj_out ? -accI[y][r] : accI[y][r]);
     }
 }
 
@@ -269,11 +275,12 @@ hipError_t launch_ao_B(hipStream_t s, uint64_t seed, double sigma, int32_t nk, i
   g1.M = nocc; g1.N = naux; g1.K = nbas;
   e = launch_tn(s, false, g1, nbas);
   if (e != hipSuccess) return e;
-  TnArgs g2{};   // B[i][a][gamma] = sum_mu conj(c_virt[mu][a]) T1[mu][i][gamma]
+  TnArgs g2{};   // B[i][a][gamma] = conj(sum_mu conj(c_virt[mu][a]) T1[mu][i][gamma])
   g2.X = c_virt; g2.ldx = nvirt; g2.sxb = 0;
   g2.Y = T1; g2.ldy = (int64_t)nocc * naux; g2.syb = naux;
   g2.O = out; g2.ldo = naux; g2.sob = (int64_t)nvirt * naux;
   g2.M = nvirt; g2.N = naux; g2.K = nbas;
+  g2.conj_out = 1;
   return launch_tn(s, true, g2, nocc);
 }
 

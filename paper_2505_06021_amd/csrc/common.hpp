@@ -66,8 +66,8 @@ hipError_t launch_philox_B(hipStream_t s, uint64_t seed, double sigma, int32_t n
 // e = (mu * nbas + nu) * naux + gamma.
 hipError_t launch_philox_C(hipStream_t s, uint64_t seed, double sigma, int32_t nk, int32_t iq, int32_t ik,
                            int32_t nbas, int32_t naux, void *out);
-// B^gamma_ia(k,q) = sum_{mu nu} conj(cv_{mu a}) C^{mu nu}_gamma cv_{nu i} of one (q, k) block
-// into out ([nocc][nvirt][naux]): C from launch_philox_C into `scratch`
+// B^gamma_ia(k,q) = conj(sum_{mu nu} conj(cv_{mu a}) C^{mu nu}_gamma co_{nu i}) of one (q, k)
+// block into out ([nocc][nvirt][naux]): the conjugate of the pair coefficient C^{ai}_gamma: C from launch_philox_C into `scratch`
 // (ao_scratch_bytes), then two batched complex FP64 MFMA products.  c_occ points at the
 // projected occupied coefficients of k (+) q ([nbas][nocc]), c_virt at the virtual ones of
 // k ([nbas][nvirt]).

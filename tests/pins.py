@@ -19,8 +19,10 @@ import numpy as np
 
 
 def ao_block(system, iq, ik):
-    """B[i][a][gamma] of an atomic-orbital system, one gamma at a time as the matrix product
-    (c_virt(k)^H C_gamma c_occ(k (+) q))^T, from the generator's projected coefficients."""
+    """B[i][a][gamma] of an atomic-orbital system, one gamma at a time as the conjugate of
+    the matrix product (c_virt(k)^H C_gamma c_occ(k (+) q))^T (the pair coefficient
+    C^{ai}_gamma of Sec. 2.2; B is its conjugate), from the generator's projected
+    coefficients."""
     from paper_2505_06021_amd import inputs
     C = inputs.philox_C_block(system.seed, system.sigma, system.nk, iq, ik, system.nbas, system.naux)
     cv = system.c_virt[ik]
@@ -28,7 +30,7 @@ def ao_block(system, iq, ik):
     out = np.empty((system.nocc, system.nvirt, system.naux), dtype=np.complex128)
     for g in range(system.naux):
         out[:, :, g] = (cv.conj().T @ C[:, :, g] @ co).T
-    return out
+    return out.conj()
 
 
 def transitions(system, iq):
