@@ -1,10 +1,17 @@
 #!/usr/bin/env python3
 """Throughput of the periodic RPA hot path on one MI355X.
 
-One step = one full RPA correlation energy of the workload: device Philox generation
-of B for every q, chi0 for every (q, w) point, Pi = V^(1/2) chi0 V^(1/2), the Cholesky
-log-det and the q/w quadrature, all in librpa's kernels, with the inputs (band
-energies, V^(1/2), weights, the Philox seed) resident in HBM before timing starts.
+One step = the whole hot path for one q-point of the workload and all of its imaginary
+frequencies: device Philox generation of B(q), chi0 for every (q, w) point of that q,
+Pi = V^(1/2) chi0 V^(1/2) and the Cholesky log-det, all in librpa's kernels, with the
+inputs (band energies, V^(1/2), frequency nodes, the Philox seed) resident in HBM before
+timing starts.  Steps visit the q-points in turn; once every q has been visited, the
+energy E = sum_q zeta_q sum_j W_j eps(q, w_j) / (2 pi) is assembled from the timed steps.
+
+The default workload is the largest single-GPU configuration (3x3x1 k-grid, N_occ 96,
+N_virt 900, N_aux 2400, 16 frequencies) in FP64; the FP32 and split-BF16 contractions of
+the same workload are timed over one sweep of the q-points next to it and their energies
+compared with the FP64 one.
 
 Prints one JSON line: (q, w) points per second, the roofline position of the dominant
 kernel (chi0) from HIP events recorded on its stream, and the CPU oracle timed on a
@@ -70,14 +77,31 @@ def traffic_from_profiles(workload, prec):
     return d.get("bytes_per_launch")
 
 
+def host_info():
+    """BLAS library, its threads, and the host's physical and logical cores."""
+    import numpy as np   # noqa: F401  (loads the BLAS whose thread pool is reported)
+    info = {"blas": None, "threads": os.cpu_count() or 1,
+            "logical_cores": os.cpu_count(), "physical_cores": None}
+    try:
+        import psutil
+        info["physical_cores"] = psutil.cpu_count(logical=False)
+    except Exception:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        pools = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        if pools:
+            info["blas"] = f"{pools[0].get('internal_api')} {pools[0].get('version')}"
+            info["threads"] = max(int(i.get("num_threads", 1)) for i in pools)
+    except Exception:
+        pass
+    return info
+
+
 def cpu_baseline(make, budget_s=12.0, max_points=24):
     """The oracle as it stands, on the first points of the workload, on the host cores."""
     from oracle import rpa_oracle as orc
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        threads = os.cpu_count() or 1
+    hi = host_info()
     s = make()
     pts = [(q, j) for q in range(s.nq) for j in range(s.nw)]
     t0 = time.perf_counter()
@@ -88,9 +112,45 @@ def cpu_baseline(make, budget_s=12.0, max_points=24):
         if time.perf_counter() - t0 > budget_s and n >= 2:
             break
     dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "points/s", "cores": int(threads), "kind": "oracle",
+    return {"value": n / dt, "unit": "points/s", "cores": int(hi["threads"]), "kind": "oracle",
+            "blas": hi["blas"], "physical_cores": hi["physical_cores"],
+            "logical_cores": hi["logical_cores"],
             "sample": f"first {n} (q, w) points of the workload in q-major order, "
                       f"{dt:.1f} s, NumPy FP64 with host Philox B"}
+
+
+def cpu_baseline_slice(s, nocc_sample=8):
+    """The oracle on one (q, w) point of a workload too large to time whole on the host:
+    chi0 over a slice of the point's contraction rows (the first k-point and its first
+    nocc_sample occupied bands), then Pi and the Cholesky log-det at the full N_aux.  The
+    oracle's chi0 costs the same per contraction row everywhere (B rows from the host
+    Philox stream, then the weighted rank update), so the point's time is the slice's
+    chi0 time scaled by the ratio of rows plus the full-size Pi and log-det time."""
+    import dataclasses
+
+    import numpy as np
+    from oracle import rpa_oracle as orc
+    hi = host_info()
+    nocc = min(nocc_sample, s.nocc)
+    part = dataclasses.replace(
+        s, nk=1, nocc=nocc, kq=np.zeros((s.nq, 1), dtype=np.int32),
+        eps_occ=np.ascontiguousarray(s.eps_occ[s.kq[0, :1], :nocc]),
+        eps_virt=np.ascontiguousarray(s.eps_virt[:1]), zeta_k=np.ones(1))
+    t0 = time.perf_counter()
+    c = orc.chi0(part, 0, s.omega[0])
+    t1 = time.perf_counter()
+    orc.trace_log(orc.pi_matrix(s.vhalf[0], c / s.nk))
+    t2 = time.perf_counter()
+    rows_full, rows_part = s.M, part.M
+    per_point = (t1 - t0) * rows_full / rows_part + (t2 - t1)
+    return {"value": 1.0 / per_point, "unit": "points/s", "cores": int(hi["threads"]), "kind": "oracle",
+            "blas": hi["blas"], "physical_cores": hi["physical_cores"],
+            "logical_cores": hi["logical_cores"],
+            "sample": f"one (q, w) point extrapolated from a slice: oracle chi0 over {rows_part} of the "
+                      f"point's {rows_full} contraction rows (first k-point, first {nocc} occupied bands) "
+                      f"in {t1 - t0:.1f} s, scaled by {rows_full / rows_part:.0f}, plus the full-size "
+                      f"Pi and Cholesky log-det ({t2 - t1:.1f} s): {per_point:.0f} s per point; "
+                      f"NumPy FP64 with host Philox B"}
 
 
 def serving(args):
@@ -182,12 +242,74 @@ def serving(args):
     print(json.dumps(line), flush=True)
 
 
+def run_steps(ctx, s, m, prec, steps, q0=0, label=""):
+    """`steps` steps of one q each (q = q0, q0 + 1, ... mod nq); returns {q: eps[nw]}."""
+    import numpy as np
+    out = {}
+    for i in range(steps):
+        q = (q0 + i) % s.nq
+        eps = ctx.points(s, [q] * s.nw, s.omega, prec=prec, marshal=m)
+        out[q] = np.asarray(eps)
+        if label:
+            print(f"[bench] {label} step {i} q={q} eps[0]={eps[0]:.10f}", file=sys.stderr, flush=True)
+    return out
+
+
+def energy_of(s, eps_by_q):
+    """E from a full set of per-q integrands (None unless every q is there)."""
+    if len(eps_by_q) < s.nq:
+        return None
+    return math.fsum(float(s.zeta_q[q]) * float(s.weight[j]) * float(eps_by_q[q][j]) / (2.0 * math.pi)
+                     for q in range(s.nq) for j in range(s.nw))
+
+
+def chi0_roofline(s, kt, steps, prec_name):
+    """Roofline of the chi0 contraction from the HIP-event kernel times of `steps` steps."""
+    launches, ms = kt["chi0"]
+    pts_per_launch = steps * s.nw / max(launches, 1)
+    flops_launch = chi0_flops_per_point(s) * pts_per_launch
+    # split-BF16 issues three MFMA products per real product; its peak is the BF16 one
+    issued_launch = flops_launch * (3.0 if prec_name == "bf16x3" else 1.0)
+    avg_s = ms * 1e-3 / max(launches, 1)
+    achieved = issued_launch / avg_s / 1e12 if avg_s > 0 else 0.0
+    algorithmic = flops_launch / avg_s / 1e12 if avg_s > 0 else 0.0
+    peak = PEAK_TFLOPS[prec_name]
+    return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "kernel": "chi0", "flops_per_launch": issued_launch,
+            "algorithmic_flops_per_launch": flops_launch, "algorithmic_TFLOPs": algorithmic,
+            "avg_launch_ms": avg_s * 1e3, "launches": launches}
+
+
+def golden_check(workload, s, eps_by_q, prec_name):
+    """Compare the steps' eps with the stored oracle values of the workload."""
+    tol = {"fp64": 1e-10, "fp32": 1e-8, "bf16x3": 2e-7}[prec_name]
+    out = []
+    for name in (f"{workload}.json", f"{workload}_sampled.json"):
+        path = os.path.join(ROOT, "tests", "golden", name)
+        if not os.path.exists(path):
+            continue
+        g = json.load(open(path))
+        if "points" in g:
+            pts = [(p["iq"], p["j"], p["eps"]) for p in g["points"]]
+        else:
+            pts = [(q, j, g["eps"][q][j]) for q in range(len(g["eps"])) for j in range(len(g["eps"][q]))]
+        for q, j, ref in pts:
+            if q in eps_by_q:
+                out.append((q, j, abs(float(eps_by_q[q][j]) - ref) / abs(ref)))
+    if not out:
+        return None
+    worst = max(r for _, _, r in out)
+    return {"points_checked": len(out), "max_rel_err_eps": worst, "tol": tol, "ok": worst <= tol}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="slab3x3_naux384", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=18)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="slab3x3_naux2400", choices=sorted(WORKLOADS))
+    ap.add_argument("--mixed", default="fp32,bf16x3",
+                    help="reduced-precision contractions timed beside an FP64 run ('none' to skip)")
     ap.add_argument("--prec", default="fp64", choices=sorted(PREC_CODE))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", action="store_true",
@@ -212,6 +334,7 @@ def main():
         serving(args)
         return
 
+    import numpy as np
     import torch
     from paper_2505_06021_amd import inputs, rpa
 
@@ -225,50 +348,79 @@ def main():
         del src, dst
 
     make = getattr(inputs, WORKLOADS[args.workload])
+    t_in = time.perf_counter()
     s = make()
-    npts = s.nq * s.nw
     ctx = rpa.Context(0)
     m = rpa._Marshal(s, device=not args.host_inputs)   # inputs resident in HBM before timing
     prec = PREC_CODE[args.prec]
-    print(f"[bench] {args.workload} prec={args.prec} points/step={npts} warmup={args.warmup} "
-          f"steps={args.steps}", file=sys.stderr, flush=True)
-    for i in range(args.warmup):
-        E, _ = ctx.energy(s, prec=prec, marshal=m)
-        print(f"[bench] warmup {i} E={E:.12f}", file=sys.stderr, flush=True)
+    npts = s.nw                                          # points per step: one q, every w
+    print(f"[bench] {args.workload} prec={args.prec} points/step={npts} (one q) nq={s.nq} "
+          f"warmup={args.warmup} steps={args.steps} (inputs {time.perf_counter() - t_in:.1f} s)",
+          file=sys.stderr, flush=True)
+    run_steps(ctx, s, m, prec, args.warmup, label="warmup")
     ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    eps_by_q = {}
     for i in range(args.steps):
-        E, eps = ctx.energy(s, prec=prec, marshal=m)
+        q = i % s.nq
+        eps_by_q[q] = np.asarray(ctx.points(s, [q] * s.nw, s.omega, prec=prec, marshal=m))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kt = ctx.profile_read()
     ctx.profile(False)
-    ctx.close()
     ms_step = (t1 - t0) * 1e3 / args.steps
     print(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
-
-    launches, ms = kt["chi0"]
-    pts_per_launch = args.steps * npts / max(launches, 1)
-    flops_launch = chi0_flops_per_point(s) * pts_per_launch
-    # split-BF16 issues three MFMA products per real product; its peak is the BF16 one
-    issued_launch = flops_launch * (3.0 if args.prec == "bf16x3" else 1.0)
-    avg_s = ms * 1e-3 / max(launches, 1)
-    achieved = issued_launch / avg_s / 1e12 if avg_s > 0 else 0.0
-    algorithmic = flops_launch / avg_s / 1e12 if avg_s > 0 else 0.0
-    peak = PEAK_TFLOPS[args.prec]
-    traffic = traffic_from_profiles(args.workload, args.prec)
-
-    check = None
+    roof = chi0_roofline(s, kt, args.steps, args.prec)
+    roof["traffic"] = traffic_from_profiles(args.workload, args.prec)
+    E = energy_of(s, eps_by_q)
+    check = {"E": E, "q_visited": sorted(eps_by_q)}
     gold = os.path.join(ROOT, "tests", "golden", f"{args.workload}.json")
-    check = {"E": E}   # the energy of the last timed step (Ha per cell)
-    if os.path.exists(gold):
+    if E is not None and os.path.exists(gold):
         g = json.load(open(gold))
-        check = {"E": E, "E_oracle": g["E"], "rel_err": abs(E - g["E"]) / abs(g["E"])}
+        if "E" in g:
+            check.update(E_oracle=g["E"], rel_err=abs(E - g["E"]) / abs(g["E"]))
+    check["sampled"] = golden_check(args.workload, s, eps_by_q, args.prec)
+    tiles = {p: sorted({v for k, v in rpa.tuned().items()
+                        if k.startswith({"fp64": "f64_", "fp32": "f32_", "bf16x3": "bf16_"}[p])})
+             for p in PREC_CODE}
+
+    # the reduced-precision contractions of the same workload: one sweep of the q-points
+    mixed = {}
+    wanted = [] if args.mixed == "none" or args.prec != "fp64" else args.mixed.split(",")
+    for pname in wanted:
+        pc = PREC_CODE[pname]
+        run_steps(ctx, s, m, pc, 1, label=f"{pname} warmup")
+        ctx.profile(True)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        eq = run_steps(ctx, s, m, pc, s.nq)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        kq = ctx.profile_read()
+        ctx.profile(False)
+        Em = energy_of(s, eq)
+        r = chi0_roofline(s, kq, s.nq, pname)
+        dmax = max(float(np.max(np.abs(eq[q] - eps_by_q[q]) / np.abs(eps_by_q[q])))
+                   for q in eq if q in eps_by_q) if eps_by_q else None
+        mixed[pname] = {"value": s.nq * s.nw / (tb - ta), "unit": "points/s",
+                        "ms_per_step": (tb - ta) * 1e3 / s.nq, "steps": s.nq,
+                        "chi0_frac_of_peak": r["frac"], "chi0_peak_TFLOPs": r["peak"],
+                        "chi0_avg_launch_ms": r["avg_launch_ms"],
+                        "chi0_algorithmic_TFLOPs": r["algorithmic_TFLOPs"],
+                        "E": Em, "abs_dE_vs_fp64_Ha_per_cell": abs(Em - E) if (Em is not None and E is not None) else None,
+                        "max_rel_deps_vs_fp64": dmax,
+                        "sampled": golden_check(args.workload, s, eq, pname),
+                        "chi0_tile_config": sorted({v for k, v in rpa.tuned().items()
+                                                    if k.startswith({"fp32": "f32_", "bf16x3": "bf16_"}[pname])})}
+        print(f"[bench] {pname}: {mixed[pname]['value']:.3f} points/s, dE {mixed[pname]['abs_dE_vs_fp64_Ha_per_cell']}",
+              file=sys.stderr, flush=True)
+    ctx.close()
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(make)
+        # the oracle of a large point takes many minutes on the host: time a slice of one
+        cpu = cpu_baseline_slice(s) if s.M * s.naux > 5e8 else cpu_baseline(make)
 
     line = {
         "metric": "(q,w) RPA points/s",
@@ -287,18 +439,13 @@ def main():
         "config": {"workload": args.workload, "grid": list(s.grid), "nk": s.nk, "nq": s.nq, "nk_occ": s.nk_occ, "nbas": s.nbas,
                    "nocc": s.nocc, "nvirt": s.nvirt, "naux": s.naux, "nw": s.nw,
                    "is_complex": s.is_complex, "chi0_precision": args.prec,
+                   "step": "one q-point: B(q) generation and all of its frequencies",
                    "B": "Philox4x32-10 on device", "parallelism": "single GPU",
-                   "chi0_tile_config": sorted({v for k, v in rpa.tuned().items()
-                                               if k.startswith({"fp64": "f64_", "fp32": "f32_",
-                                                                "bf16x3": "bf16_"}[args.prec])})},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": traffic,
-                     "kernel": "chi0", "flops_per_launch": issued_launch,
-                     "algorithmic_flops_per_launch": flops_launch,
-                     "algorithmic_TFLOPs": algorithmic,
-                     "avg_launch_ms": avg_s * 1e3, "launches": launches},
+                   "chi0_tile_config": tiles[args.prec]},
+        "roofline": roof,
         "kernels_ms_per_step": {k: v[1] / args.steps for k, v in kt.items()},
         "check": check,
+        "mixed_precision": mixed or None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

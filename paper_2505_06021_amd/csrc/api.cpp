@@ -22,13 +22,9 @@ int set_device(Ctx &c) {
   return RPA_OK;
 }
 
-int64_t budget_of(Ctx &c) {
-  std::lock_guard<std::mutex> g(c.mem_mu);
-  // the synchronous path may reuse its own cached workspaces, so count them as available
-  int64_t cached = 0;
-  for (auto &kv : c.cache) cached += kv.second.bytes;
-  return c.hbm_limit - c.in_use + cached;
-}
+// Device bytes a synchronous call may plan with (its own cached workspaces count as
+// available; what admitted serving jobs have reserved does not).
+int64_t budget_of(Ctx &c) { return c.sync_budget(); }
 
 // Copy `bytes` between a caller array in `memspace` and a device buffer.
 int to_device(void *dst, const void *src, size_t bytes, int memspace, hipStream_t s) {
@@ -232,7 +228,9 @@ int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega, rpa_
     int ks_max = 1;
     for (int i = 0; i < n; ++i) ks_max = std::max(ks_max, ks_of[i]);
     const int64_t plane = (int64_t)N * N * 16;
-    while (ks_max > 1 && !c.would_fit((int64_t)(ks_max - 1) * plane)) --ks_max;
+    auto it = c.cache.find("chi0_partial");
+    const int64_t have = it != c.cache.end() ? it->second.bytes : 0;   // reused if large enough
+    while (ks_max > 1 && !c.would_fit(std::max<int64_t>(0, (int64_t)(ks_max - 1) * plane - have))) --ks_max;
     for (int i = 0; i < n; ++i) ks_of[i] = std::min(ks_of[i], ks_max);
     if (ks_max > 1) return c.workspace("chi0_partial", (int64_t)(ks_max - 1) * plane, (void **)&a.partial);
     return RPA_OK;

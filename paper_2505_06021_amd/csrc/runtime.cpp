@@ -40,26 +40,38 @@ double now_seconds() {
 }
 
 // ---- device memory ----------------------------------------------------------------
-int Ctx::alloc(DevBuf &b, int64_t bytes, const char *what) {
+namespace {
+// What admitted serving jobs may still allocate (mem_mu held).
+int64_t outstanding_locked(const Ctx &c) {
+  return std::max<int64_t>(0, c.reserved - (c.in_use - c.cached_bytes));
+}
+}  // namespace
+
+int Ctx::alloc(DevBuf &b, int64_t bytes, const char *what, bool cached) {
   if (bytes <= 0) bytes = 256;
   {
     std::lock_guard<std::mutex> g(mem_mu);
-    if (in_use + bytes > hbm_limit)
-      return fail(RPA_E_NOMEM, "%s: %lld bytes requested, %lld of %lld in use", what,
-                  (long long)bytes, (long long)in_use, (long long)hbm_limit);
+    const int64_t held = in_use + (cached ? outstanding_locked(*this) : 0);
+    if (held + bytes > hbm_limit)
+      return fail(RPA_E_NOMEM, "%s: %lld bytes requested, %lld of %lld in use or reserved", what,
+                  (long long)bytes, (long long)held, (long long)hbm_limit);
     in_use += bytes;
+    if (cached) cached_bytes += bytes;
     high_water = std::max(high_water, in_use);
   }
   hipError_t e = hipMalloc(&b.p, (size_t)bytes);
   if (e != hipSuccess) {
     std::lock_guard<std::mutex> g(mem_mu);
     in_use -= bytes;
+    if (cached) cached_bytes -= bytes;
     b.p = nullptr;
     (void)hipGetLastError();
     return fail(e == hipErrorOutOfMemory ? RPA_E_NOMEM : RPA_E_DEVICE, "%s: hipMalloc(%lld) failed: %s",
                 what, (long long)bytes, hipGetErrorString(e));
   }
+  std::lock_guard<std::mutex> g(mem_mu);
   b.bytes = bytes;
+  b.cached = cached;
   return RPA_OK;
 }
 
@@ -68,8 +80,10 @@ void Ctx::release(DevBuf &b) {
   (void)hipFree(b.p);
   std::lock_guard<std::mutex> g(mem_mu);
   in_use -= b.bytes;
+  if (b.cached) cached_bytes -= b.bytes;
   b.p = nullptr;
   b.bytes = 0;
+  b.cached = false;
 }
 
 int Ctx::workspace(const char *name, int64_t bytes, void **out) {
@@ -82,7 +96,7 @@ int Ctx::workspace(const char *name, int64_t bytes, void **out) {
     RPA_HIP(hipStreamSynchronize(stream));
     release(b);
   }
-  RPA_TRY(alloc(b, bytes, name));
+  RPA_TRY(alloc(b, bytes, name, true));
   *out = b.p;
   return RPA_OK;
 }
@@ -130,7 +144,29 @@ int Ctx::prof_collect() {
 
 bool Ctx::would_fit(int64_t extra) {
   std::lock_guard<std::mutex> g(mem_mu);
-  return in_use + extra <= hbm_limit;
+  return in_use + outstanding_locked(*this) + extra <= hbm_limit;
+}
+
+int64_t Ctx::sync_budget() {
+  // Everything outside the cache belongs to admitted jobs and lies within their
+  // reservations, so what a synchronous call may hold, its cache included, is the limit
+  // minus the reservations.
+  std::lock_guard<std::mutex> g(mem_mu);
+  return hbm_limit - std::max<int64_t>(reserved, in_use - cached_bytes);
+}
+
+bool Ctx::try_reserve(int64_t need, int64_t *cached_out) {
+  std::lock_guard<std::mutex> g(mem_mu);
+  if (cached_out) *cached_out = cached_bytes;
+  // synchronous-call caches stay allocated; everything else in use is reserved by jobs
+  if (need > hbm_limit - cached_bytes - reserved) return false;
+  reserved += need;
+  return true;
+}
+
+void Ctx::unreserve(int64_t need) {
+  std::lock_guard<std::mutex> g(mem_mu);
+  reserved -= need;
 }
 
 // ---- validation -----------------------------------------------------------------
@@ -233,11 +269,9 @@ int lanes_wanted() {
 }
 
 bool trln_single() {
-  static bool v = [] {
-    const char *e = getenv("RPA_TRLN_SINGLE");
-    return e && atoi(e) != 0;
-  }();
-  return v;
+  // read at every call, so that a process can switch between the two factorisations
+  const char *e = getenv("RPA_TRLN_SINGLE");
+  return e && atoi(e) != 0;
 }
 
 namespace {
@@ -265,7 +299,7 @@ struct Arena {
       if (!b.p || b.bytes < total) {
         RPA_HIP(hipStreamSynchronize(st));
         ctx.free_cache();
-        RPA_TRY(ctx.alloc(ctx.cache["pipeline"], total, "pipeline workspace"));
+        RPA_TRY(ctx.alloc(ctx.cache["pipeline"], total, "pipeline workspace", true));
       }
       base = ctx.cache["pipeline"].p;
     } else {

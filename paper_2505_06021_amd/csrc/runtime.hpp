@@ -47,6 +47,7 @@ class Scheduler;
 struct DevBuf {
   void *p = nullptr;
   int64_t bytes = 0;
+  bool cached = false;   // a workspace of synchronous calls (counted in Ctx::cached_bytes)
 };
 
 struct Ctx {
@@ -54,11 +55,19 @@ struct Ctx {
   hipStream_t own_stream = nullptr;
   hipStream_t stream = nullptr;     // stream of synchronous calls
   std::mutex mu;                    // serialises synchronous calls on this context
+  // Device-memory accounting, guarded by mem_mu.  in_use counts every allocation;
+  // cached_bytes the part held by the workspace cache of synchronous calls; reserved the
+  // footprints of the serving jobs admitted so far (each job allocates at most its own,
+  // so reserved - (in_use - cached_bytes) is what admitted jobs may still allocate).
   std::mutex mem_mu;
   int64_t hbm_limit = 0;
   int64_t in_use = 0;
   int64_t high_water = 0;
-  std::map<std::string, DevBuf> cache;   // grow-only workspaces of synchronous calls
+  int64_t cached_bytes = 0;
+  int64_t reserved = 0;
+  // Grow-only workspaces of synchronous calls.  The map itself is only read or changed
+  // by a thread holding `mu`; other threads read cached_bytes instead.
+  std::map<std::string, DevBuf> cache;
   std::unique_ptr<Scheduler> sched;
   // kernel timing of synchronous calls (rpa_profile)
   bool profile = false;
@@ -75,12 +84,23 @@ struct Ctx {
   hipStream_t aux_stream();
   hipStream_t aux = nullptr;
 
-  int alloc(DevBuf &b, int64_t bytes, const char *what);
+  // Allocate `bytes` of device memory.  A cached (synchronous-call) allocation must also
+  // leave room for what admitted serving jobs may still allocate; a job's allocation is
+  // part of its own reservation.
+  int alloc(DevBuf &b, int64_t bytes, const char *what, bool cached = false);
   void release(DevBuf &b);
   // Cached workspace of at least `bytes` (device), reused across synchronous calls.
   int workspace(const char *name, int64_t bytes, void **out);
   void free_cache();
+  // Whether a synchronous call may allocate `extra` more bytes now.
   bool would_fit(int64_t extra);
+  // Device bytes a synchronous call may plan with: the limit minus the serving jobs'
+  // reservations (the call's own cached workspaces count as available).
+  int64_t sync_budget();
+  // Free part of the limit for admitting a serving job of `need` bytes: if it fits, the
+  // need is added to `reserved` in the same critical section and true is returned.
+  bool try_reserve(int64_t need, int64_t *cached_out);
+  void unreserve(int64_t need);
 };
 
 // ---- staged system ----------------------------------------------------------------

@@ -157,15 +157,12 @@ int Scheduler::submit(const rpa_system *sys, const rpa_freq *freq, rpa_precision
 
 Scheduler::Job *Scheduler::pick_locked() {
   for (int attempt = 0; attempt < 2; ++attempt) {
-    int64_t free_now, cached = 0;
-    {
-      std::lock_guard<std::mutex> g(ctx_.mem_mu);
-      for (auto &kv : ctx_.cache) cached += kv.second.bytes;
-      // synchronous-call caches stay allocated; everything else in use is reserved by jobs
-      free_now = ctx_.hbm_limit - cached - reserved_;
-    }
+    // the first queued job whose footprint fits is reserved in the same critical section
+    // of the context's memory lock as the check, so a synchronous call planning at the
+    // same time already sees the reservation
+    int64_t cached = 0;
     for (auto it = queue_.begin(); it != queue_.end(); ++it) {
-      if ((*it)->need <= free_now) {
+      if (ctx_.try_reserve((*it)->need, &cached)) {
         Job *j = *it;
         queue_.erase(it);
         return j;
@@ -194,7 +191,6 @@ void Scheduler::worker(int w) {
         if (stop_) break;
         continue;
       }
-      reserved_ += j->need;
       ++running_;
     }
     j->t_start = now_seconds();
@@ -230,7 +226,7 @@ void Scheduler::worker(int w) {
       if (rc != RPA_OK) j->err = last_error();
       j->t_done = now_seconds();
       j->finished = true;
-      reserved_ -= j->need;
+      ctx_.unreserve(j->need);
       --running_;
       ++done_;
       // free the inputs now; the record stays until it is polled

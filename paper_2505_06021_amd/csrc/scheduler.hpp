@@ -40,7 +40,6 @@ class Scheduler {
   std::map<uint64_t, Job *> jobs_;
   std::vector<std::thread> workers_;
   uint64_t next_id_ = 1;
-  int64_t reserved_ = 0;
   int64_t submitted_ = 0, done_ = 0, running_ = 0;
   bool stop_ = false;
   bool started_ = false;

@@ -7,6 +7,7 @@ workload recipe next to the values:
     python tests/golden/make_golden.py sampled   # sampled points of the two large systems
     python tests/golden/make_golden.py dual      # the 3x3x1 slab on dual k/q grids, all points
     python tests/golden/make_golden.py sampledao # sampled points of the atomic-orbital slab
+    python tests/golden/make_golden.py sampled2400  # the 3x3x1 N_aux 2400 slab (adds missing points)
 """
 import json
 import math
@@ -42,11 +43,21 @@ def full(make):
     return dict(recipe=recipe(s), E=E, eps=g.tolist(), oracle_seconds=time.time() - t)
 
 
-def sampled(make, pts):
+def sampled(make, pts, keep=None):
+    """Oracle values of the listed (q, j) points.  keep: a file this script wrote before
+    for the same recipe; its points are reused and only the missing ones are computed."""
     s = make()
+    old = {}
+    if keep and os.path.exists(os.path.join(HERE, keep + ".json")):
+        prev = json.load(open(os.path.join(HERE, keep + ".json")))
+        if prev["recipe"] == recipe(s):
+            old = {(p["iq"], p["j"]): p for p in prev["points"]}
     out = []
     t = time.time()
     for iq, j in pts:
+        if (iq, j) in old:
+            out.append(old[(iq, j)])
+            continue
         out.append(dict(iq=iq, j=j, omega=float(s.omega[j]), eps=orc.point(s, iq, j, row_block=4)))
         print(f"  point q={iq} j={j}: {out[-1]['eps']!r}  ({time.time() - t:.0f} s)", flush=True)
     return dict(recipe=recipe(s), points=out, oracle_seconds=time.time() - t)
@@ -68,4 +79,7 @@ if __name__ == "__main__":
     elif what == "sampled6x6":
         write("slab6x6_naux1200_sampled", sampled(inputs.slab_6x6_1200, [(0, 0), (0, 7), (17, 0), (17, 7)]))
     elif what == "sampled2400":
-        write("slab3x3_naux2400_sampled", sampled(inputs.slab_3x3_2400, [(0, 0), (4, 7)]))
+        # two pairs of points on one q each, so that the paired (two frequencies per
+        # workgroup) contraction runs on an oracle-checked pair at this size
+        name = "slab3x3_naux2400_sampled"
+        write(name, sampled(inputs.slab_3x3_2400, [(0, 0), (0, 15), (4, 7), (4, 8)], keep=name))

@@ -39,6 +39,11 @@ def rel_fro(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
+def rel_rows(a, b):
+    """Element by element: max_PQ |a_PQ - b_PQ| / max_Q' |b_PQ'| (each row's own scale)."""
+    return float(np.max(np.abs(a - b).max(axis=1) / np.abs(b).max(axis=1)))
+
+
 def ragged_system(seed=31, nw=5):
     # N = 150 spans three 64-wide tiles with a ragged tail; M = 4*3*7 = 84 is not a
     # multiple of the 16-row K step
@@ -74,6 +79,7 @@ def test_chi0_gamma_real_explicit_B(ctx):
         got = ctx.chi0(s, 0, s.omega[j])
         assert got.dtype == np.float64
         assert rel_fro(got, ref) <= 1e-12
+        assert rel_rows(got, ref) <= 1e-12
 
 
 def test_chi0_ragged_tiles_philox(ctx):
@@ -84,6 +90,7 @@ def test_chi0_ragged_tiles_philox(ctx):
             ref = orc.chi0(s, iq, om)
             got = ctx.chi0(s, iq, om)
             assert rel_fro(got, ref) <= 1e-12, (iq, om)
+            assert rel_rows(got, ref) <= 1e-12, (iq, om)
             assert np.abs(got - got.conj().T).max() == 0.0
 
 
@@ -94,6 +101,30 @@ def test_chi0_slab384_sampled(ctx):
         ref = orc.chi0(s, iq, s.omega[j])
         got = ctx.chi0(s, iq, s.omega[j])
         assert rel_fro(got, ref) <= 1e-12
+        assert rel_rows(got, ref) <= 1e-12
+
+
+def test_chi0_split_count_capped_by_hbm_limit(monkeypatch):
+    """rpa_chi0 under an HBM limit that holds only a few of the row splits' partial
+    planes: the capped split count still gives the oracle's chi0 (and the one-split
+    result to rounding)."""
+    from paper_2505_06021_amd import rpa
+    say("chi0 split count under a tight HBM limit")
+    s = inputs.slab_3x3_384()
+    iq, om = 2, s.omega[3]
+    ref = orc.chi0(s, iq, om)
+    N, M = s.naux, s.M
+    plane = N * N * 16
+    # B slab, weight table, output and descriptors, plus three partial planes
+    limit = M * N * 16 + M * 8 + 2 * plane + (1 << 20) + 3 * plane
+    with rpa.Context(0, hbm_limit=limit) as c:
+        got = c.chi0(s, iq, om, device=False)
+    assert rel_fro(got, ref) <= 1e-12
+    assert rel_rows(got, ref) <= 1e-12
+    monkeypatch.setenv("RPA_CHI0_KSPLIT", "1")
+    with rpa.Context(0) as c:
+        one = c.chi0(s, iq, om, device=False)
+    assert rel_rows(got, one) <= 1e-13
 
 
 def test_chi0_device_memspace_equals_host(ctx):
@@ -147,6 +178,29 @@ def test_trln_matches_oracle(ctx, n):
     got = ctx.trln(pis)
     scale = np.max(np.abs(ref))
     assert np.max(np.abs(got - ref)) <= 1e-10 * scale
+
+
+@pytest.mark.parametrize("n", [1, 17, 150, 384])
+def test_trln_single_workgroup_matches_oracle(ctx, monkeypatch, n):
+    # RPA_TRLN_SINGLE=1: the one-workgroup-per-matrix factorisation instead of the blocked one
+    say(f"trln single-workgroup n={n}")
+    monkeypatch.setenv("RPA_TRLN_SINGLE", "1")
+    s = inputs.make_system("t", (1, 1, 1), 4, 30, n, 6, 300 + n, is_complex=True, sigma=0.2,
+                           periodic=False)
+    pis = np.stack(pis_of(s, [(0, j) for j in range(s.nw)]))
+    ref = np.array([orc.trace_log(p) for p in pis])
+    got = ctx.trln(pis)
+    assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+def test_energy_single_workgroup_trln_matches_oracle(ctx, monkeypatch):
+    say("energy with the single-workgroup Cholesky")
+    monkeypatch.setenv("RPA_TRLN_SINGLE", "1")
+    s = ragged_system(nw=4)
+    E_ref, g_ref = orc.energy(s)
+    E, eps = ctx.energy(s)
+    assert abs(E - E_ref) <= 1e-10 * abs(E_ref)
+    check_grid(eps, g_ref)
 
 
 def test_trln_real_input(ctx):
