@@ -160,6 +160,24 @@ int rpa_set_stream(rpa_ctx *ctx, void *hip_stream);
 int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega,
              rpa_precision prec, void *chi0);
 
+/* rpa_chi0 for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same FP64 chi0 of one
+ * (q, omega) point, written in full into chi0 [naux][naux] (complex, device memory), with
+ * no device allocation.  Its scratch (the small system arrays, one weight per contraction
+ * row and the partial planes of the row splits) is a fixed 64 MiB device array per GPU,
+ * held until the process ends; the row split count is capped to the planes that fit
+ * beside the weights.  The system must be complex with B given (nbas = 0), and every array
+ * in device memory; prec must be RPA_FP64.  The tile configuration is the one the tuner
+ * already chose for this shape in the process (by rpa_chi0), else the fixed or default
+ * one; nothing is timed.  Calls through one context are serialised; calls through two
+ * contexts on the same GPU at the same time race on the shared scratch.  Results equal
+ * rpa_chi0's to rounding (bit for bit at the same configuration and split count).
+ * Errors: RPA_E_ARG (precision, memspace, real or atomic-orbital system, B NULL, bad
+ * sizes), RPA_E_NOMEM if the band energies and nk*nocc*nvirt row weights do not fit in
+ * the 64 MiB, RPA_E_DEVICE. */
+int rpa_chi0_noalloc(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega,
+                     rpa_precision prec, void *chi0);
+
 /* Pi = V^(1/2) chi0 V^(1/2) (Algorithm 1, "Z = V^0.5 P V^0.5") for one n x n pair, all
  * arrays [n][n] in `memspace`; Pi is written in full.  Errors: RPA_E_ARG, RPA_E_NOMEM,
  * RPA_E_DEVICE. */

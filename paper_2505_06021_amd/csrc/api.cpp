@@ -80,6 +80,7 @@ int rpa_init(rpa_ctx **out, int device, uint64_t hbm_limit_bytes) {
   RPA_HIP(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return fail(RPA_E_ARG, "device %d not in [0, %d)", device, ndev);
   RPA_HIP(hipSetDevice(device));
+  RPA_TRY(noalloc_setup(device));   // address of the fixed scratch of rpa_chi0_noalloc
   size_t free_b = 0, total_b = 0;
   RPA_HIP(hipMemGetInfo(&free_b, &total_b));
   rpa_ctx *ctx = new (std::nothrow) rpa_ctx();

@@ -177,6 +177,14 @@ int tune_bf16_tile(hipStream_t st, const Bf16Group &g, int64_t M, int N, int64_t
 // row split count of each configuration in that order; the candidates are timed with it.
 int tune_f32_tile(hipStream_t st, const Chi0Args &a, int npts, bool cplx, const float2 *B32, const double *diag,
                   int *tile_out, const int *ksplit_of = nullptr);
+// The FP64 configuration tune_chi0_cfg would give this shape without timing anything:
+// the environment's fixed choice, else the choice already made (or loaded) for its shape
+// bucket, else the default (t64k16).
+int chi0_cfg_lookup(const Chi0Args &a, int npts, bool cplx);
+// Fixed device scratch of rpa_chi0_noalloc (noalloc.hip): its size, and the per-device
+// lookup of its address (called by rpa_init with the device current).
+constexpr int64_t kNoallocScratchBytes = (int64_t)64 << 20;
+int noalloc_setup(int device);
 // "bucket configuration" lines of the choices made so far; returns the full length.
 int tuned_entries(char *buf, int len);
 // RPA_TRLN_SINGLE=1 selects the one-workgroup-per-matrix Cholesky instead of the blocked one.

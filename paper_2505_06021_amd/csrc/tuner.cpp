@@ -165,6 +165,16 @@ int tune_chi0_cfg(hipStream_t st, const Chi0Args &a, int npts, bool cplx, int *c
   return RPA_OK;
 }
 
+int chi0_cfg_lookup(const Chi0Args &a, int npts, bool cplx) {
+  const int f = fixed_cfg();
+  if (f >= 0) return f;
+  const std::string key = bucket(a, npts, cplx);
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  load_cache_locked();
+  auto it = g_tuned.find(key);
+  return it != g_tuned.end() ? it->second : kDefaultCfg;
+}
+
 int tune_bf16_tile(hipStream_t st, const Bf16Group &g, int64_t M, int N, int64_t slots, int64_t max_part, bool cplx,
                    int *tn_out) {
   if (const char *e = getenv("RPA_BF16_TILE")) {

@@ -20,7 +20,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librpa.so")
 
-EXPORTS = ("rpa_init", "rpa_finalize", "rpa_last_error", "rpa_set_stream", "rpa_chi0", "rpa_pi",
+EXPORTS = ("rpa_init", "rpa_finalize", "rpa_last_error", "rpa_set_stream", "rpa_chi0", "rpa_chi0_noalloc", "rpa_pi",
            "rpa_trln", "rpa_energy", "rpa_points", "rpa_philox_B", "rpa_philox_words",
            "rpa_submit", "rpa_poll", "rpa_get_stats", "rpa_profile", "rpa_profile_read", "rpa_tuned")
 KERNEL_KINDS = ("philox", "chi0", "pi", "trln", "other", "chi0_aux")
@@ -78,6 +78,7 @@ def load():
         "rpa_finalize": [P],
         "rpa_set_stream": [P, P],
         "rpa_chi0": [P, C.POINTER(RpaSystemC), I32, D, C.c_int, P],
+        "rpa_chi0_noalloc": [P, C.POINTER(RpaSystemC), I32, D, C.c_int, P],
         "rpa_pi": [P, I32, I32, I32, P, P, P],
         "rpa_trln": [P, I32, I32, I32, I32, P, P],
         "rpa_energy": [P, C.POINTER(RpaSystemC), C.POINTER(RpaFreqC), C.c_int, P, P],
@@ -230,6 +231,13 @@ class Context:
             return out.cpu().numpy()
         out = np.empty((system.naux, system.naux), dtype=dt)
         self._check(self.lib.rpa_chi0(self.h, C.byref(m.c), iq, float(omega), prec, out.ctypes.data))
+        return out
+
+    def chi0_noalloc(self, marshal, iq, omega, out, prec=FP64):
+        """rpa_chi0_noalloc on a device-memory system description (a _Marshal made with
+        device=True and an explicit B) into the complex device tensor `out`."""
+        self._check(self.lib.rpa_chi0_noalloc(self.h, C.byref(marshal.c), iq, float(omega), prec,
+                                              out.data_ptr()))
         return out
 
     def pi(self, vhalf, chi0):
