@@ -53,12 +53,18 @@ enum rpa_status {
   RPA_E_CANCELLED = -7     /* job cancelled by rpa_finalize                            */
 };
 
-/* Arithmetic of the chi0 contraction; Pi, the Cholesky/log-det and the sums are FP64. */
+/* Arithmetic of the chi0 contraction; Pi, the Cholesky/log-det and the sums are FP64.
+ * Energy error per cell against FP64, as tested: FP32 and split-FP16 within 1e-6 Ha on
+ * every tested system; split-BF16 within about 1e-8 relative, which exceeds 1e-6 Ha on
+ * some systems (its tested bound is 2e-5 Ha): it is the fastest, not the most exact. */
 typedef enum {
   RPA_FP64 = 0,      /* FP64 MFMA                                                      */
   RPA_FP32 = 1,      /* FP32 MFMA, FP64 flush of partial sums, exact FP64 diagonal     */
-  RPA_BF16X3 = 2     /* split-BF16 (hi*hi + hi*lo + lo*hi) on MFMA, FP32 accumulate,
-                        FP64 flush of partial sums, exact FP64 diagonal                */
+  RPA_BF16X3 = 2,    /* split-BF16 (hi*hi + hi*lo + lo*hi) on MFMA, FP32 accumulate,
+                        FP64 sum of the row splits, exact FP64 diagonal                */
+  RPA_F16X3 = 3      /* split-FP16 (hi*hi + hi*lo + lo*hi) on MFMA with power-of-two
+                        operand scaling, FP32 accumulate, FP64 sum of the row splits,
+                        exact FP64 diagonal; as fast as split-BF16                     */
 } rpa_precision;
 
 typedef enum { RPA_MEM_HOST = 0, RPA_MEM_DEVICE = 1 } rpa_memspace;
@@ -66,9 +72,9 @@ typedef enum { RPA_MEM_HOST = 0, RPA_MEM_DEVICE = 1 } rpa_memspace;
 typedef struct rpa_ctx rpa_ctx;
 
 /*
- * One periodic system (Algorithm 1, "Require: C, eps_n").  The contraction runs over the
- * nk k-points of the regular grid for each of the nq q-points; Delta_kia(q) =
- * eps_a(k) - eps_i(k (+) q).
+ * One periodic system (the inputs of Algorithm 1: fit coefficients and band energies).
+ * The contraction runs over the nk k-points of the regular grid for each of the nq
+ * q-points; Delta_kia(q) = eps_a(k) - eps_i(k (+) q).
  *  kq        [nq][nk]  int32: row of eps_occ that holds k (+) q, in [0, nk_occ).
  *  eps_occ   [nk_occ][nocc]: occupied band energies (Hartree) at every point k (+) q can
  *            reach; eps_virt [nk][nvirt]: virtual band energies at the regular k.
@@ -178,7 +184,7 @@ int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega,
 int rpa_chi0_noalloc(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega,
                      rpa_precision prec, void *chi0);
 
-/* Pi = V^(1/2) chi0 V^(1/2) (Algorithm 1, "Z = V^0.5 P V^0.5") for one n x n pair, all
+/* Pi = V^(1/2) chi0 V^(1/2) (Algorithm 1, the sandwich step) for one n x n pair, all
  * arrays [n][n] in `memspace`; Pi is written in full.  Errors: RPA_E_ARG, RPA_E_NOMEM,
  * RPA_E_DEVICE. */
 int rpa_pi(rpa_ctx *ctx, int32_t n, int32_t is_complex, int32_t memspace,

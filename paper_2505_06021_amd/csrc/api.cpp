@@ -136,7 +136,7 @@ int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega, rpa_
   if (!chi0) return fail(RPA_E_ARG, "chi0 output is NULL");
   if (iq < 0 || iq >= hs.nq) return fail(RPA_E_ARG, "iq = %d outside [0, nq)", iq);
   if (!std::isfinite(omega) || omega < 0.0) return fail(RPA_E_ARG, "omega must be finite and >= 0");
-  if (prec != RPA_FP64 && prec != RPA_FP32 && prec != RPA_BF16X3)
+  if (prec != RPA_FP64 && prec != RPA_FP32 && prec != RPA_BF16X3 && prec != RPA_F16X3)
     return fail(RPA_E_ARG, "unknown precision %d", (int)prec);
   const int N = hs.naux;
   const int64_t M = (int64_t)hs.nk * hs.nocc * hs.nvirt;
@@ -236,8 +236,9 @@ int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega, rpa_
     if (ks_max > 1) return c.workspace("chi0_partial", (int64_t)(ks_max - 1) * plane, (void **)&a.partial);
     return RPA_OK;
   };
-  if (prec == RPA_BF16X3) {
-    // prepared left (unscaled) and right (scaled) operands, then the split contraction
+  if (prec == RPA_BF16X3 || prec == RPA_F16X3) {
+    // prepared left (unweighted) and right (weighted) operands, then the split contraction
+    const bool f16 = prec == RPA_F16X3;
     double *dg, *scr;
     unsigned short *lr;
     float2 *part;
@@ -251,8 +252,19 @@ int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega, rpa_
     RPA_TRY(c.workspace("chi0_bf16_part", max_part * 8, (void **)&part));
     RPA_TRY(c.workspace("chi0_diag", (int64_t)N * 8, (void **)&dg));
     RPA_TRY(c.workspace("chi0_diag_scratch", bf16_diag_scratch_doubles(M, N) * 8, (void **)&scr));
-    RPA_HIP(launch_bf16_prepare(c.stream, B, cplx, M, N, nullptr, 1, lr));
-    RPA_HIP(launch_bf16_prepare(c.stream, B, cplx, M, N, wt, 1, lr + pe, scr, dg));
+    double *sc = nullptr;   // fp16: [slab maxima | weight maxima | left scale | right scale]
+    if (f16) {
+      const int64_t nb = f16_absmax_scratch_doubles(1);
+      RPA_TRY(c.workspace("chi0_f16_scales", (2 * nb + 2) * 8, (void **)&sc));
+      RPA_HIP(launch_absmax_blocks(c.stream, (const double *)B, M * N * (cplx ? 2 : 1), 0, 1, sc));
+      RPA_HIP(launch_absmax_blocks(c.stream, wt, M, M, 1, sc + nb));
+      RPA_HIP(launch_f16_scales(c.stream, sc, nullptr, nullptr, 1, sc + 2 * nb));
+      RPA_HIP(launch_f16_scales(c.stream, sc, sc + nb, a.pts, 1, sc + 2 * nb + 1));
+    }
+    const double *lsc = f16 ? sc + 2 * f16_absmax_scratch_doubles(1) : nullptr;
+    const double *rsc = f16 ? lsc + 1 : nullptr;
+    RPA_HIP(launch_bf16_prepare(c.stream, B, cplx, M, N, nullptr, 1, lr, nullptr, nullptr, lsc, f16));
+    RPA_HIP(launch_bf16_prepare(c.stream, B, cplx, M, N, wt, 1, lr + pe, scr, dg, rsc, f16));
     Bf16Group g{};
     g.L = lr;
     g.l_stride = 0;
@@ -261,11 +273,12 @@ int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega, rpa_
     g.pts = a.pts;
     g.part = part;
     g.npts = 1;
+    g.f16 = f16;
     int tn = 128;
     RPA_TRY(tune_bf16_tile(c.stream, g, M, N, ncu, max_part, cplx, &tn));
     bf16_plan(M, N, 1, ncu, max_part, tn, &g.pl);
     RPA_HIP(launch_bf16_herk_groups(c.stream, &g, 1, cplx));
-    RPA_HIP(launch_bf16_reduce(c.stream, g.pl, part, 1, N, dg, out, 0));
+    RPA_HIP(launch_bf16_reduce(c.stream, g.pl, part, 1, N, dg, out, 0, a.pts, lsc, rsc));
   } else if (prec != RPA_FP64) {
     float2 *b32;
     double *dg, *scr;
@@ -374,7 +387,7 @@ int rpa_energy(rpa_ctx *ctx, const rpa_system *sys, const rpa_freq *freq, rpa_pr
   RPA_TRY(validate_system(sys, hs));
   RPA_TRY(validate_freq(freq));
   if (!E) return fail(RPA_E_ARG, "E is NULL");
-  if (prec != RPA_FP64 && prec != RPA_FP32 && prec != RPA_BF16X3)
+  if (prec != RPA_FP64 && prec != RPA_FP32 && prec != RPA_BF16X3 && prec != RPA_F16X3)
     return fail(RPA_E_ARG, "unknown precision %d", (int)prec);
   PointJob job;
   job.sys = sys;
@@ -404,7 +417,7 @@ int rpa_points(rpa_ctx *ctx, const rpa_system *sys, int32_t npts, const int32_t 
   if (npts < 0) return fail(RPA_E_ARG, "npts < 0");
   if (npts == 0) return RPA_OK;
   if (!iq || !w || !eps) return fail(RPA_E_ARG, "NULL array");
-  if (prec != RPA_FP64 && prec != RPA_FP32 && prec != RPA_BF16X3)
+  if (prec != RPA_FP64 && prec != RPA_FP32 && prec != RPA_BF16X3 && prec != RPA_F16X3)
     return fail(RPA_E_ARG, "unknown precision %d", (int)prec);
   PointJob job;
   job.sys = sys;

@@ -1,15 +1,25 @@
-// Split-BF16 chi0 from prepared operands (the reduced-precision path of the chi0 build,
-// periodic RPA section: chi0_PQ(q, i w) = sum_k zeta_k sum_ia conj(B_iaP) w_ia B_iaQ).
+// Split-BF16 and split-FP16 chi0 from prepared operands (the reduced-precision paths of
+// the chi0 build, periodic RPA section: chi0_PQ(q, i w) = sum_k zeta_k sum_ia
+// conj(B_iaP) w_ia B_iaQ).
 //
-// The operands are written once into HBM in the form the BF16 MFMA consumes:
-//   L   = B            per q (shared by every frequency of that q)
-//   R_p = w_p zeta B   per point p of a launch
-// every element x of both split in FP64 as hi = bf16(x), lo = bf16(x - hi), for its real
-// and imaginary parts: four planes (re hi, re lo, im hi, im lo).  The contraction then
-// does nothing but copy panels into LDS and issue MFMAs:
+// The operands are written once into HBM in the form the 16-bit MFMA consumes:
+//   L   = s_L B            per q (shared by every frequency of that q)
+//   R_p = s_p w_p zeta B   per point p of a launch
+// every element x of both split in FP64 as hi = t(x), lo = t(x - hi), t the rounding to
+// the 16-bit format (bf16, or fp16), for its real and imaginary parts: four planes (re hi,
+// re lo, im hi, im lo).  The contraction then does nothing but copy panels into LDS and
+// issue MFMAs:
 //   Re chi0 += Lr Rr + Li Ri,   Im chi0 += Lr Ri - Li Rr,
 // each real product as hi*hi + hi*lo + lo*hi with FP32 accumulation (the lo*lo term is
-// below the FP32 rounding of the sum).  The contraction rows are cut into splits of at
+// below the FP32 rounding of the sum).  The two formats differ in what hi + lo keeps:
+// bf16's 8-bit significands leave about 2^-17 of each element (enough for a relative
+// energy error near 1e-8, not for 1e-6 Ha on every system), fp16's 11-bit significands
+// about 2^-22.  fp16 has a narrow exponent range, so the fp16 operands are scaled by
+// powers of two (s_L from the largest |Re|, |Im| of the B slab, s_p from that times the
+// largest |w_m zeta_k| of the point) that put their largest element just below 2^14:
+// hi*hi stays far inside FP32's range and an element below fp16's normal range carries
+// an error below 2^-39 of the largest one.  The reduction divides by s_L s_p (exact).
+// bf16 keeps s = 1.  The contraction rows are cut into splits of at
 // most BF16_SPLIT_ROWS rows; each split's FP32 tile goes to a partial buffer, so no FP32
 // sum runs over more rows than that, and a reduction adds the splits in FP64 in a fixed
 // order, mirrors the lower triangle into the Hermitian matrix and puts in the diagonal
@@ -34,6 +44,7 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 
 constexpr int HT = 128;          // column padding of the prepared layout (the largest tile)
 constexpr int HK = 32;           // contraction rows per step (the K of one BF16 MFMA)
@@ -52,17 +63,35 @@ __device__ __forceinline__ void tile_of(int t, int &tr, int &tc) {
 
 __device__ __forceinline__ int seg_pos(int s, int n) { return s ^ ((n >> 1) & 3); }
 
-// hi = bf16(x) (round to nearest even through FP32), lo = bf16(x - hi) with the
-// difference taken in FP64; two values at once, packed as the MFMA reads them.
+// hi = t(x) (round to nearest even through FP32), lo = t(x - hi) with the difference
+// taken in FP64 (exact: hi has at most 11 significant bits); two values at once, packed
+// as the MFMA reads them.  t = bf16, or fp16 when F16.
+template <bool F16>
 __device__ __forceinline__ void split_pair(double x0, double x1, unsigned &hi, unsigned &lo) {
   typedef float f2v __attribute__((ext_vector_type(2)));
   typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+  typedef _Float16 h2v __attribute__((ext_vector_type(2)));
   const f2v xf = {(float)x0, (float)x1};
-  hi = __builtin_bit_cast(unsigned, __builtin_convertvector(xf, b2v));
-  const double h0 = (double)__builtin_bit_cast(float, hi << 16);
-  const double h1 = (double)__builtin_bit_cast(float, hi & 0xffff0000u);
-  const f2v r = {(float)(x0 - h0), (float)(x1 - h1)};
-  lo = __builtin_bit_cast(unsigned, __builtin_convertvector(r, b2v));
+  if (F16) {
+    const h2v h = __builtin_convertvector(xf, h2v);
+    hi = __builtin_bit_cast(unsigned, h);
+    const f2v r = {(float)(x0 - (double)h[0]), (float)(x1 - (double)h[1])};
+    lo = __builtin_bit_cast(unsigned, __builtin_convertvector(r, h2v));
+  } else {
+    hi = __builtin_bit_cast(unsigned, __builtin_convertvector(xf, b2v));
+    const double h0 = (double)__builtin_bit_cast(float, hi << 16);
+    const double h1 = (double)__builtin_bit_cast(float, hi & 0xffff0000u);
+    const f2v r = {(float)(x0 - h0), (float)(x1 - h1)};
+    lo = __builtin_bit_cast(unsigned, __builtin_convertvector(r, b2v));
+  }
+}
+
+// Power of two that puts a largest magnitude m just below 2^14 (1 for m = 0 or not finite).
+__device__ __forceinline__ double f16_scale_of(double m) {
+  if (!(m > 0.0) || !(m < 1e300)) return 1.0;
+  int e;
+  (void)frexp(m, &e);          // m < 2^e
+  return ldexp(1.0, 14 - e);
 }
 
 // ------------------------------------------------------------------ preparation
@@ -75,11 +104,11 @@ __device__ __forceinline__ void split_pair(double x0, double x1, unsigned &hi, u
 // (workgroup row chunk, point, column).
 constexpr int PREP_STEPS = 4;
 
-template <bool CPLX, bool NTS>
+template <bool CPLX, bool NTS, bool F16>
 __global__ __launch_bounds__(256) void bf16_prepare_kernel(const void *B, int64_t M, int N, int Np,
                                                            const double *wtab, int64_t w_stride, int np,
                                                            unsigned short *out, int64_t out_stride,
-                                                           double *dpart) {
+                                                           double *dpart, const double *scale) {
   // the row tile and, after the last step, the diagonal's reduction buffer share one LDS
   // array (37 KB a workgroup in all: four workgroups per CU)
   constexpr int TB_BYTES = HK * (PREP_COLS + 1) * 16, RED_BYTES = 4 * PREP_MAXP * PREP_COLS * 8;
@@ -131,12 +160,13 @@ __global__ __launch_bounds__(256) void bf16_prepare_kernel(const void *B, int64_
     for (int e = 0; e < 8; ++e) b2[e] = v[e].x * v[e].x + v[e].y * v[e].y;
     for (int p = 0; p < reps; ++p) {
       unsigned hr[4], lr[4], hi_[4], li_[4];
+      const double sc = scale ? scale[p] : 1.0;   // a power of two: exact
 #pragma unroll
       for (int e2 = 0; e2 < 4; ++e2) {
-        const double w0 = wtab ? wl[p][8 * s + 2 * e2] : 1.0;
-        const double w1 = wtab ? wl[p][8 * s + 2 * e2 + 1] : 1.0;
-        split_pair(w0 * v[2 * e2].x, w1 * v[2 * e2 + 1].x, hr[e2], lr[e2]);
-        if (CPLX) split_pair(w0 * v[2 * e2].y, w1 * v[2 * e2 + 1].y, hi_[e2], li_[e2]);
+        const double w0 = (wtab ? wl[p][8 * s + 2 * e2] : 1.0) * sc;
+        const double w1 = (wtab ? wl[p][8 * s + 2 * e2 + 1] : 1.0) * sc;
+        split_pair<F16>(w0 * v[2 * e2].x, w1 * v[2 * e2 + 1].x, hr[e2], lr[e2]);
+        if (CPLX) split_pair<F16>(w0 * v[2 * e2].y, w1 * v[2 * e2 + 1].y, hi_[e2], li_[e2]);
       }
       if (dpart) {
         double d = 0.0;
@@ -220,15 +250,20 @@ struct HerkArgs {
   int64_t nkc;               // steps in the whole contraction (Mp / 32)
 };
 
-__device__ __forceinline__ f4 mfma_bf16(bf8 a, bf8 b, f4 c) {
+__device__ __forceinline__ f4 mfma16(bf8 a, bf8 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ f4 mfma16(h8 a, h8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
 
-__device__ __forceinline__ bf8 negate(bf8 x) {
+// -x of eight packed 16-bit values (the sign is bit 15 in both formats)
+template <class V>
+__device__ __forceinline__ V negate(V x) {
   typedef unsigned u4v __attribute__((ext_vector_type(4)));
   u4v u = __builtin_bit_cast(u4v, x);
   u ^= 0x80008000u;
-  return __builtin_bit_cast(bf8, u);
+  return __builtin_bit_cast(V, u);
 }
 
 // one 8 KB panel (128 columns x 32 rows of one plane) from HBM straight into LDS: one
@@ -247,8 +282,9 @@ struct HerkLaunch {
   HerkArgs g[BF16_MAX_GROUPS];
 };
 
-template <bool CPLX, int TW>
+template <bool CPLX, int TW, bool F16>
 __global__ __launch_bounds__(4 * TW) void herk_bf16x3_kernel(HerkLaunch hl) {
+  typedef typename std::conditional<F16, h8, bf8>::type bf8;   // the fragment type
   constexpr int NPL = CPLX ? 4 : 2;
   constexpr int XB = TW / 32;      // 16-row blocks per wave (wave rows: TW / 2)
   constexpr int NWC = TW / 32;     // waves across the tile's columns (32 columns each)
@@ -331,32 +367,32 @@ __global__ __launch_bounds__(4 * TW) void herk_bf16x3_kernel(HerkLaunch hl) {
       for (int pl = 0; pl < NPL; ++pl) A[pl] = frag(lds[buf][0][pl], wr * (TW / 2) + x * 16 + li);
       // Re: Lr Rr (+ Li Ri); each as hi hi + hi lo + lo hi
 #pragma unroll
-      for (int y = 0; y < 2; ++y) accR[x][y] = mfma_bf16(A[0], Bv[y][0], accR[x][y]);
+      for (int y = 0; y < 2; ++y) accR[x][y] = mfma16(A[0], Bv[y][0], accR[x][y]);
 #pragma unroll
-      for (int y = 0; y < 2; ++y) accR[x][y] = mfma_bf16(A[0], Bv[y][1], accR[x][y]);
+      for (int y = 0; y < 2; ++y) accR[x][y] = mfma16(A[0], Bv[y][1], accR[x][y]);
 #pragma unroll
-      for (int y = 0; y < 2; ++y) accR[x][y] = mfma_bf16(A[1], Bv[y][0], accR[x][y]);
+      for (int y = 0; y < 2; ++y) accR[x][y] = mfma16(A[1], Bv[y][0], accR[x][y]);
       if (CPLX) {
         const bf8 nh = negate(A[2]), nl = negate(A[3]);
 #pragma unroll
-        for (int y = 0; y < 2; ++y) accI[x][y] = mfma_bf16(A[0], Bv[y][2], accI[x][y]);
+        for (int y = 0; y < 2; ++y) accI[x][y] = mfma16(A[0], Bv[y][2], accI[x][y]);
 #pragma unroll
-        for (int y = 0; y < 2; ++y) accR[x][y] = mfma_bf16(A[2], Bv[y][2], accR[x][y]);
+        for (int y = 0; y < 2; ++y) accR[x][y] = mfma16(A[2], Bv[y][2], accR[x][y]);
 #pragma unroll
-        for (int y = 0; y < 2; ++y) accI[x][y] = mfma_bf16(A[0], Bv[y][3], accI[x][y]);
+        for (int y = 0; y < 2; ++y) accI[x][y] = mfma16(A[0], Bv[y][3], accI[x][y]);
 #pragma unroll
-        for (int y = 0; y < 2; ++y) accR[x][y] = mfma_bf16(A[2], Bv[y][3], accR[x][y]);
+        for (int y = 0; y < 2; ++y) accR[x][y] = mfma16(A[2], Bv[y][3], accR[x][y]);
 #pragma unroll
-        for (int y = 0; y < 2; ++y) accI[x][y] = mfma_bf16(A[1], Bv[y][2], accI[x][y]);
+        for (int y = 0; y < 2; ++y) accI[x][y] = mfma16(A[1], Bv[y][2], accI[x][y]);
 #pragma unroll
-        for (int y = 0; y < 2; ++y) accR[x][y] = mfma_bf16(A[3], Bv[y][2], accR[x][y]);
+        for (int y = 0; y < 2; ++y) accR[x][y] = mfma16(A[3], Bv[y][2], accR[x][y]);
         // Im: - Li Rr
 #pragma unroll
-        for (int y = 0; y < 2; ++y) accI[x][y] = mfma_bf16(nh, Bv[y][0], accI[x][y]);
+        for (int y = 0; y < 2; ++y) accI[x][y] = mfma16(nh, Bv[y][0], accI[x][y]);
 #pragma unroll
-        for (int y = 0; y < 2; ++y) accI[x][y] = mfma_bf16(nh, Bv[y][1], accI[x][y]);
+        for (int y = 0; y < 2; ++y) accI[x][y] = mfma16(nh, Bv[y][1], accI[x][y]);
 #pragma unroll
-        for (int y = 0; y < 2; ++y) accI[x][y] = mfma_bf16(nl, Bv[y][0], accI[x][y]);
+        for (int y = 0; y < 2; ++y) accI[x][y] = mfma16(nl, Bv[y][0], accI[x][y]);
       }
     }
   };
@@ -392,20 +428,20 @@ __global__ __launch_bounds__(4 * TW) void herk_bf16x3_kernel(HerkLaunch hl) {
         A[pl] = frag(lds[buf][0][pl], bxs[j] * 16 + li);
         Bv[pl] = frag(lds[buf][1][pl], bys[j] * 16 + li);
       }
-      dR[j] = mfma_bf16(A[0], Bv[0], dR[j]);
-      dR[j] = mfma_bf16(A[0], Bv[1], dR[j]);
-      dR[j] = mfma_bf16(A[1], Bv[0], dR[j]);
+      dR[j] = mfma16(A[0], Bv[0], dR[j]);
+      dR[j] = mfma16(A[0], Bv[1], dR[j]);
+      dR[j] = mfma16(A[1], Bv[0], dR[j]);
       if (CPLX) {
         const bf8 nh = negate(A[2]), nl = negate(A[3]);
-        dI[j] = mfma_bf16(A[0], Bv[2], dI[j]);
-        dR[j] = mfma_bf16(A[2], Bv[2], dR[j]);
-        dI[j] = mfma_bf16(A[0], Bv[3], dI[j]);
-        dR[j] = mfma_bf16(A[2], Bv[3], dR[j]);
-        dI[j] = mfma_bf16(A[1], Bv[2], dI[j]);
-        dR[j] = mfma_bf16(A[3], Bv[2], dR[j]);
-        dI[j] = mfma_bf16(nh, Bv[0], dI[j]);
-        dI[j] = mfma_bf16(nh, Bv[1], dI[j]);
-        dI[j] = mfma_bf16(nl, Bv[0], dI[j]);
+        dI[j] = mfma16(A[0], Bv[2], dI[j]);
+        dR[j] = mfma16(A[2], Bv[2], dR[j]);
+        dI[j] = mfma16(A[0], Bv[3], dI[j]);
+        dR[j] = mfma16(A[2], Bv[3], dR[j]);
+        dI[j] = mfma16(A[1], Bv[2], dI[j]);
+        dR[j] = mfma16(A[3], Bv[2], dR[j]);
+        dI[j] = mfma16(nh, Bv[0], dI[j]);
+        dI[j] = mfma16(nh, Bv[1], dI[j]);
+        dI[j] = mfma16(nl, Bv[0], dI[j]);
       }
     }
   };
@@ -462,7 +498,9 @@ __global__ __launch_bounds__(4 * TW) void herk_bf16x3_kernel(HerkLaunch hl) {
 // the FP32 tiles; the diagonal from `diag`.  A workgroup covers a 32 x 32 block of one
 // tile (tw x tw); the mirrored block goes through LDS so both writes are row-contiguous.
 __global__ __launch_bounds__(256) void herk_reduce_kernel(const float2 *part, int nsplit, int ntiles, int tw, int N,
-                                                          const double *diag, double2 *out, int64_t out_stride) {
+                                                          const double *diag, double2 *out, int64_t out_stride,
+                                                          const PointDesc *pts, const double *lscale,
+                                                          const double *rscale) {
   __shared__ double2 tb[32][33];
   const int tile = blockIdx.x, blk = blockIdx.y, p = blockIdx.z;
   int tr, tc;
@@ -478,6 +516,8 @@ __global__ __launch_bounds__(256) void herk_reduce_kernel(const float2 *part, in
   const float2 *src = part + ((int64_t)p * nsplit * ntiles + tile) * tsz;
   double2 *dst = out + (int64_t)p * out_stride;
   const double *dg = diag + (int64_t)p * N;
+  // undo the operands' power-of-two scales (1 for bf16 operands): exact
+  const double inv = lscale ? 1.0 / (lscale[pts[p].bslot] * rscale[p]) : 1.0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int i = (tid >> 5) + 8 * k;
@@ -488,6 +528,8 @@ __global__ __launch_bounds__(256) void herk_reduce_kernel(const float2 *part, in
       re += (double)v.x;
       im += (double)v.y;
     }
+    re *= inv;
+    im *= inv;
     tb[i][j] = make_double2(re, im);
     const int P = tr * tw + li, Q = tc * tw + lj;
     if (P < N && Q < N && (!dtile || P >= Q))
@@ -506,7 +548,64 @@ __global__ __launch_bounds__(256) void herk_reduce_kernel(const float2 *part, in
   }
 }
 
+// ------------------------------------------------------------------ fp16 scales
+// part[seg][blk] = max |x| over block blk of segment seg (segments of seg_len doubles,
+// seg_stride apart); the maximum is exact, so the result does not depend on the order.
+constexpr int AMAX_BLOCKS = 256;
+__global__ __launch_bounds__(256) void absmax_partial_kernel(const double *x, int64_t seg_len, int64_t seg_stride,
+                                                             double *part) {
+  __shared__ double red[256];
+  const int seg = blockIdx.y;
+  const double *xs = x + (int64_t)seg * seg_stride;
+  double m = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < seg_len; i += (int64_t)gridDim.x * 256)
+    m = fmax(m, fabs(xs[i]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(int64_t)seg * gridDim.x + blockIdx.x] = red[0];
+}
+
+// out[i] = the fp16 scale of bmax[slot_i] * (wmax ? wmax[i] : 1), slot_i = pts[i].bslot
+// (or i without pts); bmax and wmax come from absmax_partial_kernel's blocks (nblk per
+// segment) and are reduced here.
+__global__ __launch_bounds__(64) void f16_scale_kernel(const double *bpart, const double *wpart, int nblk,
+                                                       const PointDesc *pts, int n, double *out) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= n) return;
+  const int slot = pts ? pts[i].bslot : i;
+  double mb = 0.0, mw = 1.0;
+  for (int b = 0; b < nblk; ++b) mb = fmax(mb, bpart[(int64_t)slot * nblk + b]);
+  if (wpart) {
+    mw = 0.0;
+    for (int b = 0; b < nblk; ++b) mw = fmax(mw, wpart[(int64_t)i * nblk + b]);
+  }
+  out[i] = f16_scale_of(mb * mw);
+}
+
 }  // namespace
+
+int64_t f16_absmax_scratch_doubles(int nseg) { return (int64_t)nseg * AMAX_BLOCKS; }
+
+hipError_t launch_absmax_blocks(hipStream_t s, const double *x, int64_t seg_len, int64_t seg_stride, int nseg,
+                                double *part) {
+  if (nseg <= 0) return hipSuccess;
+  if (nseg > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(absmax_partial_kernel, dim3(AMAX_BLOCKS, (unsigned)nseg), dim3(256), 0, s, x, seg_len, seg_stride,
+                     part);
+  return hipGetLastError();
+}
+
+hipError_t launch_f16_scales(hipStream_t s, const double *bpart, const double *wpart, const PointDesc *pts, int n,
+                             double *out) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(f16_scale_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, bpart, wpart, AMAX_BLOCKS, pts,
+                     n, out);
+  return hipGetLastError();
+}
 
 int64_t bf16_prepared_elems(int64_t M, int N) {
   const int64_t Mp = (M + HK - 1) / HK * HK;
@@ -547,7 +646,8 @@ int64_t bf16_diag_scratch_doubles(int64_t M, int N) {
 }
 
 hipError_t launch_bf16_prepare(hipStream_t s, const void *B, bool cplx, int64_t M, int N, const double *wtab,
-                               int npts, unsigned short *out, double *dscratch, double *diag) {
+                               int npts, unsigned short *out, double *dscratch, double *diag, const double *scale,
+                               bool f16) {
   const int64_t nkc = (M + HK - 1) / HK;
   const int Np = (N + HT - 1) / HT * HT;
   const int64_t stride = bf16_prepared_elems(M, N);
@@ -561,13 +661,22 @@ hipError_t launch_bf16_prepare(hipStream_t s, const void *B, bool cplx, int64_t 
     const dim3 grid((unsigned)nchunks, (unsigned)(Np / PREP_COLS));
     double *dp = want_diag ? dscratch : nullptr;
     // right operands (w set) with non-temporal stores, the left operand through the caches
-#define RPA_PREP_LAUNCH(C, NT)                                                                       \
-  hipLaunchKernelGGL((bf16_prepare_kernel<C, NT>), grid, dim3(256), 0, s, B, M, N, Np, w, M, np, \
-                     out + (int64_t)p0 * stride, stride, dp)
-    if (cplx) {
-      if (w) RPA_PREP_LAUNCH(true, true); else RPA_PREP_LAUNCH(true, false);
+    const double *sc = scale ? scale + p0 : nullptr;
+#define RPA_PREP_LAUNCH(C, NT, F)                                                                       \
+  hipLaunchKernelGGL((bf16_prepare_kernel<C, NT, F>), grid, dim3(256), 0, s, B, M, N, Np, w, M, np, \
+                     out + (int64_t)p0 * stride, stride, dp, sc)
+    if (f16) {
+      if (cplx) {
+        if (w) RPA_PREP_LAUNCH(true, true, true); else RPA_PREP_LAUNCH(true, false, true);
+      } else {
+        if (w) RPA_PREP_LAUNCH(false, true, true); else RPA_PREP_LAUNCH(false, false, true);
+      }
     } else {
-      if (w) RPA_PREP_LAUNCH(false, true); else RPA_PREP_LAUNCH(false, false);
+      if (cplx) {
+        if (w) RPA_PREP_LAUNCH(true, true, false); else RPA_PREP_LAUNCH(true, false, false);
+      } else {
+        if (w) RPA_PREP_LAUNCH(false, true, false); else RPA_PREP_LAUNCH(false, false, false);
+      }
     }
 #undef RPA_PREP_LAUNCH
     hipError_t e = hipGetLastError();
@@ -587,8 +696,9 @@ hipError_t launch_bf16_herk_groups(hipStream_t s, const Bf16Group *groups, int n
   if (ngroups <= 0) return hipSuccess;
   if (ngroups > BF16_MAX_GROUPS) return hipErrorInvalidValue;
   const int tn = groups[0].pl.tn;
-  for (int i = 1; i < ngroups; ++i)
-    if (groups[i].pl.tn != tn) return hipErrorInvalidValue;   // one tile size per launch
+  const bool f16 = groups[0].f16;
+  for (int i = 1; i < ngroups; ++i)   // one tile size and one 16-bit format per launch
+    if (groups[i].pl.tn != tn || groups[i].f16 != f16) return hipErrorInvalidValue;
   HerkLaunch hl{};
   int64_t total = 0;
   int n = 0;
@@ -616,22 +726,32 @@ hipError_t launch_bf16_herk_groups(hipStream_t s, const Bf16Group *groups, int n
   hl.ngroups = n;
   for (int i = n; i <= BF16_MAX_GROUPS; ++i) hl.begin[i] = (int32_t)total;
   const dim3 grid((unsigned)total);
-  if (tn == 64) {
-    if (cplx) hipLaunchKernelGGL((herk_bf16x3_kernel<true, 64>), grid, dim3(256), 0, s, hl);
-    else hipLaunchKernelGGL((herk_bf16x3_kernel<false, 64>), grid, dim3(256), 0, s, hl);
+#define RPA_HERK_LAUNCH(C, T, F) hipLaunchKernelGGL((herk_bf16x3_kernel<C, T, F>), grid, dim3(4 * T), 0, s, hl)
+  if (f16) {
+    if (tn == 64) {
+      if (cplx) RPA_HERK_LAUNCH(true, 64, true); else RPA_HERK_LAUNCH(false, 64, true);
+    } else {
+      if (cplx) RPA_HERK_LAUNCH(true, 128, true); else RPA_HERK_LAUNCH(false, 128, true);
+    }
   } else {
-    if (cplx) hipLaunchKernelGGL((herk_bf16x3_kernel<true, 128>), grid, dim3(512), 0, s, hl);
-    else hipLaunchKernelGGL((herk_bf16x3_kernel<false, 128>), grid, dim3(512), 0, s, hl);
+    if (tn == 64) {
+      if (cplx) RPA_HERK_LAUNCH(true, 64, false); else RPA_HERK_LAUNCH(false, 64, false);
+    } else {
+      if (cplx) RPA_HERK_LAUNCH(true, 128, false); else RPA_HERK_LAUNCH(false, 128, false);
+    }
   }
+#undef RPA_HERK_LAUNCH
   return hipGetLastError();
 }
 
 hipError_t launch_bf16_reduce(hipStream_t s, const Bf16Plan &pl, const float2 *part, int npts, int N,
-                              const double *diag, double2 *out, int64_t out_stride) {
+                              const double *diag, double2 *out, int64_t out_stride, const PointDesc *pts,
+                              const double *lscale, const double *rscale) {
   if (npts <= 0) return hipSuccess;
+  if (lscale && (!pts || !rscale)) return hipErrorInvalidValue;
   const int nb = pl.tn / 32;
   hipLaunchKernelGGL(herk_reduce_kernel, dim3((unsigned)pl.ntiles, (unsigned)(nb * nb), (unsigned)npts), dim3(256), 0,
-                     s, part, pl.nsplit, pl.ntiles, pl.tn, N, diag, out, out_stride);
+                     s, part, pl.nsplit, pl.ntiles, pl.tn, N, diag, out, out_stride, pts, lscale, rscale);
   return hipGetLastError();
 }
 

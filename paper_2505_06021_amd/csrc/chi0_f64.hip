@@ -52,8 +52,9 @@ __global__ __launch_bounds__(256) void weight_table_kernel(Chi0Args a, int32_t n
     const int p = (int)(g / a.M);
     const int m = (int)(g - (int64_t)p * a.M);
     const PointDesc pd = a.pts[p];
-    const int k = m / nov;
-    const int rem = m - k * nov;
+    const int kr = m / nov;   // k-point of the row, relative to the rows' first one
+    const int rem = m - kr * nov;
+    const int k = a.k0 + kr;
     const int i = rem / a.nvirt;
     const int av = rem - i * a.nvirt;
     const int kq = a.kq[(int64_t)pd.q * a.nk + k];

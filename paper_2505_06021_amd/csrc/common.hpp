@@ -42,6 +42,8 @@ struct Chi0Args {
   const int32_t *pairs;     // [npairs][2] points of one slab contracted together (second
                             // index -1: none), for the paired FP64 kernel; may be null
   int32_t npairs;
+  int32_t k0;               // k-point of row 0: the rows are those of k-points k0 .. k0 +
+                            // M / (nocc * nvirt) - 1 (a chunk of a streamed q; else 0)
 };
 
 // Batched complex GEMM C_b = A_{a(b)} * B_{b(b)}, all N x N row-major.
@@ -149,9 +151,22 @@ int64_t bf16_partial_elems(const Bf16Plan &pl, int npts);
 // (one), else one right operand w_p B per point p < npts, at bf16_prepared_elems apart.
 // With dscratch (bf16_diag_scratch_doubles) and diag set, also the exact FP64 diagonal
 // diag[p][P] = sum_m wtab[p][m] |B_mP|^2 of those points.
+// scale (null: 1) is the operand's power-of-two factor (one per point for right operands,
+// read at scale[p]); f16 selects the fp16 split instead of bf16.
 int64_t bf16_diag_scratch_doubles(int64_t M, int N);
 hipError_t launch_bf16_prepare(hipStream_t s, const void *B, bool cplx, int64_t M, int N, const double *wtab,
-                               int npts, unsigned short *out, double *dscratch = nullptr, double *diag = nullptr);
+                               int npts, unsigned short *out, double *dscratch = nullptr, double *diag = nullptr,
+                               const double *scale = nullptr, bool f16 = false);
+// fp16 operand scales.  launch_absmax_blocks writes, for each of nseg segments of seg_len
+// doubles (seg_stride apart), the maxima of |x| over its blocks into part (nseg *
+// f16_absmax_scratch_doubles(1) doubles).  launch_f16_scales then sets out[i] to the
+// power of two that brings max(B slab of pts[i].bslot) * max|w_i| (wpart null: the slab
+// alone, slab i without pts) just below 2^14.
+int64_t f16_absmax_scratch_doubles(int nseg);
+hipError_t launch_absmax_blocks(hipStream_t s, const double *x, int64_t seg_len, int64_t seg_stride, int nseg,
+                                double *part);
+hipError_t launch_f16_scales(hipStream_t s, const double *bpart, const double *wpart, const PointDesc *pts, int n,
+                             double *out);
 // One contraction launch's worth of work (a sub-batch of one job).
 constexpr int BF16_MAX_GROUPS = 16;
 struct Bf16Group {
@@ -163,6 +178,7 @@ struct Bf16Group {
   float2 *part;
   Bf16Plan pl;
   int32_t npts;
+  bool f16 = false;          // fp16 operands (else bf16); one format per launch
 };
 // FP32 partial tiles of the row splits of every group's points (left operand of point p
 // at L + pts[p].bslot * l_stride, right operand p at R + p * r_stride) into its part
@@ -171,9 +187,12 @@ struct Bf16Group {
 // results are exactly those of launching it alone.
 hipError_t launch_bf16_herk_groups(hipStream_t s, const Bf16Group *groups, int ngroups, bool cplx);
 // chi0 of those points into out (FP64 complex, Hermitian, point p at p * out_stride): the
-// splits summed in FP64 in order, the diagonal from diag[p][P].
+// splits summed in FP64 in order, divided by lscale[pts[p].bslot] * rscale[p] (fp16
+// operands; lscale null: no scaling), the diagonal from diag[p][P].
 hipError_t launch_bf16_reduce(hipStream_t s, const Bf16Plan &pl, const float2 *part, int npts, int N,
-                              const double *diag, double2 *out, int64_t out_stride);
+                              const double *diag, double2 *out, int64_t out_stride,
+                              const PointDesc *pts = nullptr, const double *lscale = nullptr,
+                              const double *rscale = nullptr);
 
 // Blocked Cholesky log-det over the whole GPU on W = -Pi (see trln_blocked.hip):
 // eps[out_map[b]] = ln det(1 - Pi_b) + Re Tr Pi_b, info_out[out_map[b]] = -1 or the failing

@@ -78,8 +78,9 @@ void Fuser::run() {
     std::vector<Item *> batch;
     const bool cplx = items.front()->cplx;
     const int tn = items.front()->g.pl.tn;
+    const bool f16 = items.front()->g.f16;
     for (auto it = items.begin(); it != items.end() && (int)batch.size() < BF16_MAX_GROUPS;) {
-      if ((*it)->cplx == cplx && (*it)->g.pl.tn == tn) {
+      if ((*it)->cplx == cplx && (*it)->g.pl.tn == tn && (*it)->g.f16 == f16) {
         batch.push_back(*it);
         it = items.erase(it);
       } else {

@@ -328,25 +328,39 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   const int64_t belem = cplx ? 16 : 8;
   const bool b_direct = sys->B && sys->memspace == RPA_MEM_DEVICE;
   const bool vh_direct = sys->memspace == RPA_MEM_DEVICE && cplx;
-  const int64_t b_slot = b_direct ? 0 : M * N * belem;
   const int64_t vh_slot = vh_direct ? 0 : nn * 16;
-  // split-BF16 keeps a prepared (split, padded) copy of each B slab instead of the FP32
-  // copy of the FP32 path, plus per point in flight a prepared right operand and the
-  // partial tiles of the row splits
-  const bool bsplit = job.prec == RPA_BF16X3;
-  const int64_t prep_bytes = bsplit ? bf16_prepared_elems(M, N) * 2 : 0;
-  const int64_t b32_slot = bsplit ? prep_bytes : mixed ? M * N * 8 : 0;
+  // split-BF16 and split-FP16 keep a prepared (split, padded) copy of each B slab instead
+  // of the FP32 copy of the FP32 path, plus per point in flight a prepared right operand
+  // and the partial tiles of the row splits; fp16 operands carry power-of-two scales (one
+  // per B slot, one per point)
+  const bool bsplit = job.prec == RPA_BF16X3 || job.prec == RPA_F16X3;
+  const bool f16 = job.prec == RPA_F16X3;
+  const int64_t f16_slot = f16 ? (f16_absmax_scratch_doubles(1) + 1) * 8 : 0;   // slab maxima and scale
+  const int nov = hs.nocc * hs.nvirt;
   int ncu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx.device) != hipSuccess) ncu = 256;
+  // Sizes that follow the rows of one B slot: a whole q (kc = nk k-points), or, when one q
+  // does not fit the budget, a chunk of kc k-points: the q is then streamed chunk by
+  // chunk (B of each chunk generated or copied into the slot, contracted for every point
+  // of the batch, and the chunks' chi0 added in chunk order).
+  int kc = hs.nk;
+  int64_t Mc = M, b_slot = 0, prep_bytes = 0, b32_slot = 0, per_pt = 0, diag_scratch = 0;
+  auto set_rows = [&](int k) {
+    kc = k;
+    Mc = (int64_t)k * nov;
+    b_slot = b_direct ? 0 : Mc * N * belem;
+    prep_bytes = bsplit ? bf16_prepared_elems(Mc, N) * 2 : 0;
+    b32_slot = bsplit ? prep_bytes : mixed ? Mc * N * 8 : 0;   // the slots' stride in d_B32
+    per_pt = 2 * nn * 16 + Mc * 8 + (mixed ? (int64_t)N * 8 : 0) + trln_blocked_scratch_bytes(1) + 64;
+    diag_scratch = bsplit ? bf16_diag_scratch_doubles(Mc, N) * 8 : mixed ? diag_exact_scratch_doubles(Mc, N, 16) * 8 : 0;
+  };
+  set_rows(hs.nk);
   auto bsplit_bytes = [&](int64_t r) -> int64_t {
     if (!bsplit || r <= 0) return 0;
     Bf16Plan pl;
-    bf16_plan(M, N, (int)r, ncu, 0, 128, &pl);
-    return r * prep_bytes + bf16_partial_elems(pl, (int)r) * 8 + 512;
+    bf16_plan(Mc, N, (int)r, ncu, 0, 128, &pl);
+    return r * (prep_bytes + f16_slot) + bf16_partial_elems(pl, (int)r) * 8 + 512;
   };
-  const int64_t per_pt = 2 * nn * 16 + M * 8 + (mixed ? (int64_t)N * 8 : 0) + trln_blocked_scratch_bytes(1) + 64;
-  const int64_t diag_scratch = bsplit ? bf16_diag_scratch_doubles(M, N) * 8
-                              : mixed ? diag_exact_scratch_doubles(M, N, 16) * 8 : 0;
   // atomic-orbital systems: the projected coefficients and the transform's scratch
   const int64_t ao_bytes = hs.nbas > 0 ? (int64_t)(hs.c_occ.size() + hs.c_virt.size()) * 8 + 512 +
                                              ao_scratch_bytes(hs.nbas, hs.nocc, hs.naux)
@@ -379,7 +393,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
     return c;
   };
   // fixed per-lane buffers: one point's split-BF16 operands and the exact-diagonal scratch
-  const int64_t one_split = bsplit_bytes(1) + diag_scratch;
+  int64_t one_split = 0;
   int nlanes = (use_cache && lanes_wanted() > 1 && npts >= 8) ? 2 : 1;
   hipStream_t lane_st[2] = {st, nullptr};
   if (nlanes == 2) {
@@ -388,20 +402,32 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   }
   int64_t rest = 0, pbatch = 0, rbatch = 0;
   for (;;) {
+    one_split = bsplit_bytes(1) + diag_scratch;
     const int64_t lane_min = nlanes * (per_pt + one_split);
     gq = (int)qs.size();
     if (job.max_q_group > 0) gq = std::min(gq, job.max_q_group);
-    while (gq > 1 && gq * (b_slot + vh_slot + b32_slot) + nlanes * std::min<int64_t>(pts_of(0, gq), 256) * per_pt +
+    if (kc < hs.nk) gq = 1;
+    // device bytes per q slot: B, V^(1/2), the reduced-precision copy and the fp16
+    // operand's maxima and scale
+    const int64_t per_slot = b_slot + vh_slot + b32_slot + f16_slot;
+    while (gq > 1 && gq * per_slot + nlanes * std::min<int64_t>(pts_of(0, gq), 256) * per_pt +
                          nlanes * one_split > avail)
       --gq;
-    rest = avail - gq * (b_slot + vh_slot + b32_slot);
+    rest = avail - gq * per_slot;
     if (rest < lane_min && nlanes == 2) {
       nlanes = 1;
       continue;
     }
+    if (rest < lane_min && kc > 1) {
+      // one q does not fit: stream it in chunks of fewer k-points (one lane: the lanes
+      // would share the chunk slot)
+      set_rows((kc + 1) / 2);
+      nlanes = 1;
+      continue;
+    }
     if (rest < lane_min)
-      return fail(RPA_E_NOMEM, "one q of this system needs %lld bytes, budget is %lld",
-                  (long long)(b_slot + vh_slot + b32_slot + per_pt + one_split + small), (long long)budget);
+      return fail(RPA_E_NOMEM, "one k-point of one q of this system needs %lld bytes, budget is %lld",
+                  (long long)(per_slot + per_pt + one_split + small), (long long)budget);
     const int64_t pb_cap = (rest / nlanes - one_split) / per_pt;
     int64_t max_group_pts = 0;
     for (size_t g0 = 0; g0 < qs.size(); g0 += gq) max_group_pts = std::max(max_group_pts, pts_of((int)g0, gq));
@@ -418,8 +444,12 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
     break;
   }
   // FP64 and FP32: two more partial planes per lane (up to four row splits per launch)
-  // where the budget holds them; one plane (two splits) otherwise
+  // where the budget holds them; one plane (two splits) otherwise.  A streamed q keeps
+  // each later chunk's chi0 in the first plane before adding it in.
   const int tplanes = (!bsplit && pbatch * per_pt + one_split + 2 * pbatch * nn * 16 <= rest / nlanes) ? kBatchSplits - 1 : 1;
+  const bool streamed = kc < hs.nk;
+  const int nchunks = (hs.nk + kc - 1) / kc;
+  const int max_split = streamed ? tplanes : tplanes + 1;
 
   Arena ar(ctx, use_cache);
   const bool prof = use_cache && ctx.profile;   // timing only on the synchronous path
@@ -446,7 +476,12 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   if (mixed) ar.plan(gq * b32_slot, (void **)&d_B32);
   Bf16Plan rplan{};
   int bf16_tn = 0;   // split-BF16 tile edge, chosen on the first contraction
-  if (bsplit) bf16_plan(M, N, (int)rbatch, ncu, 0, 128, &rplan);
+  if (bsplit) bf16_plan(Mc, N, (int)rbatch, ncu, 0, 128, &rplan);
+  double *d_bpart = nullptr, *d_lscale = nullptr;   // fp16: slab maxima and scales per slot
+  if (f16) {
+    ar.plan(f16_absmax_scratch_doubles(gq) * 8, (void **)&d_bpart);
+    ar.plan((int64_t)gq * 8, (void **)&d_lscale);
+  }
   // per-lane batch buffers
   struct LaneBufs {
     PointDesc *pts = nullptr;
@@ -455,6 +490,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
     double *w = nullptr, *diag = nullptr, *dscr = nullptr;
     unsigned short *R = nullptr;
     float2 *part = nullptr;
+    double *wpart = nullptr, *rscale = nullptr;   // fp16: weight maxima and scales per point
   } lanes[2];
   for (int l = 0; l < nlanes; ++l) {
     LaneBufs &lb = lanes[l];
@@ -469,6 +505,10 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
     if (bsplit) {
       ar.plan(rbatch * prep_bytes, (void **)&lb.R);
       ar.plan(bf16_partial_elems(rplan, (int)rbatch) * 8, (void **)&lb.part);
+    }
+    if (f16) {
+      ar.plan(f16_absmax_scratch_doubles((int)rbatch) * 8, (void **)&lb.wpart);
+      ar.plan(rbatch * 8, (void **)&lb.rscale);
     }
     ar.plan(pbatch * nn * 16 * tplanes, &lb.T);
     ar.plan(trln_blocked_scratch_bytes((int32_t)pbatch), &lb.tscr);
@@ -499,6 +539,57 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
     RPA_HIP(hipMemcpyAsync(d_cvirt, hs.c_virt.data(), hs.c_virt.size() * 8, hipMemcpyHostToDevice, st));
   }
 
+  // B rows of the k-points [k0, k1) of q into slot s on stream S: generated (Philox, or
+  // the MO transform of an atomic-orbital system), or copied from the caller's host B; then
+  // the slot's reduced-precision copy (FP32, or the prepared split operand with its scale)
+  auto stage_b = [&](hipStream_t S, int s, int q, int k0, int k1) -> int {
+    const int64_t rows = (int64_t)(k1 - k0) * nov;
+    const int64_t off = ((int64_t)q * M + (int64_t)k0 * nov) * N * belem;   // in a caller's B
+    const char *src;
+    if (!b_direct) {
+      char *dst = (char *)d_B + (int64_t)s * b_slot;
+      if (!sys->B) {
+        if (prof) RPA_TRY(ctx.prof_begin(S, RPA_K_PHILOX));
+        if (hs.nbas > 0) {
+          // the MO transform of the pair-fit coefficients, one k block at a time
+          const int64_t cstride = (int64_t)hs.nbas * hs.nocc, vstride = (int64_t)hs.nbas * hs.nvirt;
+          const int64_t per_k = (int64_t)nov * N;
+          for (int ik = k0; ik < k1; ++ik)
+            RPA_HIP(launch_ao_B(S, sys->philox_seed, sys->sigma, hs.nk, q, ik, hs.nbas, hs.nocc, hs.nvirt, N,
+                                d_cocc + (int64_t)hs.kq[(size_t)q * hs.nk + ik] * cstride,
+                                d_cvirt + (int64_t)ik * vstride, d_aoscr,
+                                reinterpret_cast<double2 *>(dst) + (int64_t)(ik - k0) * per_k));
+        } else {
+          RPA_HIP(launch_philox_B(S, sys->philox_seed, sys->sigma, hs.nk, q, k0, k1, hs.nocc, hs.nvirt, N, cplx,
+                                  dst));
+        }
+        if (prof) RPA_TRY(ctx.prof_end(S));
+      } else {
+        RPA_HIP(hipMemcpyAsync(dst, (const char *)sys->B + off, (size_t)(rows * N * belem), hipMemcpyHostToDevice, S));
+      }
+      src = dst;
+    } else {
+      src = (const char *)sys->B + off;
+    }
+    if (mixed) {
+      if (prof) RPA_TRY(ctx.prof_begin(S, RPA_K_CHI0_AUX));
+      if (f16) {
+        // the slab's largest |Re|, |Im| and from it the left operand's scale
+        double *bp = d_bpart + f16_absmax_scratch_doubles(1) * s;
+        RPA_HIP(launch_absmax_blocks(S, (const double *)src, rows * N * (cplx ? 2 : 1), 0, 1, bp));
+        RPA_HIP(launch_f16_scales(S, bp, nullptr, nullptr, 1, d_lscale + s));
+      }
+      if (bsplit)
+        RPA_HIP(launch_bf16_prepare(S, src, cplx, rows, N, nullptr, 1,
+                                    (unsigned short *)((char *)d_B32 + (int64_t)s * b32_slot), nullptr, nullptr,
+                                    f16 ? d_lscale + s : nullptr, f16));
+      else
+        RPA_HIP(launch_to_f32(S, src, d_B32 + (int64_t)s * Mc * N, rows * N, cplx));
+      if (prof) RPA_TRY(ctx.prof_end(S));
+    }
+    return RPA_OK;
+  };
+
   // host copies of every batch's descriptors stay alive until the final synchronisation
   std::deque<std::vector<PointDesc>> keep_pts;
   std::deque<std::vector<int32_t>> keep_maps;
@@ -509,43 +600,11 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
       RPA_HIP(hipStreamSynchronize(st));
       if (nlanes == 2) RPA_HIP(hipStreamSynchronize(lane_st[1]));
     }
-    // stage B and V^(1/2) of the group's q's into slots
+    // stage B (whole q's; streamed q's chunk by chunk below) and V^(1/2) of the group's
+    // q's into slots
     for (int s = 0; s < ng; ++s) {
       const int q = qs[g0 + s];
-      if (!b_direct) {
-        char *dst = (char *)d_B + (int64_t)s * b_slot;
-        if (!sys->B) {
-          if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_PHILOX));
-          if (hs.nbas > 0) {
-            // the MO transform of the pair-fit coefficients, one k block at a time
-            const int64_t cstride = (int64_t)hs.nbas * hs.nocc, vstride = (int64_t)hs.nbas * hs.nvirt;
-            const int64_t per_k = (int64_t)hs.nocc * hs.nvirt * N;
-            for (int ik = 0; ik < hs.nk; ++ik)
-              RPA_HIP(launch_ao_B(st, sys->philox_seed, sys->sigma, hs.nk, q, ik, hs.nbas, hs.nocc, hs.nvirt, N,
-                                  d_cocc + (int64_t)hs.kq[(size_t)q * hs.nk + ik] * cstride,
-                                  d_cvirt + (int64_t)ik * vstride, d_aoscr,
-                                  reinterpret_cast<double2 *>(dst) + (int64_t)ik * per_k));
-          } else {
-            RPA_HIP(launch_philox_B(st, sys->philox_seed, sys->sigma, hs.nk, q, 0, hs.nk, hs.nocc,
-                                    hs.nvirt, N, cplx, dst));
-          }
-          if (prof) RPA_TRY(ctx.prof_end(st));
-        } else {
-          RPA_HIP(hipMemcpyAsync(dst, (const char *)sys->B + (int64_t)q * b_slot, (size_t)b_slot,
-                                 hipMemcpyHostToDevice, st));
-        }
-      }
-      if (mixed) {
-        const char *src = b_direct ? (const char *)sys->B + (int64_t)q * M * N * belem
-                                   : (const char *)d_B + (int64_t)s * b_slot;
-        if (prof) RPA_TRY(ctx.prof_begin(st, RPA_K_CHI0_AUX));
-        if (bsplit)
-          RPA_HIP(launch_bf16_prepare(st, src, cplx, M, N, nullptr, 1,
-                                      (unsigned short *)((char *)d_B32 + (int64_t)s * b32_slot)));
-        else
-          RPA_HIP(launch_to_f32(st, src, d_B32 + (int64_t)s * M * N, M * N, cplx));
-        if (prof) RPA_TRY(ctx.prof_end(st));
-      }
+      if (!streamed) RPA_TRY(stage_b(st, s, q, 0, hs.nk));
       if (vh_slot) {
         double2 *dst = (double2 *)((char *)d_vh + (int64_t)s * vh_slot);
         if (cplx) {
@@ -616,20 +675,36 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
       void *d_chi = lb.chi, *d_T = lb.T, *d_tscr = lb.tscr;
       PointDesc *d_pts = lb.pts;
 
+      // the contraction, once per chunk of the q's k-points (one chunk unless the q is
+      // streamed); chunk c > 0 goes to the first T plane and is added to chi0 in order
+      for (int c = 0; c < nchunks; ++c) {
+      const int k0 = c * kc, k1 = std::min(hs.nk, k0 + kc);
+      const int64_t rows = (int64_t)(k1 - k0) * nov;
+      if (streamed) RPA_TRY(stage_b(S, 0, hp[0].q, k0, k1));   // one q per group: slot 0
+      void *out_c = c == 0 ? d_chi : d_T;
+      // FP64 rows of this chunk that point i of the batch contracts
+      auto fp64_rows = [&](int i) -> const char * {
+        if (b_direct)
+          return (const char *)sys->B + ((int64_t)job.pq[(size_t)gp[b0 + i]] * M + (int64_t)k0 * nov) * N * belem;
+        return (const char *)d_B + (int64_t)hp[i].bslot * b_slot;
+      };
       Chi0Args ca{};
-      ca.B = b_direct ? sys->B : d_B;
-      ca.b_slot_stride = M * N;
+      // a caller's device B is read in place (the FP64 contraction by q, at the chunk's
+      // first row); staged slots, FP32 copies and prepared operands by slot
+      ca.B = b_direct ? (const void *)((const char *)sys->B + (int64_t)k0 * nov * N * belem) : d_B;
+      ca.b_slot_stride = (b_direct && !mixed) ? M * N : Mc * N;
       ca.eps_occ = d_eo;
       ca.eps_virt = d_ev;
       ca.kq = d_kq;
       ca.zeta_k = d_zk;
       ca.pts = d_pts;
       ca.wtab = d_w;
-      ca.out = (double2 *)d_chi;
+      ca.out = (double2 *)out_c;
       ca.out_stride = nn;
-      ca.nk = hs.nk; ca.nocc = hs.nocc; ca.nvirt = hs.nvirt; ca.N = N; ca.M = M;
+      ca.nk = hs.nk; ca.nocc = hs.nocc; ca.nvirt = hs.nvirt; ca.N = N; ca.M = rows;
+      ca.k0 = k0;
       ca.ksplit = 1;
-      ca.partial = (double2 *)d_T;
+      ca.partial = (double2 *)d_T + (c == 0 ? 0 : (int64_t)nb * nn);
       ca.pairs = lb.amap + 3 * nb;
       ca.npairs = npairs;
       int cfg = 1;   // FP64 tile configuration (the tuner's choice, made after the weights)
@@ -641,7 +716,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
       // until the sandwich.  RPA_CHI0_KSPLIT fixes the count (tests, timing).
       auto pick_split = [&](int64_t tn, int64_t slots, int64_t units, int max_split) {
         const int64_t T = (N + tn - 1) / tn;
-        int ks = chi0_pick_ksplit(T * (T + 1) / 2 * units * nlanes, slots, M, max_split);
+        int ks = chi0_pick_ksplit(T * (T + 1) / 2 * units * nlanes, slots, rows, max_split);
         if (const char *e = getenv("RPA_CHI0_KSPLIT")) {
           const int v = atoi(e);
           if (v >= 1) ks = std::min(v, max_split);
@@ -652,7 +727,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
       if (!mixed) {
         for (int c = 0; c < chi0_cfg_count() && c < 8; ++c)
           ks_of[c] = pick_split(chi0_cfg_tile(c), (int64_t)chi0_cfg_slots_per_cu(c) * ncu,
-                                chi0_cfg_points_per_wg(c) == 2 ? npairs : nb, tplanes + 1);
+                                chi0_cfg_points_per_wg(c) == 2 ? npairs : nb, max_split);
         RPA_TRY(tune_chi0_cfg(S, ca, nb, cplx, &cfg, ks_of));
       }
       int f32_tile = kF32T64;   // FP32 configuration (64- or 128-wide, or 64-wide paired)
@@ -662,9 +737,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
         while (i0 < nb) {
           int i1 = i0 + 1;
           while (i1 < nb && hp[i1].bslot == hp[i0].bslot) ++i1;
-          const int64_t slab = b_direct ? job.pq[(size_t)gp[b0 + i0]] : hp[i0].bslot;
-          const char *bsrc = (const char *)(b_direct ? sys->B : d_B) + slab * M * N * belem;
-          RPA_HIP(launch_diag_exact(S, bsrc, cplx, M, N, d_w + (int64_t)i0 * M, i1 - i0, d_dscr,
+          RPA_HIP(launch_diag_exact(S, fp64_rows(i0), cplx, rows, N, d_w + (int64_t)i0 * rows, i1 - i0, d_dscr,
                                     d_diag + (int64_t)i0 * N));
           i0 = i1;
         }
@@ -673,7 +746,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
         for (int c = 0; c < 3; ++c) {
           const int e = f32_cfg_edge(f32_cfgs[c]);
           f32_ks[c] = pick_split(e, (e == 128 ? 1LL : 2LL) * ncu, f32_cfg_points_per_wg(f32_cfgs[c]) == 2 ? npairs : nb,
-                                 tplanes + 1);
+                                 max_split);
         }
         RPA_TRY(tune_f32_tile(S, ca, nb, cplx, d_B32, d_diag, &f32_tile, f32_ks));
         ca.ksplit = f32_ks[f32_tile == kF32T128 ? 1 : f32_tile == kF32T64W2 ? 2 : 0];
@@ -689,15 +762,19 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
           // points on one B slab), then contract and reduce
           for (int r0 = 0; r0 < nb; r0 += (int)rbatch) {
             const int r1 = std::min<int>(nb, r0 + (int)rbatch);
+            if (f16) {
+              // each point's right-operand scale from its slab's maximum and its own
+              // largest weight
+              RPA_HIP(launch_absmax_blocks(S, d_w + (int64_t)r0 * rows, rows, rows, r1 - r0, lb.wpart));
+              RPA_HIP(launch_f16_scales(S, d_bpart, lb.wpart, d_pts + r0, r1 - r0, lb.rscale));
+            }
             int i0 = r0;
             while (i0 < r1) {
               int i1 = i0 + 1;
               while (i1 < r1 && hp[i1].bslot == hp[i0].bslot) ++i1;
-              const int64_t slab = b_direct ? job.pq[(size_t)gp[b0 + i0]] : hp[i0].bslot;
-              const char *bsrc = (const char *)(b_direct ? sys->B : d_B) + slab * M * N * belem;
-              RPA_HIP(launch_bf16_prepare(S, bsrc, cplx, M, N, d_w + (int64_t)i0 * M, i1 - i0,
+              RPA_HIP(launch_bf16_prepare(S, fp64_rows(i0), cplx, rows, N, d_w + (int64_t)i0 * rows, i1 - i0,
                                           d_R + (int64_t)(i0 - r0) * (prep_bytes / 2), d_dscr,
-                                          d_diag + (int64_t)i0 * N));
+                                          d_diag + (int64_t)i0 * N, f16 ? lb.rscale + (i0 - r0) : nullptr, f16));
               i0 = i1;
             }
             const int64_t max_part = bf16_partial_elems(rplan, (int)rbatch);
@@ -711,10 +788,11 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
               tg.pts = d_pts + r0;
               tg.part = d_part;
               tg.npts = r1 - r0;
-              RPA_TRY(tune_bf16_tile(S, tg, M, N, ncu, max_part, cplx, &bf16_tn));
+              tg.f16 = f16;
+              RPA_TRY(tune_bf16_tile(S, tg, rows, N, ncu, max_part, cplx, &bf16_tn));
             }
             Bf16Plan pl;
-            bf16_plan(M, N, r1 - r0, ncu, max_part, bf16_tn, &pl);
+            bf16_plan(rows, N, r1 - r0, ncu, max_part, bf16_tn, &pl);
             Bf16Group grp{};
             grp.L = (const unsigned short *)d_B32;
             grp.l_stride = prep_bytes / 2;
@@ -724,13 +802,15 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
             grp.part = d_part;
             grp.pl = pl;
             grp.npts = r1 - r0;
+            grp.f16 = f16;
             if (prof) RPA_TRY(ctx.prof_end(S));
             if (prof) RPA_TRY(ctx.prof_begin(S, RPA_K_CHI0));
             RPA_TRY(fused_herk(job.fuser, S, grp, cplx));
             if (prof) RPA_TRY(ctx.prof_end(S));
             if (prof) RPA_TRY(ctx.prof_begin(S, RPA_K_CHI0_AUX));
             RPA_HIP(launch_bf16_reduce(S, pl, d_part, r1 - r0, N, d_diag + (int64_t)r0 * N,
-                                       (double2 *)d_chi + (int64_t)r0 * nn, nn));
+                                       (double2 *)out_c + (int64_t)r0 * nn, nn, d_pts + r0,
+                                       f16 ? d_lscale : nullptr, f16 ? lb.rscale : nullptr));
             if (prof) RPA_TRY(ctx.prof_end(S));
             if (prof && r1 < nb) RPA_TRY(ctx.prof_begin(S, RPA_K_CHI0_AUX));
           }
@@ -745,6 +825,12 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
         RPA_HIP(launch_chi0_f64(S, ca, nb, cplx, cfg));
       }
       if (prof && !bsplit) RPA_TRY(ctx.prof_end(S));
+      if (c > 0) {
+        if (prof) RPA_TRY(ctx.prof_begin(S, RPA_K_OTHER));
+        RPA_HIP(launch_split_add(S, (const double2 *)d_T, 1, (int64_t)nb * nn, (double2 *)d_chi));
+        if (prof) RPA_TRY(ctx.prof_end(S));
+      }
+      }
 
       const double2 *vh = vh_direct ? (const double2 *)sys->vhalf : (const double2 *)d_vh;
       GemmArgs g1{};   // T = chi0 V^(1/2)

@@ -51,16 +51,17 @@ Scheduler::Scheduler(Ctx &c) : ctx_(c) {}
 
 Scheduler::~Scheduler() { shutdown(); }
 
-int64_t Scheduler::footprint(const HostSmall &hs, int nw, rpa_precision prec) {
+int64_t Scheduler::footprint(const HostSmall &hs, int nw, rpa_precision prec, int kc) {
   const bool mixed = prec != RPA_FP64;
   const int64_t N = hs.naux;
-  const int64_t M = (int64_t)hs.nk * hs.nocc * hs.nvirt;
+  // rows of one B slot: a whole q, or a chunk of kc k-points of a streamed q
+  const int64_t M = (int64_t)(kc > 0 && kc < hs.nk ? kc : hs.nk) * hs.nocc * hs.nvirt;
   const int64_t belem = hs.is_complex ? 16 : 8;
-  const bool bsplit = prec == RPA_BF16X3;
+  const bool bsplit = prec == RPA_BF16X3 || prec == RPA_F16X3;
   const int64_t small = (int64_t)(hs.eps_occ.size() + hs.eps_virt.size() + hs.zeta_k.size()) * 8 +
                         (int64_t)hs.kq.size() * 4 + (int64_t)hs.nq * nw * 32 + 4096 +
                         (int64_t)(hs.nq + nw + 1) * 8 +
-                        (prec == RPA_BF16X3 ? bf16_diag_scratch_doubles(M, (int)N) * 8
+                        (bsplit ? bf16_diag_scratch_doubles(M, (int)N) * 8
                          : mixed ? diag_exact_scratch_doubles(M, (int)N, 16) * 8 : 0) +
                         (hs.nbas > 0 ? (int64_t)(hs.c_occ.size() + hs.c_virt.size()) * 8 + 512 +
                                            ao_scratch_bytes(hs.nbas, hs.nocc, hs.naux)
@@ -68,7 +69,8 @@ int64_t Scheduler::footprint(const HostSmall &hs, int nw, rpa_precision prec) {
   // one q staged at a time: FP64 B (and its FP32 copy, or its prepared split-BF16 copy),
   // V^(1/2), and per point chi0, T, the weight table and the exact diagonal -- the same
   // sizes run_points() budgets
-  const int64_t prep = bsplit ? bf16_prepared_elems(M, (int)N) * 2 : 0;
+  // (the fp16 operands' scales and maxima: a few KB per slot and per point)
+  const int64_t prep = bsplit ? bf16_prepared_elems(M, (int)N) * 2 + (f16_absmax_scratch_doubles(1) + 1) * 8 : 0;
   const int64_t per_q = M * N * belem + N * N * 16 + (hs.is_complex ? 0 : N * N * 8) +
                         (bsplit ? prep : mixed ? M * N * 8 : 0);
   const int64_t per_pt = 2 * N * N * 16 + M * 8 + (mixed ? N * 8 : 0) + trln_blocked_scratch_bytes(1) + 64;
@@ -96,7 +98,7 @@ void Scheduler::start_locked() {
 
 int Scheduler::submit(const rpa_system *sys, const rpa_freq *freq, rpa_precision prec, uint64_t *id) {
   if (!id) return fail(RPA_E_ARG, "job_id pointer is NULL");
-  if (prec != RPA_FP64 && prec != RPA_FP32 && prec != RPA_BF16X3)
+  if (prec != RPA_FP64 && prec != RPA_FP32 && prec != RPA_BF16X3 && prec != RPA_F16X3)
     return fail(RPA_E_ARG, "unknown precision %d", (int)prec);
   RPA_HIP(hipSetDevice(ctx_.device));
   std::unique_ptr<Job> j(new Job());
@@ -108,7 +110,9 @@ int Scheduler::submit(const rpa_system *sys, const rpa_freq *freq, rpa_precision
   const int64_t N = hs.naux;
   const int64_t M = (int64_t)hs.nk * hs.nocc * hs.nvirt;
   const int64_t belem = hs.is_complex ? 16 : 8;
-  j->need = footprint(hs, freq->nw, prec);
+  j->need = footprint(hs, freq->nw, prec, hs.nk);
+  // a job whose whole q does not fit the limit streams its q's one k-point at a time
+  if (j->need > ctx_.hbm_limit) j->need = footprint(hs, freq->nw, prec, 1);
   if (j->need > ctx_.hbm_limit)
     return fail(RPA_E_NOMEM, "job needs %lld device bytes, above the limit %lld", (long long)j->need,
                 (long long)ctx_.hbm_limit);
@@ -211,7 +215,7 @@ void Scheduler::worker(int w) {
       pj.weight = j->weight;
       pj.max_q_group = 1;
       pj.fuser = fuser_;
-      const bool fusing = j->prec == RPA_BF16X3;
+      const bool fusing = j->prec == RPA_BF16X3 || j->prec == RPA_F16X3;
       if (fusing) fuser_register(fuser_, +1);
       rc = run_points(ctx_, st, pj, j->need, false);
       if (fusing) fuser_register(fuser_, -1);

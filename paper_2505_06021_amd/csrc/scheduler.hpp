@@ -24,8 +24,9 @@ class Scheduler {
   void fill_stats(rpa_stats *out);
   void shutdown();
 
-  // Device bytes a job of this shape holds while it runs (one q at a time).
-  static int64_t footprint(const HostSmall &hs, int nw, rpa_precision prec);
+  // Device bytes a job of this shape holds while it runs (one q at a time, its B slot
+  // holding kc k-points: all of them, or a chunk of a streamed q).
+  static int64_t footprint(const HostSmall &hs, int nw, rpa_precision prec, int kc);
 
  private:
   struct Job;

@@ -1,5 +1,5 @@
 // Batched complex FP64 GEMM on the matrix cores for Pi = V^(1/2) chi0 V^(1/2)
-// (Algorithm 1, "Z = V^0.5 P V^0.5"): two launches, T = chi0 V^(1/2) and
+// (Algorithm 1, the sandwich step): two launches, T = chi0 V^(1/2) and
 // Pi = V^(1/2) T, the second restricted to tiles on or below the diagonal because
 // only the lower triangle of the Hermitian Pi feeds the Cholesky factorisation and
 // the trace.

@@ -15,7 +15,7 @@ import numpy as np
 RPA_OK, RPA_PENDING = 0, 1
 RPA_E_ARG, RPA_E_NOMEM, RPA_E_DEVICE, RPA_E_NOTSPD = -1, -2, -3, -4
 RPA_E_UNKNOWN_JOB, RPA_E_INTERNAL, RPA_E_CANCELLED = -5, -6, -7
-FP64, FP32, BF16X3 = 0, 1, 2
+FP64, FP32, BF16X3, F16X3 = 0, 1, 2, 3
 MEM_HOST, MEM_DEVICE = 0, 1
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librpa.so")

@@ -13,8 +13,8 @@ from oracle import rpa_oracle as orc
 from paper_2505_06021_amd import inputs
 
 pytestmark = pytest.mark.gpu
-FP32, BF16X3 = 1, 2
-TOL_E = {FP32: 1e-6, BF16X3: 2e-5}
+FP32, BF16X3, F16X3 = 1, 2, 3
+TOL_E = {FP32: 1e-6, BF16X3: 2e-5, F16X3: 1e-6}
 
 
 def say(msg):
@@ -53,7 +53,7 @@ def test_ao_energy_fp64_matches_oracle(ctx):
     assert np.all(np.abs(eps - g_ref) <= 1e-10 * scale)
 
 
-@pytest.mark.parametrize("prec", [FP32, BF16X3])
+@pytest.mark.parametrize("prec", [FP32, BF16X3, F16X3])
 def test_ao_energy_mixed(ctx, prec):
     s = ao()
     say(f"ao energy prec={prec}")

@@ -12,8 +12,8 @@ from oracle import rpa_oracle as orc
 from paper_2505_06021_amd import inputs
 
 pytestmark = pytest.mark.gpu
-FP32, BF16X3 = 1, 2
-TOL_E = {FP32: 1e-6, BF16X3: 2e-5}
+FP32, BF16X3, F16X3 = 1, 2, 3
+TOL_E = {FP32: 1e-6, BF16X3: 2e-5, F16X3: 1e-6}
 
 
 def say(msg):
@@ -57,7 +57,7 @@ def test_dual_chi0_matches_oracle(ctx, iq):
     assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("prec", [FP32, BF16X3])
+@pytest.mark.parametrize("prec", [FP32, BF16X3, F16X3])
 def test_dual_energy_mixed(ctx, prec):
     s = dual()
     say(f"dual-grid energy prec={prec}")

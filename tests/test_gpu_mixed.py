@@ -1,12 +1,16 @@
-"""Reduced-precision chi0 (FP32 and split-BF16 MFMA with FP64 flush and exact FP64
-diagonal) against the FP64 oracle and the FP64 GPU path.
+"""Reduced-precision chi0 (FP32, split-BF16 and split-FP16 MFMA with FP64 sums of the
+row splits and an exact FP64 diagonal) against the FP64 oracle and the FP64 GPU path.
 
 Stated tolerances (measured margins are recorded in the test output):
   chi0 FP32      ||d chi0||_F <= 1e-6 ||chi0||_F,  diagonal to 1e-13
+  chi0 F16X3     ||d chi0||_F <= 1e-6 ||chi0||_F,  diagonal to 1e-13
   chi0 BF16X3    ||d chi0||_F <= 1e-4 ||chi0||_F,  diagonal to 1e-13
   energy FP32    |E - E_FP64| <= 1e-6 Ha per cell
+  energy F16X3   |E - E_FP64| <= 1e-6 Ha per cell
   energy BF16X3  |E - E_FP64| <= 2e-5 Ha per cell on the small test systems, and <= 1e-6 Ha
-                 per cell on the 3x3x1 N_aux 384 slab of the benchmark (measured 3.4e-7)
+                 per cell on the 3x3x1 N_aux 384 slab of the benchmark (measured 3.4e-7): the
+                 two bf16 terms keep about 16 bits of each operand, which is not enough for
+                 1e-6 Ha on every system
 """
 import json
 import os
@@ -20,9 +24,9 @@ from paper_2505_06021_amd import inputs
 
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-FP32, BF16X3 = 1, 2
-TOL_CHI0 = {FP32: 1e-6, BF16X3: 1e-4}
-TOL_E = {FP32: 1e-6, BF16X3: 2e-5}
+FP32, BF16X3, F16X3 = 1, 2, 3
+TOL_CHI0 = {FP32: 1e-6, BF16X3: 1e-4, F16X3: 1e-6}
+TOL_E = {FP32: 1e-6, BF16X3: 2e-5, F16X3: 1e-6}
 
 
 def say(msg):
@@ -41,7 +45,7 @@ def ragged(nw=4):
     return inputs.make_system("ragged", (2, 2, 1), 3, 7, 150, nw, 31, is_complex=True, sigma=0.15)
 
 
-@pytest.mark.parametrize("prec", [FP32, BF16X3])
+@pytest.mark.parametrize("prec", [FP32, BF16X3, F16X3])
 def test_chi0_mixed_against_oracle(ctx, prec):
     for name, s, pts in [("ragged", ragged(), [(0, 0.0), (3, 0.77)]),
                          ("slab384", inputs.slab_3x3_384(), [(4, 0.3)])]:
@@ -58,7 +62,7 @@ def test_chi0_mixed_against_oracle(ctx, prec):
             assert np.abs(got - got.conj().T).max() == 0.0
 
 
-@pytest.mark.parametrize("prec", [FP32, BF16X3])
+@pytest.mark.parametrize("prec", [FP32, BF16X3, F16X3])
 def test_chi0_mixed_real_system(ctx, prec):
     say(f"chi0 real prec={prec}")
     s = inputs.gamma_real_128().materialize_B()
@@ -67,7 +71,7 @@ def test_chi0_mixed_real_system(ctx, prec):
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= TOL_CHI0[prec]
 
 
-@pytest.mark.parametrize("prec", [FP32, BF16X3])
+@pytest.mark.parametrize("prec", [FP32, BF16X3, F16X3])
 def test_energy_mixed_slab384(ctx, prec):
     say(f"energy slab384 prec={prec}")
     g = json.load(open(os.path.join(GOLD, "slab3x3_naux384.json")))
@@ -80,7 +84,7 @@ def test_energy_mixed_slab384(ctx, prec):
     assert abs(E - g["E"]) <= 1e-6 + 1e-10 * abs(g["E"])
 
 
-@pytest.mark.parametrize("prec", [FP32, BF16X3])
+@pytest.mark.parametrize("prec", [FP32, BF16X3, F16X3])
 def test_energy_mixed_ragged_and_gamma(ctx, prec):
     for s in (ragged(6), inputs.gamma_real_128()):
         say(f"energy {s.name} prec={prec}")
@@ -90,64 +94,85 @@ def test_energy_mixed_ragged_and_gamma(ctx, prec):
         assert abs(E - E64) <= TOL_E[prec]
 
 
-def test_mixed_is_deterministic(ctx):
-    say("mixed determinism")
+@pytest.mark.parametrize("prec", [BF16X3, F16X3])
+def test_mixed_is_deterministic(ctx, prec):
+    say(f"mixed determinism prec={prec}")
     s = ragged(3)
-    a = ctx.energy(s, prec=BF16X3)
-    b = ctx.energy(s, prec=BF16X3)
+    a = ctx.energy(s, prec=prec)
+    b = ctx.energy(s, prec=prec)
     assert a[0] == b[0] and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("scale", [1e-30, 1e-3, 1e25])
+def test_chi0_f16x3_operand_scaling(ctx, scale):
+    # fp16 alone spans about 6e-8 .. 6.5e4: the power-of-two operand scales keep the
+    # relative error whatever the magnitude of B (chi0 scales with scale^2)
+    from paper_2505_06021_amd import rpa  # noqa: F401
+    s = ragged(2).materialize_B()
+    s.B = s.B * scale
+    ref = orc.chi0(s, 1, 0.4)
+    say(f"chi0 f16x3 with B scaled by {scale:g}")
+    got = ctx.chi0(s, 1, 0.4, prec=F16X3)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    say(f"  rel Frobenius error {err:.3e}")
+    assert np.all(np.isfinite(got))
+    assert err <= TOL_CHI0[F16X3]
 
 
 # ------------------------------------------------ split-BF16 from prepared operands
 
+@pytest.mark.parametrize("prec", [BF16X3, F16X3])
 @pytest.mark.parametrize("tile", ["64", "128"])
 @pytest.mark.parametrize("naux,nocc,nvirt", [(1, 2, 5), (127, 3, 7), (128, 4, 9), (129, 3, 7), (256, 8, 150)])
-def test_chi0_bf16x3_tile_and_split_edges(ctx, monkeypatch, naux, nocc, nvirt, tile):
+def test_chi0_split16_tile_and_split_edges(ctx, monkeypatch, naux, nocc, nvirt, tile, prec):
     # 64- and 128-wide output tiles and 32-row steps with ragged tails; (8, 150) on a
     # 2x2x1 grid gives M = 4800 rows, more than one 4096-row split
     monkeypatch.setenv("RPA_BF16_TILE", tile)
     s = inputs.make_system(f"edge{naux}", (2, 2, 1), nocc, nvirt, naux, 2, 77 + naux, is_complex=True)
     ref = orc.chi0(s, 2, s.omega[1])
-    say(f"chi0 bf16x3 tile {tile} N={naux} M={4 * nocc * nvirt}")
-    got = ctx.chi0(s, 2, s.omega[1], prec=BF16X3)
+    say(f"chi0 prec={prec} tile {tile} N={naux} M={4 * nocc * nvirt}")
+    got = ctx.chi0(s, 2, s.omega[1], prec=prec)
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     say(f"  rel Frobenius error {err:.3e}")
-    assert err <= TOL_CHI0[BF16X3]
+    assert err <= TOL_CHI0[prec]
     d_ref = np.real(np.diagonal(ref))
     assert np.max(np.abs(np.real(np.diagonal(got)) - d_ref) / np.abs(d_ref)) <= 1e-13
     assert np.abs(got - got.conj().T).max() == 0.0
 
 
-def test_energy_bf16x3_device_inputs_bitwise(ctx):
-    say("energy bf16x3 device inputs")
+@pytest.mark.parametrize("prec", [BF16X3, F16X3])
+def test_energy_split16_device_inputs_bitwise(ctx, prec):
+    say(f"energy prec={prec} device inputs")
     s = ragged(3)
-    a = ctx.energy(s, prec=BF16X3, device=False)
-    b = ctx.energy(s, prec=BF16X3, device=True)
+    a = ctx.energy(s, prec=prec, device=False)
+    b = ctx.energy(s, prec=prec, device=True)
     assert a[0] == b[0] and np.array_equal(a[1], b[1])
 
 
-def test_energy_bf16x3_sub_launches_under_hbm_limit():
+@pytest.mark.parametrize("prec", [BF16X3, F16X3])
+def test_energy_split16_sub_launches_under_hbm_limit(prec):
     # a 600 MB limit leaves room for the prepared right operands of only a few points
     # at a time, so each batch runs as several contraction launches
     from paper_2505_06021_amd import rpa
     s = inputs.slab_3x3_384()
     with rpa.Context(0) as free:
-        E0, eps0 = free.energy(s, prec=BF16X3)
-    say("energy bf16x3 under a 600 MB limit")
+        E0, eps0 = free.energy(s, prec=prec)
+    say(f"energy prec={prec} under a 600 MB limit")
     with rpa.Context(0, hbm_limit=600 * 2 ** 20) as tight:
-        E1, eps1 = tight.energy(s, prec=BF16X3)
+        E1, eps1 = tight.energy(s, prec=prec)
     say(f"  E free {E0:.12f} E tight {E1:.12f}")
-    assert abs(E1 - E0) <= TOL_E[BF16X3]
+    assert abs(E1 - E0) <= TOL_E[prec]
     assert np.max(np.abs(eps1 - eps0)) <= 1e-6 * np.max(np.abs(eps0))
 
 
-def test_bf16x3_tile_edges_agree_bitwise_with_one_split(ctx, monkeypatch):
+@pytest.mark.parametrize("prec", [BF16X3, F16X3])
+def test_split16_tile_edges_agree_bitwise_with_one_split(ctx, monkeypatch, prec):
     # with one row split both tile edges issue the same MFMA sequence for every element
     s = inputs.make_system("tiles", (2, 2, 1), 3, 7, 200, 3, 5, is_complex=True)   # M = 84
     got = {}
     for tile in ("64", "128"):
         monkeypatch.setenv("RPA_BF16_TILE", tile)
-        got[tile] = ctx.energy(s, prec=BF16X3)
+        got[tile] = ctx.energy(s, prec=prec)
     assert got["64"][0] == got["128"][0] and np.array_equal(got["64"][1], got["128"][1])
 
 

@@ -2,9 +2,10 @@
 
 Each HBM-traffic record under profiles/ carries a hash of its kernel source's code
 (comments and blank lines left out); bench.py reports that record's traffic only while
-the hash matches.  Each rocprofv3 summary names the command that made it, and that
-command runs committed files only.
+the hash matches, and null once the kernel has changed.  Each rocprofv3 summary names the
+command that made it, and that command runs committed files only.
 """
+import glob
 import json
 import os
 import sys
@@ -16,26 +17,48 @@ sys.path.insert(0, ROOT)
 
 import bench  # noqa: E402
 
-PRECS = ("fp64", "fp32", "bf16x3")
+SRC = {"fp64": "chi0_f64.hip", "fp32": "chi0_mixed.hip", "bf16x3": "chi0_bf16.hip", "f16x3": "chi0_bf16.hip"}
+RECORDS = sorted(glob.glob(os.path.join(ROOT, "profiles", "chi0_*_traffic.json")))
+SUMMARIES = sorted(glob.glob(os.path.join(ROOT, "profiles", "chi0_*.txt")))
 
 
-@pytest.mark.parametrize("prec", PRECS)
-def test_traffic_record_matches_kernel_source(prec):
-    path = os.path.join(ROOT, "profiles", f"chi0_{prec}_slab3x3_naux384_traffic.json")
+def parse(path):
+    name = os.path.basename(path)[len("chi0_"):]
+    prec, workload = name.split("_", 1)
+    return prec, workload.replace("_traffic.json", "").replace(".txt", "")
+
+
+@pytest.mark.parametrize("path", RECORDS, ids=[os.path.basename(p) for p in RECORDS])
+def test_traffic_record_is_reported_only_for_its_kernel(path):
     rec = json.load(open(path))
-    src = {"fp64": "chi0_f64.hip", "fp32": "chi0_mixed.hip", "bf16x3": "chi0_bf16.hip"}[prec]
-    assert rec["kernel_source_sha256_16"] == bench.kernel_source_hash(src)
-    t = bench.traffic_from_profiles("slab3x3_naux384", prec)
-    assert t is not None and t >= rec["algorithmic_bytes_per_launch"]
-    assert all("rocprofv3 --pmc" in c and "_work" not in c for c in rec["commands"])
+    prec, workload = parse(path)
+    t = bench.traffic_from_profiles(workload, prec)
+    if rec["kernel_source_sha256_16"] == bench.kernel_source_hash(SRC[prec]):
+        assert t is not None and t >= rec["algorithmic_bytes_per_launch"]
+    else:
+        assert t is None
+    assert all("rocprofv3 --pmc" in c and "_work" not in c and "bench.py" in c for c in rec["commands"])
 
 
-@pytest.mark.parametrize("prec", PRECS)
-def test_kernel_trace_summary_names_its_command(prec):
-    text = open(os.path.join(ROOT, "profiles", f"chi0_{prec}_slab3x3_naux384.txt")).read()
+def test_default_workload_has_current_records():
+    # the bench's default line (3x3x1, N_aux 2400, FP64) has a kernel trace summary and a
+    # traffic record taken with the committed contraction kernel
+    assert os.path.exists(os.path.join(ROOT, "profiles", "chi0_fp64_slab3x3_naux2400.txt"))
+    assert bench.traffic_from_profiles("slab3x3_naux2400", "fp64") is not None
+
+
+@pytest.mark.parametrize("path", SUMMARIES, ids=[os.path.basename(p) for p in SUMMARIES])
+def test_kernel_trace_summary_names_its_command(path):
+    text = open(path).read()
+    prec, workload = parse(path)
     cmd = [ln for ln in text.splitlines() if "rocprofv3 --kernel-trace --stats" in ln]
     assert cmd and "bench.py" in cmd[0] and "_work" not in cmd[0]
-    assert "chi0" in text and "AverageNs" in text
+    # the command reproduces the summary's workload and precision
+    if workload != "slab3x3_naux2400":
+        assert f"--workload {workload}" in cmd[0]
+    if prec != "fp64":
+        assert f"--prec {prec}" in cmd[0]
+    assert "AverageNs" in text
 
 
 def test_code_hash_ignores_comments_only():
