@@ -314,6 +314,9 @@ def main():
     ap.add_argument("--steps", type=int, default=18)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="slab3x3_naux2400", choices=sorted(WORKLOADS))
+    ap.add_argument("--step", default="q", choices=["q", "energy"],
+                    help="one step = one q-point and its frequencies (default), or one full rpa_energy "
+                         "call over every point of the workload")
     ap.add_argument("--mixed", default="fp32,bf16x3,f16x3",
                     help="reduced-precision contractions timed beside an FP64 run ('none' to skip)")
     ap.add_argument("--prec", default="fp64", choices=sorted(PREC_CODE))
@@ -359,27 +362,37 @@ def main():
     ctx = rpa.Context(0)
     m = rpa._Marshal(s, device=not args.host_inputs)   # inputs resident in HBM before timing
     prec = PREC_CODE[args.prec]
-    npts = s.nw                                          # points per step: one q, every w
+    npts = s.nw if args.step == "q" else s.nq * s.nw      # points per step
     print(f"[bench] {args.workload} prec={args.prec} points/step={npts} (one q) nq={s.nq} "
           f"warmup={args.warmup} steps={args.steps} (inputs {time.perf_counter() - t_in:.1f} s)",
           file=sys.stderr, flush=True)
-    run_steps(ctx, s, m, prec, args.warmup, label="warmup")
+    if args.step == "q":
+        run_steps(ctx, s, m, prec, args.warmup, label="warmup")
+    else:
+        for i in range(args.warmup):
+            E_w, _ = ctx.energy(s, prec=prec, marshal=m)
+            print(f"[bench] warmup {i} E={E_w:.12f}", file=sys.stderr, flush=True)
     ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     eps_by_q = {}
+    E_energy = None
     for i in range(args.steps):
-        q = i % s.nq
-        eps_by_q[q] = np.asarray(ctx.points(s, [q] * s.nw, s.omega, prec=prec, marshal=m))
+        if args.step == "q":
+            q = i % s.nq
+            eps_by_q[q] = np.asarray(ctx.points(s, [q] * s.nw, s.omega, prec=prec, marshal=m))
+        else:
+            E_energy, grid = ctx.energy(s, prec=prec, marshal=m)
+            eps_by_q = {q: grid[q] for q in range(s.nq)}
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kt = ctx.profile_read()
     ctx.profile(False)
     ms_step = (t1 - t0) * 1e3 / args.steps
     print(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
-    roof = chi0_roofline(s, kt, args.steps, args.prec)
+    roof = chi0_roofline(s, kt, args.steps * npts // s.nw, args.prec)
     roof["traffic"] = traffic_from_profiles(args.workload, args.prec)
-    E = energy_of(s, eps_by_q)
+    E = energy_of(s, eps_by_q) if E_energy is None else E_energy
     check = {"E": E, "q_visited": sorted(eps_by_q)}
     gold = os.path.join(ROOT, "tests", "golden", f"{args.workload}.json")
     if E is not None and os.path.exists(gold):
@@ -446,7 +459,8 @@ def main():
         "config": {"workload": args.workload, "grid": list(s.grid), "nk": s.nk, "nq": s.nq, "nk_occ": s.nk_occ, "nbas": s.nbas,
                    "nocc": s.nocc, "nvirt": s.nvirt, "naux": s.naux, "nw": s.nw,
                    "is_complex": s.is_complex, "chi0_precision": args.prec,
-                   "step": "one q-point: B(q) generation and all of its frequencies",
+                   "step": ("one q-point: B(q) generation and all of its frequencies" if args.step == "q" else
+                            "one RPA energy: every (q, w) point and the quadrature"),
                    "B": "Philox4x32-10 on device", "parallelism": "single GPU",
                    "chi0_tile_config": tiles[args.prec]},
         "roofline": roof,

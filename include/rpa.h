@@ -87,8 +87,14 @@ typedef struct rpa_ctx rpa_ctx;
  *            the pair-fit coefficients C^{mu nu}_P drawn from Philox stream 1 of B's key
  *            (philox_seed, sigma; element e = (mu * nbas + nu) * naux + P).  Requires
  *            is_complex = 1 and B = NULL.
- *  c_occ     [nk_occ][nbas][nocc], c_virt [nk][nbas][nvirt]: KS coefficients (complex)
- *            after the periodic projector of Sec. 2.3 (T(k) c, applied by the caller).
+ *  c_occ     [nk_occ][nbas][nocc], c_virt [nk][nbas][nvirt]: KS coefficients (complex):
+ *            already projected (T(k) c of Sec. 2.3) when S_ao is NULL, else raw.
+ *  S_ao      NULL, or [nk][nbas][nbas] (complex, Hermitian): the overlaps S(k) of the basis;
+ *            the library then applies the periodic projector of Sec. 2.3 on the device,
+ *            c~(k) = T(k) c(k) with T(k) = U(k) R~ U(k)^H from S(k) = U D U^H, keeping the
+ *            eigen-directions whose eigenvalue (ascending order) is >= eps_d at every k.
+ *            Regular grids only (nk_occ = nk), nbas <= 1024.
+ *  eps_d     the projector's threshold (used when S_ao != NULL).
  *  zeta_k    [nk], zeta_q [nq]: integration weights; NULL means 1/nk and 1/nq.
  *  B         [nq][nk][nocc][nvirt][naux]: fit coefficients B^P_ia(k,q), P fastest: the
  *            complex conjugates of the MO-basis PADF coefficients C^{ai}_P(k+q,k) of
@@ -114,6 +120,8 @@ typedef struct {
   int32_t nbas;
   const void *c_occ;
   const void *c_virt;
+  const void *S_ao;
+  double eps_d;
 } rpa_system;
 
 /* Imaginary-frequency quadrature (host memory): nodes omega_j and weights W_j that
@@ -137,8 +145,9 @@ typedef struct {
 typedef struct {
   int64_t hbm_limit, hbm_in_use, hbm_high_water;
   int64_t jobs_submitted, jobs_done, jobs_running, jobs_queued;
-  /* split-BF16 contractions of served jobs: fused launches, the job sub-batches they
-   * carried, and sub-batches large enough to be launched alone */
+  /* contractions of served jobs (split 16-bit, paired FP64, paired FP32): fused launches,
+   * the job sub-batches they carried, and sub-batches launched alone (large enough to fill
+   * the GPU, or of a configuration that is not fused) */
   int64_t fused_launches, fused_groups, solo_groups;
 } rpa_stats;
 
@@ -214,6 +223,15 @@ int rpa_energy(rpa_ctx *ctx, const rpa_system *sys, const rpa_freq *freq,
 int rpa_points(rpa_ctx *ctx, const rpa_system *sys, int32_t npts, const int32_t *iq,
                const double *w, rpa_precision prec, double *eps);
 
+/* The periodic projector of Sec. 2.3: T [nk][nbas][nbas] (complex) from the overlaps
+ * S [nk][nbas][nbas] (complex, Hermitian) and the threshold eps_d, both arrays in
+ * `memspace`: S(k) = U D U^H (Jacobi eigendecomposition on the device, FP64), the
+ * eigen-directions sorted by ascending eigenvalue, an index kept only if its eigenvalue is
+ * >= eps_d at every k, T(k) = U R~ U^H.  Errors: RPA_E_ARG (sizes, nbas > 1024),
+ * RPA_E_NOMEM, RPA_E_DEVICE. */
+int rpa_projector(rpa_ctx *ctx, int32_t nk, int32_t nbas, double eps_d, int32_t memspace, const void *S,
+                  void *T);
+
 /* Device Philox generator of the fit coefficients of block (q = iq, k = ik):
  * out [nocc][nvirt][naux] in `memspace`.  Stream: Philox4x32-10 (Salmon et al., SC'11)
  * with key (seed mod 2^32, (seed >> 32) + iq*nk + ik mod 2^32) and counter
@@ -239,7 +257,7 @@ int rpa_philox_words(rpa_ctx *ctx, uint64_t seed, int32_t nk, int32_t iq, int32_
  * RPA_PENDING, or the job's final status with *out filled and, if eps_qw != NULL,
  * its [nq][nw] integrand; a finished job is consumed by the successful poll.
  * Environment: RPA_SERVE_WORKERS (concurrent jobs, 1..16, default 4) and RPA_FUSE_WINDOW_US
- * (how long the fuser waits for other jobs' small split-BF16 launches, default 300).
+ * (how long the fuser waits for other jobs' small contraction launches, default 300).
  * Errors: RPA_E_ARG, RPA_E_NOMEM, RPA_E_UNKNOWN_JOB, or the job's own error. */
 int rpa_submit(rpa_ctx *ctx, const rpa_system *sys, const rpa_freq *freq,
                rpa_precision prec, uint64_t *job_id);

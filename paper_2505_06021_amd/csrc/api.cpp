@@ -154,8 +154,9 @@ int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega, rpa_
       RPA_TRY(c.workspace("ao_scratch", ao_scratch_bytes(hs.nbas, hs.nocc, N), &scr));
       double2 *co = reinterpret_cast<double2 *>(cbuf);
       double2 *cv = co + hs.c_occ.size() / 2;
-      RPA_HIP(hipMemcpyAsync(co, hs.c_occ.data(), hs.c_occ.size() * 8, hipMemcpyHostToDevice, c.stream));
-      RPA_HIP(hipMemcpyAsync(cv, hs.c_virt.data(), hs.c_virt.size() * 8, hipMemcpyHostToDevice, c.stream));
+      void *pstage;
+      RPA_TRY(c.workspace("ao_stage", ao_stage_scratch_bytes(hs), &pstage));
+      RPA_TRY(stage_ao_coefficients(c.stream, hs, co, cv, pstage));
       const int64_t per_k = (int64_t)hs.nocc * hs.nvirt * N;
       for (int ik = 0; ik < hs.nk; ++ik)
         RPA_HIP(launch_ao_B(c.stream, sys->philox_seed, sys->sigma, hs.nk, iq, ik, hs.nbas, hs.nocc, hs.nvirt, N,
@@ -427,6 +428,28 @@ int rpa_points(rpa_ctx *ctx, const rpa_system *sys, int32_t npts, const int32_t 
   job.pw.assign(w, w + npts);
   RPA_TRY(run_points(c, c.stream, job, budget_of(c), true));
   memcpy(eps, job.eps.data(), (size_t)npts * 8);
+  return RPA_OK;
+}
+
+int rpa_projector(rpa_ctx *ctx, int32_t nk, int32_t nbas, double eps_d, int32_t memspace, const void *S,
+                  void *T) {
+  RPA_TRY(check_ctx(ctx));
+  Ctx &c = ctx->c;
+  std::lock_guard<std::mutex> g(c.mu);
+  RPA_TRY(set_device(c));
+  if (nk < 1 || nk > 65535 || nbas < 1 || nbas > 1024) return fail(RPA_E_ARG, "nk %d or nbas %d out of range", nk, nbas);
+  if (!(eps_d >= 0.0) || !std::isfinite(eps_d)) return fail(RPA_E_ARG, "eps_d must be finite and >= 0");
+  if (memspace != RPA_MEM_HOST && memspace != RPA_MEM_DEVICE) return fail(RPA_E_ARG, "bad memspace");
+  if (!S || !T) return fail(RPA_E_ARG, "NULL array");
+  const int64_t bytes = (int64_t)nk * nbas * nbas * 16;
+  void *ds, *dt, *scr;
+  RPA_TRY(c.workspace("proj_S", bytes, &ds));
+  RPA_TRY(c.workspace("proj_T", bytes, &dt));
+  RPA_TRY(c.workspace("proj_scratch", projector_scratch_bytes(nk, nbas), &scr));
+  RPA_TRY(to_device(ds, S, (size_t)bytes, memspace, c.stream));
+  RPA_HIP(launch_projector(c.stream, (const double2 *)ds, nk, nbas, eps_d, scr, (double2 *)dt));
+  RPA_TRY(from_device(T, dt, (size_t)bytes, memspace, c.stream));
+  RPA_HIP(hipStreamSynchronize(c.stream));
   return RPA_OK;
 }
 

@@ -357,18 +357,43 @@ __device__ __forceinline__ void contract_diag5(const double2 (*la)[LDP], const d
 // -1 leaves the pair single).
 // In diagonal tiles waves 0 and 1 take point 0's ten lower blocks, five each, and waves
 // 2 and 3 point 1's, so the busiest wave issues 5/8 of an off-diagonal tile's products.
+// A launch of the paired kernel holds up to CHI0_MAX_GROUPS groups (the point batches of
+// one job, or of several jobs of the serving loop launched together); group i owns the
+// workgroups [begin[i], begin[i + 1]) of the one-dimensional grid and is contracted
+// exactly as it would be alone.
+struct Chi0Launch {
+  int32_t ngroups;
+  int32_t begin[CHI0_MAX_GROUPS + 1];
+  Chi0Args g[CHI0_MAX_GROUPS];
+};
+
 template <bool CPLX_B>
-__global__ __launch_bounds__(256) void chi0_f64_w2_kernel(Chi0Args a) {
+__global__ __launch_bounds__(256) void chi0_f64_w2_kernel(Chi0Launch L) {
   constexpr int KT = 16;
   __shared__ double2 lds[2][2][KT][LDP];
   __shared__ double lw[2][2][KT];   // [buffer][point of the pair][row]
 
-  // one-dimensional grid, off-diagonal tiles of every (pair, split) first and the shorter
-  // diagonal tiles last, so the last round of workgroups is made of short ones
+  // the group (uniform over the workgroup), selected with constant indices only so that
+  // its arguments stay in scalar registers
+  int gi = 0;
+#pragma unroll
+  for (int k = 1; k < CHI0_MAX_GROUPS; ++k)
+    if (k < L.ngroups && (int32_t)blockIdx.x >= L.begin[k]) gi = k;
+  Chi0Args a = L.g[0];
+  int32_t gbase = L.begin[0];
+#pragma unroll
+  for (int k = 1; k < CHI0_MAX_GROUPS; ++k)
+    if (k == gi) {
+      a = L.g[k];
+      gbase = L.begin[k];
+    }
+
+  // one-dimensional grid per group, off-diagonal tiles of every (pair, split) first and
+  // the shorter diagonal tiles last, so the last round of workgroups is made of short ones
   const int T = (a.N + TN - 1) / TN;
   const int noff = T * (T - 1) / 2;
   const int64_t nunits = (int64_t)a.npairs * a.ksplit;
-  const int64_t g = blockIdx.x;
+  const int64_t g = (int64_t)blockIdx.x - gbase;
   int tr, tc, pair, split;
   if (g < (int64_t)noff * nunits) {
     const int k = (int)(g % noff);               // strictly lower tile k: row r > column c
@@ -800,17 +825,8 @@ hipError_t launch_chi0_f64(hipStream_t s, const Chi0Args &args, int32_t npts, bo
   // of the same tile and K step computes the same sums
   if (cfg == 4 && (a.pairs == nullptr || a.npairs <= 0)) cfg = 1;
   if (cfg == 4) {
-    const int T = (a.N + TN - 1) / TN;
-    const int64_t nwg = (int64_t)T * (T + 1) / 2 * a.npairs * ks;
-    if (nwg > 0x7fffffff) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)nwg);
-    if (cplx_b)
-      hipLaunchKernelGGL((chi0_f64_w2_kernel<true>), grid, dim3(256), 0, s, a);
-    else
-      hipLaunchKernelGGL((chi0_f64_w2_kernel<false>), grid, dim3(256), 0, s, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || ks == 1) return e;
-    return launch_split_add(s, a.partial, ks - 1, (int64_t)npts * a.out_stride, a.out);
+    Chi0Group one{a, npts};
+    return launch_chi0_f64_paired_groups(s, &one, 1, cplx_b);
   }
   if (cfg == 3) {
     const int T = (a.N + TW - 1) / TW;
@@ -839,6 +855,50 @@ hipError_t launch_chi0_f64(hipStream_t s, const Chi0Args &args, int32_t npts, bo
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || ks == 1) return e;
   return launch_split_add(s, a.partial, ks - 1, (int64_t)npts * a.out_stride, a.out);
+}
+
+int64_t chi0_paired_workgroups(const Chi0Args &a) {
+  const int T = (a.N + TN - 1) / TN;
+  return (int64_t)T * (T + 1) / 2 * a.npairs * (a.ksplit > 1 ? a.ksplit : 1);
+}
+
+hipError_t launch_chi0_f64_paired_groups(hipStream_t s, const Chi0Group *groups, int ngroups, bool cplx_b) {
+  if (ngroups <= 0) return hipSuccess;
+  if (ngroups > CHI0_MAX_GROUPS) return hipErrorInvalidValue;
+  Chi0Launch L{};
+  int64_t total = 0;
+  int n = 0;
+  for (int i = 0; i < ngroups; ++i) {
+    const Chi0Group &gr = groups[i];
+    if (gr.npts <= 0) continue;
+    if (gr.a.ksplit > kMaxSplit || gr.a.pairs == nullptr || gr.a.npairs <= 0) return hipErrorInvalidValue;
+    Chi0Args a = gr.a;
+    a.ksplit = a.ksplit > 1 ? a.ksplit : 1;
+    a.split_stride = (int64_t)gr.npts * a.out_stride;
+    L.g[n] = a;
+    L.begin[n] = (int32_t)total;
+    total += chi0_paired_workgroups(a);
+    if (total > 0x7fffffff) return hipErrorInvalidValue;
+    ++n;
+  }
+  if (n == 0) return hipSuccess;
+  L.ngroups = n;
+  for (int i = n; i <= CHI0_MAX_GROUPS; ++i) L.begin[i] = (int32_t)total;
+  const dim3 grid((unsigned)total);
+  if (cplx_b)
+    hipLaunchKernelGGL((chi0_f64_w2_kernel<true>), grid, dim3(256), 0, s, L);
+  else
+    hipLaunchKernelGGL((chi0_f64_w2_kernel<false>), grid, dim3(256), 0, s, L);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // each group's later row splits added into its output, in split order
+  for (int i = 0; i < n; ++i) {
+    const Chi0Args &a = L.g[i];
+    if (a.ksplit <= 1) continue;
+    e = launch_split_add(s, a.partial, a.ksplit - 1, a.split_stride, a.out);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_split_add(hipStream_t s, const double2 *partial, int32_t nparts, int64_t n, double2 *out) {

@@ -197,10 +197,41 @@ __device__ __forceinline__ void contract_diag5_f32(const float2 (*la)[LDP32], co
 // float product w * b the single-point kernel forms at its LDS store, so the sums are bit
 // for bit the same); half the loads, LDS stores and barriers per MFMA.  In diagonal tiles
 // waves 0 and 1 take point 0's ten lower blocks, five each, and waves 2 and 3 point 1's.
+// A launch holds up to CHI0_MAX_GROUPS groups (NP = 2 only: the point batches of several
+// serving jobs launched together); group i owns the workgroups [begin[i], begin[i + 1])
+// of the one-dimensional grid and is contracted exactly as it would be alone.
+struct Chi0F32Launch {
+  int32_t ngroups;
+  int32_t begin[CHI0_MAX_GROUPS + 1];
+  Chi0Args g[CHI0_MAX_GROUPS];
+  const float2 *B32[CHI0_MAX_GROUPS];
+  const double *diag[CHI0_MAX_GROUPS];
+};
+
 template <int KT, int NP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void chi0_f32_kernel(Chi0Args a,
-                                                                                              const float2 *B32,
-                                                                                              const double *diag) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void chi0_f32_kernel(Chi0F32Launch L) {
+  // the group (uniform over the workgroup), selected with constant indices only so that
+  // its arguments stay in scalar registers
+  int gi = 0;
+  if constexpr (NP == 2) {
+#pragma unroll
+    for (int k = 1; k < CHI0_MAX_GROUPS; ++k)
+      if (k < L.ngroups && (int32_t)blockIdx.x >= L.begin[k]) gi = k;
+  }
+  Chi0Args a = L.g[0];
+  const float2 *B32 = L.B32[0];
+  const double *diag = L.diag[0];
+  int32_t gbase = L.begin[0];
+  if constexpr (NP == 2) {
+#pragma unroll
+    for (int k = 1; k < CHI0_MAX_GROUPS; ++k)
+      if (k == gi) {
+        a = L.g[k];
+        B32 = L.B32[k];
+        diag = L.diag[k];
+        gbase = L.begin[k];
+      }
+  }
   __shared__ float2 lds[2][2][KT][LDP32];
   __shared__ float lw[2][NP][KT];   // per-row weights of the pair (NP = 2 only)
   constexpr int RPI = 16;
@@ -219,7 +250,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
     const int T = (a.N + TN - 1) / TN;
     const int noff = T * (T - 1) / 2;
     const int64_t nunits = (int64_t)a.npairs * a.ksplit;
-    const int64_t g = blockIdx.x;
+    const int64_t g = (int64_t)blockIdx.x - gbase;
     int64_t u;
     if (g < (int64_t)noff * nunits) {
       const int k = (int)(g % noff);   // strictly lower tile k: row r > column c
@@ -770,10 +801,8 @@ hipError_t launch_chi0_mixed(hipStream_t s, const Chi0Args &args, int32_t npts, 
   // of the same tile computes the same sums
   if (tile == kF32T64W2 && (a.pairs == nullptr || a.npairs <= 0)) tile = kF32T64;
   if (tile == kF32T64W2) {
-    const int T = (a.N + TN - 1) / TN;
-    const int64_t nwg = (int64_t)T * (T + 1) / 2 * a.npairs * ks;
-    if (nwg > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((chi0_f32_kernel<16, 2>), dim3((unsigned)nwg), dim3(256), 0, s, a, B32, diag);
+    Chi0F32Group one{a, npts, B32, diag};
+    return launch_chi0_f32_paired_groups(s, &one, 1);
   } else if (tile == kF32T128) {
     const int T = (a.N + TW32 - 1) / TW32;
     const int64_t nwg = (int64_t)T * (T + 1) / 2 * npts * ks;
@@ -783,11 +812,52 @@ hipError_t launch_chi0_mixed(hipStream_t s, const Chi0Args &args, int32_t npts, 
   } else {
     const int T = (a.N + TN - 1) / TN;
     const dim3 grid((unsigned)(T * (T + 1) / 2), (unsigned)npts, (unsigned)ks);
-    hipLaunchKernelGGL((chi0_f32_kernel<16, 1>), grid, dim3(256), 0, s, a, B32, diag);
+    Chi0F32Launch L{};
+    L.ngroups = 1;
+    L.g[0] = a;
+    L.B32[0] = B32;
+    L.diag[0] = diag;
+    hipLaunchKernelGGL((chi0_f32_kernel<16, 1>), grid, dim3(256), 0, s, L);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || ks == 1) return e;
   return launch_split_add(s, a.partial, ks - 1, (int64_t)npts * a.out_stride, a.out);
+}
+
+hipError_t launch_chi0_f32_paired_groups(hipStream_t s, const Chi0F32Group *groups, int ngroups) {
+  if (ngroups <= 0) return hipSuccess;
+  if (ngroups > CHI0_MAX_GROUPS) return hipErrorInvalidValue;
+  Chi0F32Launch L{};
+  int64_t total = 0;
+  int n = 0;
+  for (int i = 0; i < ngroups; ++i) {
+    const Chi0F32Group &gr = groups[i];
+    if (gr.npts <= 0) continue;
+    if (gr.a.ksplit > kMaxSplit || gr.a.pairs == nullptr || gr.a.npairs <= 0) return hipErrorInvalidValue;
+    Chi0Args a = gr.a;
+    a.ksplit = a.ksplit > 1 ? a.ksplit : 1;
+    a.split_stride = (int64_t)gr.npts * a.out_stride;
+    L.g[n] = a;
+    L.B32[n] = gr.B32;
+    L.diag[n] = gr.diag;
+    L.begin[n] = (int32_t)total;
+    total += chi0_paired_workgroups(a);
+    if (total > 0x7fffffff) return hipErrorInvalidValue;
+    ++n;
+  }
+  if (n == 0) return hipSuccess;
+  L.ngroups = n;
+  for (int i = n; i <= CHI0_MAX_GROUPS; ++i) L.begin[i] = (int32_t)total;
+  hipLaunchKernelGGL((chi0_f32_kernel<16, 2>), dim3((unsigned)total), dim3(256), 0, s, L);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  for (int i = 0; i < n; ++i) {   // each group's later row splits, added in split order
+    const Chi0Args &a = L.g[i];
+    if (a.ksplit <= 1) continue;
+    e = launch_split_add(s, a.partial, a.ksplit - 1, a.split_stride, a.out);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace rpa

@@ -77,6 +77,16 @@ int64_t ao_scratch_bytes(int32_t nbas, int32_t nocc, int32_t naux);
 hipError_t launch_ao_B(hipStream_t s, uint64_t seed, double sigma, int32_t nk, int32_t iq, int32_t ik, int32_t nbas,
                        int32_t nocc, int32_t nvirt, int32_t naux, const double2 *c_occ, const double2 *c_virt,
                        void *scratch, double2 *out);
+// The periodic projector of Sec. 2.3 (projector.hip): T(k) = U(k) R~ U(k)^H from the
+// overlaps S [nk][nbas][nbas] (complex, Hermitian; device memory), R~ keeping the
+// eigen-directions whose ascending-order eigenvalue is >= eps_d at every k; T written to
+// T [nk][nbas][nbas].  scratch holds projector_scratch_bytes(nk, nbas) bytes.  nbas <= 1024.
+int64_t projector_scratch_bytes(int32_t nk, int32_t nbas);
+hipError_t launch_projector(hipStream_t s, const double2 *S, int32_t nk, int32_t nbas, double eps_d, void *scratch,
+                            double2 *T);
+// out[k] = T[k] c[k] for c [nk][nbas][nb] (complex), out of place.
+hipError_t launch_project_coeff(hipStream_t s, const double2 *T, const double2 *c, int32_t nk, int32_t nbas,
+                                int32_t nb, double2 *out);
 hipError_t launch_philox_words(hipStream_t s, uint64_t seed, int32_t nk, int32_t iq, int32_t ik,
                                uint64_t e0, int64_t count, uint32_t *out);
 
@@ -89,6 +99,26 @@ hipError_t launch_chi0_weights(hipStream_t s, const Chi0Args &a, int32_t npts);
 // splits 1..s-1 write planes of a.partial (npts points apart) and the launch then adds
 // them into a.out in split order (repeatable).
 hipError_t launch_chi0_f64(hipStream_t s, const Chi0Args &a, int32_t npts, bool cplx_b, int cfg);
+// Paired FP64 contraction (configuration 4) of several groups of points (each with its
+// own Chi0Args and point count, all with pair tables) in one launch: every group's
+// results are exactly those of launching it alone, its row splits added in split order.
+constexpr int CHI0_MAX_GROUPS = 8;
+struct Chi0Group {
+  Chi0Args a;
+  int32_t npts;
+};
+hipError_t launch_chi0_f64_paired_groups(hipStream_t s, const Chi0Group *groups, int ngroups, bool cplx_b);
+// Workgroups of one group's paired launch (FP64 or FP32: both use 64-wide tiles).
+int64_t chi0_paired_workgroups(const Chi0Args &a);
+// The same for the paired FP32 contraction (configuration kF32T64W2), each group with its
+// own FP32 copy of B and exact FP64 diagonal.
+struct Chi0F32Group {
+  Chi0Args a;
+  int32_t npts;
+  const float2 *B32;
+  const double *diag;
+};
+hipError_t launch_chi0_f32_paired_groups(hipStream_t s, const Chi0F32Group *groups, int ngroups);
 int chi0_cfg_count();
 int chi0_cfg_tile(int cfg);            // output tile edge of a configuration
 int chi0_cfg_slots_per_cu(int cfg);    // workgroups of it that fit on one CU

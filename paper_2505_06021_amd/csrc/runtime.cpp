@@ -243,6 +243,19 @@ int validate_system(const rpa_system *sys, HostSmall &hs) {
     RPA_TRY(copy_in(hs.c_virt.data(), sys->c_virt, hs.c_virt.size() * 8, sys->memspace));
     for (double v : hs.c_occ) if (!std::isfinite(v)) return fail(RPA_E_ARG, "c_occ not finite");
     for (double v : hs.c_virt) if (!std::isfinite(v)) return fail(RPA_E_ARG, "c_virt not finite");
+    hs.S.clear();
+    hs.eps_d = 0.0;
+    if (sys->S_ao) {
+      // raw coefficients: the projector of Sec. 2.3 runs on the device
+      if (nk_occ != sys->nk)
+        return fail(RPA_E_ARG, "the device projector takes regular grids (nk_occ = nk); project dual-grid coefficients first");
+      if (sys->nbas > 1024) return fail(RPA_E_ARG, "the device projector takes nbas <= 1024 (nbas %d)", sys->nbas);
+      if (!(sys->eps_d >= 0.0) || !std::isfinite(sys->eps_d)) return fail(RPA_E_ARG, "eps_d must be finite and >= 0");
+      hs.eps_d = sys->eps_d;
+      hs.S.resize((size_t)sys->nk * sys->nbas * sys->nbas * 2);
+      RPA_TRY(copy_in(hs.S.data(), sys->S_ao, hs.S.size() * 8, sys->memspace));
+      for (double v : hs.S) if (!std::isfinite(v)) return fail(RPA_E_ARG, "S_ao not finite");
+    }
   }
   // insulators only (closed-shell occupations 2/0): every transition energy positive
   double min_occ_gap = INFINITY;
@@ -256,6 +269,41 @@ int validate_system(const rpa_system *sys, HostSmall &hs) {
     }
   if (!(min_occ_gap > 0.0))
     return fail(RPA_E_ARG, "smallest transition energy %g <= 0: only insulators are supported", min_occ_gap);
+  return RPA_OK;
+}
+
+// ---- atomic-orbital coefficients ------------------------------------------------------
+int64_t ao_stage_scratch_bytes(const HostSmall &hs) {
+  if (hs.nbas <= 0 || hs.S.empty()) return 256;
+  const int64_t nn = (int64_t)hs.nbas * hs.nbas;
+  // S, T, the raw coefficients and the projector's own scratch
+  return (int64_t)hs.nk * nn * 16 * 2 + (int64_t)(hs.c_occ.size() + hs.c_virt.size()) * 8 +
+         projector_scratch_bytes(hs.nk, hs.nbas) + 1024;
+}
+
+int stage_ao_coefficients(hipStream_t st, const HostSmall &hs, double2 *d_cocc, double2 *d_cvirt, void *scratch) {
+  if (hs.S.empty()) {
+    RPA_HIP(hipMemcpyAsync(d_cocc, hs.c_occ.data(), hs.c_occ.size() * 8, hipMemcpyHostToDevice, st));
+    RPA_HIP(hipMemcpyAsync(d_cvirt, hs.c_virt.data(), hs.c_virt.size() * 8, hipMemcpyHostToDevice, st));
+    return RPA_OK;
+  }
+  const int64_t nn = (int64_t)hs.nbas * hs.nbas;
+  char *p = (char *)scratch;
+  double2 *S = (double2 *)p;
+  p += hs.nk * nn * 16;
+  double2 *T = (double2 *)p;
+  p += hs.nk * nn * 16;
+  double2 *raw_o = (double2 *)p;
+  p += (int64_t)hs.c_occ.size() * 8;
+  double2 *raw_v = (double2 *)p;
+  p += (int64_t)hs.c_virt.size() * 8;
+  void *pscr = (void *)(((uintptr_t)p + 255) / 256 * 256);
+  RPA_HIP(hipMemcpyAsync(S, hs.S.data(), hs.S.size() * 8, hipMemcpyHostToDevice, st));
+  RPA_HIP(hipMemcpyAsync(raw_o, hs.c_occ.data(), hs.c_occ.size() * 8, hipMemcpyHostToDevice, st));
+  RPA_HIP(hipMemcpyAsync(raw_v, hs.c_virt.data(), hs.c_virt.size() * 8, hipMemcpyHostToDevice, st));
+  RPA_HIP(launch_projector(st, S, hs.nk, hs.nbas, hs.eps_d, pscr, T));
+  RPA_HIP(launch_project_coeff(st, T, raw_o, hs.nk, hs.nbas, hs.nocc, d_cocc));
+  RPA_HIP(launch_project_coeff(st, T, raw_v, hs.nk, hs.nbas, hs.nvirt, d_cvirt));
   return RPA_OK;
 }
 
@@ -363,7 +411,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   };
   // atomic-orbital systems: the projected coefficients and the transform's scratch
   const int64_t ao_bytes = hs.nbas > 0 ? (int64_t)(hs.c_occ.size() + hs.c_virt.size()) * 8 + 512 +
-                                             ao_scratch_bytes(hs.nbas, hs.nocc, hs.naux)
+                                             ao_scratch_bytes(hs.nbas, hs.nocc, hs.naux) + ao_stage_scratch_bytes(hs)
                                        : 0;
   const int64_t small = (int64_t)(hs.eps_occ.size() + hs.eps_virt.size() + hs.zeta_k.size()) * 8 +
                         (int64_t)hs.kq.size() * 4 + npts * 32 + 4096 + ao_bytes;
@@ -463,10 +511,11 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   ar.plan(npts * 8, (void **)&d_eps);
   ar.plan(npts * 4, (void **)&d_info);
   double2 *d_cocc = nullptr, *d_cvirt = nullptr;
-  void *d_aoscr = nullptr;
+  void *d_aoscr = nullptr, *d_aostage = nullptr;
   if (hs.nbas > 0) {
     ar.plan((int64_t)hs.c_occ.size() * 8, (void **)&d_cocc);
     ar.plan((int64_t)hs.c_virt.size() * 8, (void **)&d_cvirt);
+    ar.plan(ao_stage_scratch_bytes(hs), &d_aostage);
     ar.plan(ao_scratch_bytes(hs.nbas, hs.nocc, hs.naux), &d_aoscr);
   }
   if (b_slot) ar.plan(gq * b_slot, &d_B);
@@ -535,8 +584,7 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
   RPA_HIP(hipMemcpyAsync(d_zk, hs.zeta_k.data(), hs.zeta_k.size() * 8, hipMemcpyHostToDevice, st));
   RPA_HIP(hipMemcpyAsync(d_kq, hs.kq.data(), hs.kq.size() * 4, hipMemcpyHostToDevice, st));
   if (hs.nbas > 0) {
-    RPA_HIP(hipMemcpyAsync(d_cocc, hs.c_occ.data(), hs.c_occ.size() * 8, hipMemcpyHostToDevice, st));
-    RPA_HIP(hipMemcpyAsync(d_cvirt, hs.c_virt.data(), hs.c_virt.size() * 8, hipMemcpyHostToDevice, st));
+    RPA_TRY(stage_ao_coefficients(st, hs, d_cocc, d_cvirt, d_aostage));
   }
 
   // B rows of the k-points [k0, k1) of q into slot s on stream S: generated (Philox, or
@@ -817,12 +865,12 @@ int run_points(Ctx &ctx, hipStream_t st, PointJob &job, int64_t budget, bool use
         } else {
           if (prof) RPA_TRY(ctx.prof_end(S));
           if (prof) RPA_TRY(ctx.prof_begin(S, RPA_K_CHI0));
-          RPA_HIP(launch_chi0_mixed(S, ca, nb, d_B32, d_diag, (int)job.prec, f32_tile));
+          RPA_TRY(fused_chi0_f32(job.fuser, S, ca, nb, d_B32, d_diag, f32_tile));
         }
       } else {
         if (prof) RPA_TRY(ctx.prof_end(S));
         if (prof) RPA_TRY(ctx.prof_begin(S, RPA_K_CHI0));
-        RPA_HIP(launch_chi0_f64(S, ca, nb, cplx, cfg));
+        RPA_TRY(fused_chi0_f64(job.fuser, S, ca, nb, cplx, cfg));
       }
       if (prof && !bsplit) RPA_TRY(ctx.prof_end(S));
       if (c > 0) {

@@ -114,7 +114,18 @@ struct HostSmall {
   // interleaved), [nk_occ][nbas][nocc] and [nk][nbas][nvirt]
   int32_t nbas = 0;
   std::vector<double> c_occ, c_virt;
+  // raw coefficients to be projected on the device (Sec. 2.3): the overlaps S(k),
+  // [nk][nbas][nbas] complex interleaved, and the threshold; S empty: c is projected already
+  std::vector<double> S;
+  double eps_d = 0.0;
 };
+
+// Device bytes stage_ao_coefficients needs beside the two coefficient buffers.
+int64_t ao_stage_scratch_bytes(const HostSmall &hs);
+// Upload the atomic-orbital coefficients of hs into d_cocc ([nk_occ][nbas][nocc]) and
+// d_cvirt ([nk][nbas][nvirt]); with overlaps in hs, apply the periodic projector T(k) on
+// the device first (scratch: ao_stage_scratch_bytes).
+int stage_ao_coefficients(hipStream_t st, const HostSmall &hs, double2 *d_cocc, double2 *d_cvirt, void *scratch);
 
 int validate_system(const rpa_system *sys, HostSmall &hs);
 int validate_freq(const rpa_freq *f);
@@ -140,6 +151,11 @@ void fuser_stats(Fuser *f, int64_t *launches, int64_t *fused_groups, int64_t *so
 // fills the GPU by itself (or f is null), else fused with the groups other jobs post at
 // about the same time; st waits for the launch either way.
 int fused_herk(Fuser *f, hipStream_t st, const Bf16Group &g, bool cplx);
+// The same for the FP64 contraction (configuration cfg; only the paired configuration 4
+// is fused) and the FP32 contraction (tile configuration; only kF32T64W2 is fused).
+int fused_chi0_f64(Fuser *f, hipStream_t st, const Chi0Args &a, int npts, bool cplx, int cfg);
+int fused_chi0_f32(Fuser *f, hipStream_t st, const Chi0Args &a, int npts, const float2 *B32, const double *diag,
+                   int tile);
 
 struct PointJob {
   const rpa_system *sys;     // caller's description (pointers valid during run)
@@ -154,7 +170,7 @@ struct PointJob {
   std::vector<double> qstage;   // host staging of zeta_q and W_j
   double E = 0.0;
   int max_q_group = 0;          // > 0: at most this many q's staged at once
-  Fuser *fuser = nullptr;       // serving: split-BF16 contractions may be fused across jobs
+  Fuser *fuser = nullptr;       // serving: small contractions may be fused across jobs
 };
 
 int run_points(Ctx &ctx, hipStream_t stream, PointJob &job, int64_t mem_budget, bool use_cache);

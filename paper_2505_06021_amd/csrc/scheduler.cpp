@@ -64,7 +64,7 @@ int64_t Scheduler::footprint(const HostSmall &hs, int nw, rpa_precision prec, in
                         (bsplit ? bf16_diag_scratch_doubles(M, (int)N) * 8
                          : mixed ? diag_exact_scratch_doubles(M, (int)N, 16) * 8 : 0) +
                         (hs.nbas > 0 ? (int64_t)(hs.c_occ.size() + hs.c_virt.size()) * 8 + 512 +
-                                           ao_scratch_bytes(hs.nbas, hs.nocc, hs.naux)
+                                           ao_scratch_bytes(hs.nbas, hs.nocc, hs.naux) + ao_stage_scratch_bytes(hs)
                                      : 0);
   // one q staged at a time: FP64 B (and its FP32 copy, or its prepared split-BF16 copy),
   // V^(1/2), and per point chi0, T, the weight table and the exact diagonal -- the same
@@ -144,6 +144,7 @@ int Scheduler::submit(const rpa_system *sys, const rpa_freq *freq, rpa_precision
   // atomic-orbital systems: the job's own copies of the projected coefficients
   s.c_occ = j->hs.nbas > 0 ? (const void *)j->hs.c_occ.data() : nullptr;
   s.c_virt = j->hs.nbas > 0 ? (const void *)j->hs.c_virt.data() : nullptr;
+  s.S_ao = j->hs.S.empty() ? nullptr : (const void *)j->hs.S.data();
   j->prec = prec;
   j->t_submit = now_seconds();
   std::lock_guard<std::mutex> g(mu_);
@@ -215,10 +216,10 @@ void Scheduler::worker(int w) {
       pj.weight = j->weight;
       pj.max_q_group = 1;
       pj.fuser = fuser_;
-      const bool fusing = j->prec == RPA_BF16X3 || j->prec == RPA_F16X3;
-      if (fusing) fuser_register(fuser_, +1);
+      // every precision's small contractions may be fused with other jobs' of their kind
+      fuser_register(fuser_, +1);
       rc = run_points(ctx_, st, pj, j->need, false);
-      if (fusing) fuser_register(fuser_, -1);
+      fuser_register(fuser_, -1);
       if (rc == RPA_OK) {
         j->E = pj.E;
         j->eps = std::move(pj.eps);

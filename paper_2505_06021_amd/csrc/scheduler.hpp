@@ -7,8 +7,9 @@
 // soon as a worker and memory are free and their kernels overlap on the device.  Each
 // job's points run through the same pipeline and kernels as a synchronous rpa_energy
 // call on buffers the job owns, so a job's result does not depend on what runs beside it.
-// Small split-BF16 contraction launches of jobs in flight are fused into one launch
-// (fuser.cpp), which changes when they run, never what they compute.
+// Small contraction launches of jobs in flight (split 16-bit, paired FP64 and paired FP32)
+// are fused into one launch per kind (fuser.cpp), which changes when they run, never what
+// they compute.
 #pragma once
 
 #include "runtime.hpp"
@@ -44,7 +45,7 @@ class Scheduler {
   int64_t submitted_ = 0, done_ = 0, running_ = 0;
   bool stop_ = false;
   bool started_ = false;
-  Fuser *fuser_ = nullptr;   // cross-job fusion of small split-BF16 contraction launches
+  Fuser *fuser_ = nullptr;   // cross-job fusion of small contraction launches
   void start_locked();
 };
 

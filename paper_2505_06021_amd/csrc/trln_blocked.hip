@@ -6,13 +6,16 @@
 // the identity is kept implicit: with d_c the updated diagonal entry of W, the pivot is
 // 1 + d_c and 2 ln L_cc = log1p(d_c), exact to the last bit even when Pi is tiny.
 //
-// Per 64-column panel j0 of every matrix, three launches:
-//   chol_diag   one workgroup per matrix: factor the 64 x 64 diagonal block in LDS,
-//               accumulate log1p of its pivots, and form the triangular inverse L11^-1;
+// Per 64-column panel j0 of every matrix:
+//   diagonal    factor the 64 x 64 diagonal block in LDS, accumulate log1p of its
+//               pivots, and form the triangular inverse L11^-1 (one workgroup per
+//               matrix; a launch of its own for the first block, else inside the
+//               previous panel's update);
 //   chol_panel  one workgroup per 64 rows below the block: L21 = W21 L11^-H as a
 //               64 x 64 x 64 complex MFMA product;
 //   chol_update one workgroup per 64 x 64 lower-triangle tile of the trailing matrix:
-//               W22 -= L21 L21^H with v_mfma_f64_16x16x4f64.
+//               W22 -= L21 L21^H with v_mfma_f64_16x16x4f64; the workgroups of the
+//               first trailing tile then factor it as the next diagonal block.
 // A matrix whose pivot fails records the column in info[] and is skipped afterwards.
 #include "common.hpp"
 
@@ -97,14 +100,14 @@ __global__ __launch_bounds__(256) void chol_init_kernel(const double2 *W, int64_
   }
 }
 
-__global__ __launch_bounds__(256) void chol_diag_kernel(double2 *W, int64_t stride, int n, int j0, double *logacc,
-                                                        int32_t *info, double2 *linv) {
-  __shared__ double2 D[NB][LP];
-  __shared__ double2 X[NB][LP];
+// Factor the diagonal block at column j0 of matrix b (pivots 1 + d, log1p of them into
+// logacc[b], the factor's inverse L11^-1 into linv); D and X are two NB x LP LDS arrays
+// of the calling kernel.  A failing pivot records its column in info[b].  Called by the
+// whole workgroup (every branch on the pivot is uniform).
+__device__ __forceinline__ void diag_block(double2 *W, int64_t stride, int n, int j0, int b, double *logacc,
+                                           int32_t *info, double2 *linv, double2 (*D)[LP], double2 (*X)[LP]) {
   __shared__ double2 colbuf[2][NB];
   __shared__ double ld[NB];
-  const int b = blockIdx.x;
-  if (info[b] >= 0) return;
   double2 *A = W + (int64_t)b * stride;
   const int jb = min(NB, n - j0);
   const int tid = threadIdx.x;
@@ -209,6 +212,15 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(double2 *W, int64_t stri
   for (int e = tid; e < NB * NB; e += 256) out[e] = X[e / NB][e % NB];
 }
 
+__global__ __launch_bounds__(256) void chol_diag_kernel(double2 *W, int64_t stride, int n, int j0, double *logacc,
+                                                        int32_t *info, double2 *linv) {
+  __shared__ double2 D[NB][LP];
+  __shared__ double2 X[NB][LP];
+  const int b = blockIdx.x;
+  if (info[b] >= 0) return;
+  diag_block(W, stride, n, j0, b, logacc, info, linv, D, X);
+}
+
 __global__ __launch_bounds__(256) void chol_panel_kernel(double2 *W, int64_t stride, int n, int j0,
                                                          const int32_t *info, const double2 *linv) {
   __shared__ double2 Ab[NB][LP];
@@ -248,15 +260,19 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(double2 *W, int64_t str
       }
 }
 
+// Trailing update of panel j0 with a look-ahead: grid (matrix, tile), tile 0 (the next
+// diagonal block) first for every matrix; the workgroups of tile 0 then factor that block
+// for the next panel (what chol_diag would do in a launch of its own), so the latency-bound
+// factorisation runs beside the other tiles' updates instead of after them.
 __global__ __launch_bounds__(256) void chol_update_kernel(double2 *W, int64_t stride, int n, int j0,
-                                                          const int32_t *info) {
+                                                          int32_t *info, double *logacc, double2 *linv) {
   __shared__ double2 Ab[NB][LP];
   __shared__ double2 Bb[NB][LP];
-  const int b = blockIdx.y;
+  const int b = blockIdx.x;
   if (info[b] >= 0) return;
   const int jb = min(NB, n - j0);
   int tr, tc;
-  tile_of((int)blockIdx.x, tr, tc);
+  tile_of((int)blockIdx.y, tr, tc);
   const int R0 = j0 + jb + tr * NB, S0 = j0 + jb + tc * NB;
   if (R0 >= n) return;
   double2 *A = W + (int64_t)b * stride;
@@ -285,6 +301,12 @@ __global__ __launch_bounds__(256) void chol_update_kernel(double2 *W, int64_t st
           *p = make_double2(v.x - accR[x][y][r], v.y - accI[x][y][r]);
         }
       }
+  if (blockIdx.y == 0) {
+    // the updated next diagonal block is in global memory, written by this workgroup:
+    // the barrier orders those stores before the factorisation's loads
+    __syncthreads();
+    diag_block(W, stride, n, j0 + jb, b, logacc, info, linv, Ab, Bb);
+  }
 }
 
 __global__ void chol_finish_kernel(const double *trace, const double *logacc, const int32_t *info, int batch,
@@ -335,17 +357,19 @@ hipError_t launch_trln_blocked(hipStream_t s, double2 *w, int64_t stride, int32_
   hipLaunchKernelGGL(chol_init_kernel, dim3((unsigned)batch), dim3(256), 0, s, w, stride, n, trace, logacc, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  // the first diagonal block alone; every later one is factored inside the previous
+  // panel's trailing update (look-ahead)
+  hipLaunchKernelGGL(chol_diag_kernel, dim3((unsigned)batch), dim3(256), 0, s, w, stride, n, 0, logacc, info, linv);
   for (int j0 = 0; j0 < n; j0 += NB) {
     const int jb = n - j0 < NB ? n - j0 : NB;
-    hipLaunchKernelGGL(chol_diag_kernel, dim3((unsigned)batch), dim3(256), 0, s, w, stride, n, j0, logacc, info,
-                       linv);
     const int rest = n - j0 - jb;
     if (rest > 0) {
       const int nt = (rest + NB - 1) / NB;
+      if (nt * (nt + 1) / 2 > 65535) return hipErrorInvalidValue;
       hipLaunchKernelGGL(chol_panel_kernel, dim3((unsigned)nt, (unsigned)batch), dim3(256), 0, s, w, stride, n, j0,
                          info, linv);
-      hipLaunchKernelGGL(chol_update_kernel, dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)batch), dim3(256), 0, s,
-                         w, stride, n, j0, info);
+      hipLaunchKernelGGL(chol_update_kernel, dim3((unsigned)batch, (unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, s,
+                         w, stride, n, j0, info, logacc, linv);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -21,7 +21,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librpa.so")
 
 EXPORTS = ("rpa_init", "rpa_finalize", "rpa_last_error", "rpa_set_stream", "rpa_chi0", "rpa_chi0_noalloc", "rpa_pi",
-           "rpa_trln", "rpa_energy", "rpa_points", "rpa_philox_B", "rpa_philox_words",
+           "rpa_trln", "rpa_energy", "rpa_points", "rpa_projector", "rpa_philox_B", "rpa_philox_words",
            "rpa_submit", "rpa_poll", "rpa_get_stats", "rpa_profile", "rpa_profile_read", "rpa_tuned")
 KERNEL_KINDS = ("philox", "chi0", "pi", "trln", "other", "chi0_aux")
 
@@ -38,7 +38,8 @@ class RpaSystemC(C.Structure):
                 ("kq", C.c_void_p), ("eps_occ", C.c_void_p), ("eps_virt", C.c_void_p),
                 ("zeta_k", C.c_void_p), ("zeta_q", C.c_void_p), ("B", C.c_void_p),
                 ("philox_seed", C.c_uint64), ("sigma", C.c_double), ("vhalf", C.c_void_p),
-                ("nk_occ", C.c_int32), ("nbas", C.c_int32), ("c_occ", C.c_void_p), ("c_virt", C.c_void_p)]
+                ("nk_occ", C.c_int32), ("nbas", C.c_int32), ("c_occ", C.c_void_p), ("c_virt", C.c_void_p),
+                ("S_ao", C.c_void_p), ("eps_d", C.c_double)]
 
 
 class RpaFreqC(C.Structure):
@@ -83,6 +84,7 @@ def load():
         "rpa_trln": [P, I32, I32, I32, I32, P, P],
         "rpa_energy": [P, C.POINTER(RpaSystemC), C.POINTER(RpaFreqC), C.c_int, P, P],
         "rpa_points": [P, C.POINTER(RpaSystemC), I32, P, P, C.c_int, P],
+        "rpa_projector": [P, I32, I32, D, I32, P, P],
         "rpa_philox_B": [P, U64, D, I32, I32, I32, I32, I32, I32, I32, I32, P],
         "rpa_philox_words": [P, U64, I32, I32, I32, U64, I64, I32, P],
         "rpa_submit": [P, C.POINTER(RpaSystemC), C.POINTER(RpaFreqC), C.c_int, C.POINTER(U64)],
@@ -175,8 +177,16 @@ class _Marshal:
         s.nk_occ = int(np.asarray(system.eps_occ).shape[0])
         s.nbas = int(getattr(system, "nbas", 0))
         if s.nbas > 0:
-            s.c_occ = put(system.c_occ, np.complex128)
-            s.c_virt = put(system.c_virt, np.complex128)
+            if getattr(system, "project_on_device", False):
+                # raw KS coefficients and the overlaps: the library applies the projector
+                nocc = system.nocc
+                s.c_occ = put(np.ascontiguousarray(system.c_raw[:, :, :nocc]), np.complex128)
+                s.c_virt = put(np.ascontiguousarray(system.c_raw[:, :, nocc:]), np.complex128)
+                s.S_ao = put(system.S_ao, np.complex128)
+                s.eps_d = float(system.eps_d)
+            else:
+                s.c_occ = put(system.c_occ, np.complex128)
+                s.c_virt = put(system.c_virt, np.complex128)
         if device:
             import torch
             torch.cuda.synchronize()   # the uploads ran on torch's stream
@@ -276,6 +286,15 @@ class Context:
         out = np.empty(len(iq), dtype=np.float64)
         self._check(self.lib.rpa_points(self.h, C.byref(m.c), len(iq), iq.ctypes.data, om.ctypes.data,
                                         prec, out.ctypes.data))
+        return out
+
+    def projector(self, S, eps_d):
+        """T(k) of the periodic projector from the overlaps S [nk][nbas][nbas] (host)."""
+        Sh = _host(S, np.complex128)
+        nk, nbas = Sh.shape[0], Sh.shape[1]
+        out = np.empty_like(Sh)
+        self._check(self.lib.rpa_projector(self.h, nk, nbas, float(eps_d), MEM_HOST, Sh.ctypes.data,
+                                           out.ctypes.data))
         return out
 
     def philox_B(self, seed, sigma, nk, iq, ik, nocc, nvirt, naux, is_complex=True):

@@ -40,8 +40,9 @@ def test_struct_layouts_match_header():
 #include <stddef.h>
 #include "rpa.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(rpa_system), offsetof(rpa_system, kq),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(rpa_system), offsetof(rpa_system, kq),
          offsetof(rpa_system, philox_seed), offsetof(rpa_system, vhalf), offsetof(rpa_system, nk_occ),
+         offsetof(rpa_system, S_ao), offsetof(rpa_system, eps_d),
          sizeof(rpa_freq), sizeof(rpa_result), sizeof(rpa_stats));
   return 0;
 }
@@ -54,7 +55,8 @@ int main(void) {
         subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
         got = list(map(int, subprocess.run([exe], capture_output=True, text=True).stdout.split()))
     want = [C.sizeof(rpa.RpaSystemC), rpa.RpaSystemC.kq.offset, rpa.RpaSystemC.philox_seed.offset,
-            rpa.RpaSystemC.vhalf.offset, rpa.RpaSystemC.nk_occ.offset, C.sizeof(rpa.RpaFreqC),
+            rpa.RpaSystemC.vhalf.offset, rpa.RpaSystemC.nk_occ.offset, rpa.RpaSystemC.S_ao.offset,
+            rpa.RpaSystemC.eps_d.offset, C.sizeof(rpa.RpaFreqC),
             C.sizeof(rpa.RpaResultC),
             C.sizeof(rpa.RpaStatsC)]
     assert got == want
