@@ -152,8 +152,14 @@ typedef struct {
 } rpa_stats;
 
 /* Create a context on HIP device `device`.  hbm_limit_bytes caps the device memory the
- * context may hold (0 = 90% of the device memory free at creation).  Errors: RPA_E_ARG
- * (ctx NULL, bad device), RPA_E_DEVICE. */
+ * context may hold (0 = 90% of the device memory free at creation).  Debugging modes,
+ * read from the environment here, once per context: RPA_POISON=1 fills every new device
+ * allocation with 0xFF bytes (NaN in every floating-point format used) before use, so a
+ * kernel that reads workspace it has not written shows up as a changed or NaN result;
+ * RPA_FAULT=alloc:N[,N2,...] makes the N-th (1-based) device allocation of the context,
+ * and each further listed one, fail with RPA_E_NOMEM ("injected" in the message), for
+ * tests of the error paths.  Errors: RPA_E_ARG (ctx NULL, bad device, malformed
+ * RPA_FAULT), RPA_E_DEVICE. */
 int rpa_init(rpa_ctx **ctx, int device, uint64_t hbm_limit_bytes);
 
 /* Cancel queued jobs, wait for running ones, free all device memory, destroy ctx. */
@@ -256,8 +262,11 @@ int rpa_philox_words(rpa_ctx *ctx, uint64_t seed, int32_t nk, int32_t iq, int32_
  * rpa_poll waits up to timeout_ms (0 = do not wait, < 0 = forever) and returns
  * RPA_PENDING, or the job's final status with *out filled and, if eps_qw != NULL,
  * its [nq][nw] integrand; a finished job is consumed by the successful poll.
- * Environment: RPA_SERVE_WORKERS (concurrent jobs, 1..16, default 4) and RPA_FUSE_WINDOW_US
- * (how long the fuser waits for other jobs' small contraction launches, default 300).
+ * A queued job that does not fit yet is passed by later jobs that fit, until it has waited
+ * RPA_SERVE_HOLD_MS (default 60000): then no job is admitted before it.
+ * Environment: RPA_SERVE_WORKERS (concurrent jobs, 1..16, default 4), RPA_SERVE_HOLD_MS,
+ * and RPA_FUSE_WINDOW_US (how long the fuser waits for other jobs' small contraction
+ * launches, default 300).
  * Errors: RPA_E_ARG, RPA_E_NOMEM, RPA_E_UNKNOWN_JOB, or the job's own error. */
 int rpa_submit(rpa_ctx *ctx, const rpa_system *sys, const rpa_freq *freq,
                rpa_precision prec, uint64_t *job_id);

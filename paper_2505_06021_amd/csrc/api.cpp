@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <cstdlib>
 #include <new>
 #include <vector>
 
@@ -24,7 +25,7 @@ int set_device(Ctx &c) {
 
 // Device bytes a synchronous call may plan with (its own cached workspaces count as
 // available; what admitted serving jobs have reserved does not).
-int64_t budget_of(Ctx &c) { return c.sync_budget(); }
+int64_t budget_of(Ctx &c) { return c.mem.sync_budget(); }
 
 // Copy `bytes` between a caller array in `memspace` and a device buffer.
 int to_device(void *dst, const void *src, size_t bytes, int memspace, hipStream_t s) {
@@ -87,7 +88,15 @@ int rpa_init(rpa_ctx **out, int device, uint64_t hbm_limit_bytes) {
   if (!ctx) return fail(RPA_E_NOMEM, "host allocation of the context failed");
   Ctx &c = ctx->c;
   c.device = device;
-  c.hbm_limit = hbm_limit_bytes ? (int64_t)hbm_limit_bytes : (int64_t)(0.9 * (double)free_b);
+  c.mem.set_limit(hbm_limit_bytes ? (int64_t)hbm_limit_bytes : (int64_t)(0.9 * (double)free_b));
+  // debugging modes, read once per context
+  const char *fault = getenv("RPA_FAULT");
+  if (!c.faults.parse(fault)) {
+    delete ctx;
+    return fail(RPA_E_ARG, "RPA_FAULT=%s: expected alloc:N[,N2,...] with N >= 1", fault);
+  }
+  const char *poison = getenv("RPA_POISON");
+  c.poison = poison && atoi(poison) != 0;
   hipError_t e = hipStreamCreateWithFlags(&c.own_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     delete ctx;
@@ -232,7 +241,7 @@ int rpa_chi0(rpa_ctx *ctx, const rpa_system *sys, int32_t iq, double omega, rpa_
     const int64_t plane = (int64_t)N * N * 16;
     auto it = c.cache.find("chi0_partial");
     const int64_t have = it != c.cache.end() ? it->second.bytes : 0;   // reused if large enough
-    while (ks_max > 1 && !c.would_fit(std::max<int64_t>(0, (int64_t)(ks_max - 1) * plane - have))) --ks_max;
+    while (ks_max > 1 && !c.mem.would_fit(std::max<int64_t>(0, (int64_t)(ks_max - 1) * plane - have))) --ks_max;
     for (int i = 0; i < n; ++i) ks_of[i] = std::min(ks_of[i], ks_max);
     if (ks_max > 1) return c.workspace("chi0_partial", (int64_t)(ks_max - 1) * plane, (void **)&a.partial);
     return RPA_OK;
@@ -507,12 +516,10 @@ int rpa_get_stats(rpa_ctx *ctx, rpa_stats *out) {
   RPA_TRY(check_ctx(ctx));
   if (!out) return fail(RPA_E_ARG, "out is NULL");
   Ctx &c = ctx->c;
-  {
-    std::lock_guard<std::mutex> g(c.mem_mu);
-    out->hbm_limit = c.hbm_limit;
-    out->hbm_in_use = c.in_use;
-    out->hbm_high_water = c.high_water;
-  }
+  const MemLedger::Snapshot m = c.mem.snapshot();
+  out->hbm_limit = m.limit;
+  out->hbm_in_use = m.in_use;
+  out->hbm_high_water = m.high_water;
   c.sched->fill_stats(out);
   return RPA_OK;
 }

@@ -241,4 +241,8 @@ hipError_t launch_quadrature(hipStream_t s, const double *eps, const double *zet
 hipError_t launch_widen(hipStream_t s, const double *in, double2 *out, int64_t n);
 hipError_t launch_narrow(hipStream_t s, const double2 *in, double *out, int64_t n);
 
+// Fill `bytes` of device memory at p with 0xFF bytes (a NaN in FP64, FP32, FP16 and BF16),
+// for the RPA_POISON debugging mode.
+hipError_t launch_poison_fill(hipStream_t s, void *p, int64_t bytes);
+
 }  // namespace rpa

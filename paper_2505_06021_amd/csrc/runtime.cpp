@@ -34,42 +34,33 @@ int fail(int code, const char *fmt, ...) {
   return code;
 }
 
-double now_seconds() {
-  using namespace std::chrono;
-  return duration<double>(steady_clock::now().time_since_epoch()).count();
-}
-
 // ---- device memory ----------------------------------------------------------------
-namespace {
-// What admitted serving jobs may still allocate (mem_mu held).
-int64_t outstanding_locked(const Ctx &c) {
-  return std::max<int64_t>(0, c.reserved - (c.in_use - c.cached_bytes));
-}
-}  // namespace
-
 int Ctx::alloc(DevBuf &b, int64_t bytes, const char *what, bool cached) {
   if (bytes <= 0) bytes = 256;
-  {
-    std::lock_guard<std::mutex> g(mem_mu);
-    const int64_t held = in_use + (cached ? outstanding_locked(*this) : 0);
-    if (held + bytes > hbm_limit)
-      return fail(RPA_E_NOMEM, "%s: %lld bytes requested, %lld of %lld in use or reserved", what,
-                  (long long)bytes, (long long)held, (long long)hbm_limit);
-    in_use += bytes;
-    if (cached) cached_bytes += bytes;
-    high_water = std::max(high_water, in_use);
-  }
+  if (faults.alloc_fails()) return fail(RPA_E_NOMEM, "%s: allocation failure injected by RPA_FAULT", what);
+  int64_t held = 0;
+  if (!mem.charge(bytes, cached, &held))
+    return fail(RPA_E_NOMEM, "%s: %lld bytes requested, %lld of %lld in use or reserved", what, (long long)bytes,
+                (long long)held, (long long)mem.limit());
   hipError_t e = hipMalloc(&b.p, (size_t)bytes);
+  if (e == hipSuccess && poison) {
+    // a fill kernel on the legacy stream, waited for here: nothing else knows this buffer yet
+    e = launch_poison_fill(nullptr, b.p, bytes);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) {
+      (void)hipFree(b.p);
+      mem.refund(bytes, cached);
+      b.p = nullptr;
+      return fail(RPA_E_DEVICE, "%s: poison fill failed: %s", what, hipGetErrorString(e));
+    }
+  }
   if (e != hipSuccess) {
-    std::lock_guard<std::mutex> g(mem_mu);
-    in_use -= bytes;
-    if (cached) cached_bytes -= bytes;
+    mem.refund(bytes, cached);
     b.p = nullptr;
     (void)hipGetLastError();
     return fail(e == hipErrorOutOfMemory ? RPA_E_NOMEM : RPA_E_DEVICE, "%s: hipMalloc(%lld) failed: %s",
                 what, (long long)bytes, hipGetErrorString(e));
   }
-  std::lock_guard<std::mutex> g(mem_mu);
   b.bytes = bytes;
   b.cached = cached;
   return RPA_OK;
@@ -78,9 +69,7 @@ int Ctx::alloc(DevBuf &b, int64_t bytes, const char *what, bool cached) {
 void Ctx::release(DevBuf &b) {
   if (!b.p) return;
   (void)hipFree(b.p);
-  std::lock_guard<std::mutex> g(mem_mu);
-  in_use -= b.bytes;
-  if (b.cached) cached_bytes -= b.bytes;
+  mem.refund(b.bytes, b.cached);
   b.p = nullptr;
   b.bytes = 0;
   b.cached = false;
@@ -140,33 +129,6 @@ int Ctx::prof_collect() {
   }
   prof_pending.clear();
   return RPA_OK;
-}
-
-bool Ctx::would_fit(int64_t extra) {
-  std::lock_guard<std::mutex> g(mem_mu);
-  return in_use + outstanding_locked(*this) + extra <= hbm_limit;
-}
-
-int64_t Ctx::sync_budget() {
-  // Everything outside the cache belongs to admitted jobs and lies within their
-  // reservations, so what a synchronous call may hold, its cache included, is the limit
-  // minus the reservations.
-  std::lock_guard<std::mutex> g(mem_mu);
-  return hbm_limit - std::max<int64_t>(reserved, in_use - cached_bytes);
-}
-
-bool Ctx::try_reserve(int64_t need, int64_t *cached_out) {
-  std::lock_guard<std::mutex> g(mem_mu);
-  if (cached_out) *cached_out = cached_bytes;
-  // synchronous-call caches stay allocated; everything else in use is reserved by jobs
-  if (need > hbm_limit - cached_bytes - reserved) return false;
-  reserved += need;
-  return true;
-}
-
-void Ctx::unreserve(int64_t need) {
-  std::lock_guard<std::mutex> g(mem_mu);
-  reserved -= need;
 }
 
 // ---- validation -----------------------------------------------------------------

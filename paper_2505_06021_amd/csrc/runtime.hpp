@@ -17,6 +17,7 @@
 
 #include "../../include/rpa.h"
 #include "common.hpp"
+#include "serve_core.hpp"
 
 namespace rpa {
 
@@ -39,7 +40,6 @@ int fail(int code, const char *fmt, ...);
     if (rc_ != RPA_OK) return rc_; \
   } while (0)
 
-double now_seconds();
 
 class Scheduler;
 
@@ -55,16 +55,12 @@ struct Ctx {
   hipStream_t own_stream = nullptr;
   hipStream_t stream = nullptr;     // stream of synchronous calls
   std::mutex mu;                    // serialises synchronous calls on this context
-  // Device-memory accounting, guarded by mem_mu.  in_use counts every allocation;
-  // cached_bytes the part held by the workspace cache of synchronous calls; reserved the
-  // footprints of the serving jobs admitted so far (each job allocates at most its own,
-  // so reserved - (in_use - cached_bytes) is what admitted jobs may still allocate).
-  std::mutex mem_mu;
-  int64_t hbm_limit = 0;
-  int64_t in_use = 0;
-  int64_t high_water = 0;
-  int64_t cached_bytes = 0;
-  int64_t reserved = 0;
+  // Device-memory accounting (limit, in use, cached workspaces, job reservations).
+  MemLedger mem;
+  // RPA_FAULT: injected allocation failures; RPA_POISON=1: every new device allocation is
+  // filled with 0xFF bytes (NaN in every floating-point format used here) before use.
+  FaultPlan faults;
+  bool poison = false;
   // Grow-only workspaces of synchronous calls.  The map itself is only read or changed
   // by a thread holding `mu`; other threads read cached_bytes instead.
   std::map<std::string, DevBuf> cache;
@@ -92,15 +88,6 @@ struct Ctx {
   // Cached workspace of at least `bytes` (device), reused across synchronous calls.
   int workspace(const char *name, int64_t bytes, void **out);
   void free_cache();
-  // Whether a synchronous call may allocate `extra` more bytes now.
-  bool would_fit(int64_t extra);
-  // Device bytes a synchronous call may plan with: the limit minus the serving jobs'
-  // reservations (the call's own cached workspaces count as available).
-  int64_t sync_budget();
-  // Free part of the limit for admitting a serving job of `need` bytes: if it fits, the
-  // need is added to `reserved` in the same critical section and true is returned.
-  bool try_reserve(int64_t need, int64_t *cached_out);
-  void unreserve(int64_t need);
 };
 
 // ---- staged system ----------------------------------------------------------------

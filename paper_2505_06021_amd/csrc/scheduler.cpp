@@ -9,7 +9,6 @@
 namespace rpa {
 
 struct Scheduler::Job {
-  uint64_t id = 0;
   // owned host copies of the inputs
   std::vector<int32_t> kq;
   std::vector<double> eps_occ, eps_virt, zeta_k, zeta_q, omega, weight;
@@ -17,14 +16,10 @@ struct Scheduler::Job {
   rpa_system sys{};
   HostSmall hs;
   rpa_precision prec = RPA_FP64;
-  int64_t need = 0;
+  int64_t need = 0;   // device footprint, reserved while the job runs
   // outcome
-  int status = RPA_PENDING;
   double E = 0.0;
   std::vector<double> eps;
-  double t_submit = 0, t_start = 0, t_done = 0;
-  bool finished = false;
-  std::string err;
 };
 
 namespace {
@@ -32,6 +27,12 @@ int worker_count() {
   const char *s = getenv("RPA_SERVE_WORKERS");
   int n = s ? atoi(s) : 4;
   return std::max(1, std::min(n, 16));
+}
+
+// How long a queued job may be passed by later jobs that fit before it (milliseconds).
+int hold_ms() {
+  const char *s = getenv("RPA_SERVE_HOLD_MS");
+  return s ? std::max(0, atoi(s)) : 60000;
 }
 
 template <class T>
@@ -47,7 +48,7 @@ int copy_array(std::vector<T> &dst, const T *src, size_t n, int memspace) {
 }
 }  // namespace
 
-Scheduler::Scheduler(Ctx &c) : ctx_(c) {}
+Scheduler::Scheduler(Ctx &c) : ctx_(c), queue_(*this, worker_count(), 20, hold_ms()) {}
 
 Scheduler::~Scheduler() { shutdown(); }
 
@@ -86,16 +87,6 @@ int64_t Scheduler::footprint(const HostSmall &hs, int nw, rpa_precision prec, in
   return small + per_q + (int64_t)nw * per_pt + split_extra + 24 * 4096;
 }
 
-void Scheduler::start_locked() {
-  if (started_) return;
-  started_ = true;
-  int ncu = 0;
-  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx_.device) != hipSuccess) ncu = 256;
-  fuser_ = fuser_create(ctx_.device, ncu);   // null: every contraction launches alone
-  const int n = worker_count();
-  for (int w = 0; w < n; ++w) workers_.emplace_back(&Scheduler::worker, this, w);
-}
-
 int Scheduler::submit(const rpa_system *sys, const rpa_freq *freq, rpa_precision prec, uint64_t *id) {
   if (!id) return fail(RPA_E_ARG, "job_id pointer is NULL");
   if (prec != RPA_FP64 && prec != RPA_FP32 && prec != RPA_BF16X3 && prec != RPA_F16X3)
@@ -110,12 +101,13 @@ int Scheduler::submit(const rpa_system *sys, const rpa_freq *freq, rpa_precision
   const int64_t N = hs.naux;
   const int64_t M = (int64_t)hs.nk * hs.nocc * hs.nvirt;
   const int64_t belem = hs.is_complex ? 16 : 8;
-  j->need = footprint(hs, freq->nw, prec, hs.nk);
+  const int64_t lim = ctx_.mem.limit();
+  int64_t need = footprint(hs, freq->nw, prec, hs.nk);
   // a job whose whole q does not fit the limit streams its q's one k-point at a time
-  if (j->need > ctx_.hbm_limit) j->need = footprint(hs, freq->nw, prec, 1);
-  if (j->need > ctx_.hbm_limit)
-    return fail(RPA_E_NOMEM, "job needs %lld device bytes, above the limit %lld", (long long)j->need,
-                (long long)ctx_.hbm_limit);
+  if (need > lim) need = footprint(hs, freq->nw, prec, 1);
+  if (need > lim)
+    return fail(RPA_E_NOMEM, "job needs %lld device bytes, above the limit %lld", (long long)need,
+                (long long)lim);
   j->kq = hs.kq;
   j->eps_occ = hs.eps_occ;
   j->eps_virt = hs.eps_virt;
@@ -146,164 +138,123 @@ int Scheduler::submit(const rpa_system *sys, const rpa_freq *freq, rpa_precision
   s.c_virt = j->hs.nbas > 0 ? (const void *)j->hs.c_virt.data() : nullptr;
   s.S_ao = j->hs.S.empty() ? nullptr : (const void *)j->hs.S.data();
   j->prec = prec;
-  j->t_submit = now_seconds();
-  std::lock_guard<std::mutex> g(mu_);
-  if (stop_) return fail(RPA_E_CANCELLED, "context is shutting down");
-  j->id = next_id_++;
-  *id = j->id;
-  Job *raw = j.release();
-  jobs_[raw->id] = raw;
-  queue_.push_back(raw);
-  ++submitted_;
-  start_locked();
-  cv_work_.notify_one();
+  j->need = need;
+  const int rc = queue_.submit(j.get(), need, id);
+  if (rc == RPA_E_CANCELLED) return fail(rc, "context is shutting down");
+  if (rc != RPA_OK) return fail(rc, "job of %lld device bytes refused", (long long)need);
+  j.release();   // the queue owns it now
   return RPA_OK;
 }
 
-Scheduler::Job *Scheduler::pick_locked() {
-  for (int attempt = 0; attempt < 2; ++attempt) {
-    // the first queued job whose footprint fits is reserved in the same critical section
-    // of the context's memory lock as the check, so a synchronous call planning at the
-    // same time already sees the reservation
-    int64_t cached = 0;
-    for (auto it = queue_.begin(); it != queue_.end(); ++it) {
-      if (ctx_.try_reserve((*it)->need, &cached)) {
-        Job *j = *it;
-        queue_.erase(it);
-        return j;
-      }
-    }
-    // nothing fits: if the workspace cache of the synchronous calls is in the way and no
-    // synchronous call is running (try_lock never waits), release it and look again
-    if (attempt > 0 || cached == 0 || !ctx_.mu.try_lock()) break;
-    ctx_.free_cache();
-    ctx_.mu.unlock();
-  }
-  return nullptr;
+// ---- ServeBackend: what a job does on the device ------------------------------------
+
+int64_t Scheduler::limit() { return ctx_.mem.limit(); }
+
+bool Scheduler::try_reserve(int64_t need, int64_t *cached_out) { return ctx_.mem.try_reserve(need, cached_out); }
+
+void Scheduler::unreserve(int64_t need) { ctx_.mem.unreserve(need); }
+
+bool Scheduler::release_cache() {
+  // only when no synchronous call is running: try_lock never waits
+  if (!ctx_.mu.try_lock()) return false;
+  const bool any = !ctx_.cache.empty();
+  ctx_.free_cache();
+  ctx_.mu.unlock();
+  return any;
 }
 
-void Scheduler::worker(int w) {
-  (void)w;
+void Scheduler::start() {
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx_.device) != hipSuccess) ncu = 256;
+  fuser_.store(fuser_create(ctx_.device, ncu));   // null: every contraction launches alone
+}
+
+void Scheduler::stop() {
+  fuser_destroy(fuser_.exchange(nullptr));
+}
+
+void *Scheduler::worker_begin(int) {
   (void)hipSetDevice(ctx_.device);
   hipStream_t st = nullptr;
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
-  for (;;) {
-    Job *j = nullptr;
-    {
-      std::unique_lock<std::mutex> lk(mu_);
-      cv_work_.wait(lk, [&] { return stop_ || (!queue_.empty() && (j = pick_locked()) != nullptr); });
-      if (!j) {
-        if (stop_) break;
-        continue;
-      }
-      ++running_;
-    }
-    j->t_start = now_seconds();
-    int rc;
-    if (!st) {
-      rc = fail(RPA_E_DEVICE, "worker stream could not be created");
-    } else {
-      PointJob pj;
-      pj.sys = &j->sys;
-      pj.hs = &j->hs;
-      pj.prec = j->prec;
-      for (int q = 0; q < j->hs.nq; ++q)
-        for (double om : j->omega) {
-          pj.pq.push_back(q);
-          pj.pw.push_back(om);
-        }
-      pj.quadrature = true;
-      pj.weight = j->weight;
-      pj.max_q_group = 1;
-      pj.fuser = fuser_;
-      // every precision's small contractions may be fused with other jobs' of their kind
-      fuser_register(fuser_, +1);
-      rc = run_points(ctx_, st, pj, j->need, false);
-      fuser_register(fuser_, -1);
-      if (rc == RPA_OK) {
-        j->E = pj.E;
-        j->eps = std::move(pj.eps);
-      }
-    }
-    {
-      std::lock_guard<std::mutex> g(mu_);
-      j->status = rc;
-      if (rc != RPA_OK) j->err = last_error();
-      j->t_done = now_seconds();
-      j->finished = true;
-      ctx_.unreserve(j->need);
-      --running_;
-      ++done_;
-      // free the inputs now; the record stays until it is polled
-      std::vector<char>().swap(j->B);
-      std::vector<char>().swap(j->vhalf);
-    }
-    cv_done_.notify_all();
-    cv_work_.notify_all();
-  }
-  if (st) (void)hipStreamDestroy(st);
+  return (void *)st;
 }
+
+void Scheduler::worker_end(void *state) {
+  if (state) (void)hipStreamDestroy((hipStream_t)state);
+}
+
+int Scheduler::run(void *state, void *payload, std::string *err) {
+  Job *j = (Job *)payload;
+  hipStream_t st = (hipStream_t)state;
+  int rc;
+  if (!st) {
+    rc = fail(RPA_E_DEVICE, "worker stream could not be created");
+  } else {
+    PointJob pj;
+    pj.sys = &j->sys;
+    pj.hs = &j->hs;
+    pj.prec = j->prec;
+    for (int q = 0; q < j->hs.nq; ++q)
+      for (double om : j->omega) {
+        pj.pq.push_back(q);
+        pj.pw.push_back(om);
+      }
+    pj.quadrature = true;
+    pj.weight = j->weight;
+    pj.max_q_group = 1;
+    pj.fuser = fuser_.load();
+    // every precision's small contractions may be fused with other jobs' of their kind
+    fuser_register(pj.fuser, +1);
+    rc = run_points(ctx_, st, pj, j->need, false);   // within the job's reservation
+    fuser_register(pj.fuser, -1);
+    if (rc == RPA_OK) {
+      j->E = pj.E;
+      j->eps = std::move(pj.eps);
+    }
+  }
+  if (rc != RPA_OK) *err = last_error();
+  return rc;
+}
+
+void Scheduler::retire(void *payload) {
+  Job *j = (Job *)payload;
+  std::vector<char>().swap(j->B);
+  std::vector<char>().swap(j->vhalf);
+}
+
+void Scheduler::destroy(void *payload) { delete (Job *)payload; }
 
 int Scheduler::poll(uint64_t id, int32_t timeout_ms, rpa_result *out, double *eps_qw) {
   if (!out) return fail(RPA_E_ARG, "result pointer is NULL");
-  std::unique_lock<std::mutex> lk(mu_);
-  auto it = jobs_.find(id);
-  if (it == jobs_.end()) return fail(RPA_E_UNKNOWN_JOB, "job %llu is unknown or already consumed",
-                                     (unsigned long long)id);
-  Job *j = it->second;
-  auto done = [&] { return j->finished; };
-  if (!done()) {
-    if (timeout_ms == 0) return RPA_PENDING;
-    if (timeout_ms < 0) cv_done_.wait(lk, done);
-    else if (!cv_done_.wait_for(lk, std::chrono::milliseconds(timeout_ms), done)) return RPA_PENDING;
-  }
-  out->E = j->E;
-  out->status = j->status;
-  out->npoints = j->hs.nq * (int32_t)j->omega.size();
-  out->t_submit = j->t_submit;
-  out->t_start = j->t_start;
-  out->t_done = j->t_done;
-  out->hbm_bytes = j->need;
-  if (eps_qw && j->status == RPA_OK) memcpy(eps_qw, j->eps.data(), j->eps.size() * 8);
-  const int st = j->status;
-  const std::string err = j->err;
-  jobs_.erase(it);
-  delete j;
-  if (st != RPA_OK) set_error("%s", err.c_str());
+  std::string err;
+  const int st = queue_.poll(id, timeout_ms, [&](const ServeQueue::Record &r) {
+    const Job *j = (const Job *)r.payload;
+    out->E = j->E;
+    out->status = r.status;
+    out->npoints = j->hs.nq * (int32_t)j->omega.size();
+    out->t_submit = r.t_submit;
+    out->t_start = r.t_start;
+    out->t_done = r.t_done;
+    out->hbm_bytes = r.need;
+    if (eps_qw && r.status == RPA_OK) memcpy(eps_qw, j->eps.data(), j->eps.size() * 8);
+    err = *r.err;
+  });
+  if (st == RPA_E_UNKNOWN_JOB)
+    return fail(st, "job %llu is unknown or already consumed", (unsigned long long)id);
+  if (st != RPA_OK && st != RPA_PENDING) set_error("%s", err.c_str());
   return st;
 }
 
 void Scheduler::fill_stats(rpa_stats *out) {
-  std::lock_guard<std::mutex> g(mu_);
-  out->jobs_submitted = submitted_;
-  out->jobs_done = done_;
-  out->jobs_running = running_;
-  out->jobs_queued = (int64_t)queue_.size();
-  fuser_stats(fuser_, &out->fused_launches, &out->fused_groups, &out->solo_groups);
+  const ServeQueue::Counts n = queue_.counts();
+  out->jobs_submitted = n.submitted;
+  out->jobs_done = n.done;
+  out->jobs_running = n.running;
+  out->jobs_queued = n.queued;
+  fuser_stats(fuser_.load(), &out->fused_launches, &out->fused_groups, &out->solo_groups);
 }
 
-void Scheduler::shutdown() {
-  {
-    std::lock_guard<std::mutex> g(mu_);
-    if (stop_ && workers_.empty()) return;
-    stop_ = true;
-    for (Job *j : queue_) {
-      j->status = RPA_E_CANCELLED;
-      j->err = "cancelled by rpa_finalize";
-      j->finished = true;
-      j->t_done = now_seconds();
-    }
-    queue_.clear();
-  }
-  cv_work_.notify_all();
-  cv_done_.notify_all();
-  for (auto &t : workers_) t.join();
-  workers_.clear();
-  fuser_destroy(fuser_);
-  fuser_ = nullptr;
-  std::lock_guard<std::mutex> g(mu_);
-  for (auto &kv : jobs_) delete kv.second;
-  jobs_.clear();
-}
+void Scheduler::shutdown() { queue_.shutdown(); }
 
 }  // namespace rpa

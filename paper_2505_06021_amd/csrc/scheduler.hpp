@@ -9,17 +9,18 @@
 // call on buffers the job owns, so a job's result does not depend on what runs beside it.
 // Small contraction launches of jobs in flight (split 16-bit, paired FP64 and paired FP32)
 // are fused into one launch per kind (fuser.cpp), which changes when they run, never what
-// they compute.
+// they compute.  The queue, the admission and the cancellation are host-only
+// (serve_core.hpp); this file adds what runs on the device.
 #pragma once
 
 #include "runtime.hpp"
 
 namespace rpa {
 
-class Scheduler {
+class Scheduler : private ServeBackend {
  public:
   explicit Scheduler(Ctx &c);
-  ~Scheduler();
+  ~Scheduler() override;
   int submit(const rpa_system *sys, const rpa_freq *freq, rpa_precision prec, uint64_t *id);
   int poll(uint64_t id, int32_t timeout_ms, rpa_result *out, double *eps_qw);
   void fill_stats(rpa_stats *out);
@@ -31,22 +32,22 @@ class Scheduler {
 
  private:
   struct Job;
-  void worker(int w);
-  Job *pick_locked();
+  // ServeBackend
+  int64_t limit() override;
+  bool try_reserve(int64_t need, int64_t *cached_out) override;
+  void unreserve(int64_t need) override;
+  bool release_cache() override;
+  void start() override;
+  void stop() override;
+  void *worker_begin(int w) override;
+  void worker_end(void *state) override;
+  int run(void *state, void *payload, std::string *err) override;
+  void retire(void *payload) override;
+  void destroy(void *payload) override;
 
   Ctx &ctx_;
-  std::mutex mu_;
-  std::condition_variable cv_work_;
-  std::condition_variable cv_done_;
-  std::deque<Job *> queue_;
-  std::map<uint64_t, Job *> jobs_;
-  std::vector<std::thread> workers_;
-  uint64_t next_id_ = 1;
-  int64_t submitted_ = 0, done_ = 0, running_ = 0;
-  bool stop_ = false;
-  bool started_ = false;
-  Fuser *fuser_ = nullptr;   // cross-job fusion of small contraction launches
-  void start_locked();
+  std::atomic<Fuser *> fuser_{nullptr};   // cross-job fusion of small contraction launches (null until the first job)
+  ServeQueue queue_;
 };
 
 }  // namespace rpa
