@@ -37,27 +37,13 @@ __device__ __forceinline__ void tile_of(int t, int &tr, int &tc) {
   tc = t - r * (r + 1) / 2;
 }
 
-// Load rows [r0, r0+64) x columns [c0, c0+kw) of an n x n matrix into lds[row][k]
-// (zero outside the matrix or beyond kw).  Four lanes per row, 16 consecutive columns
-// each, so a row's 1 KB is read contiguously.
-__device__ __forceinline__ void load_block(double2 (*lds)[LP], const double2 *A, int n, int r0, int c0,
-                                           int kw) {
-  const int t = threadIdx.x;
-  const int r = t >> 2, kq = (t & 3) * 16;
-  const bool rv = r0 + r < n;
-#pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int k = kq + e;
-    lds[r][k] = (rv && k < kw) ? A[(int64_t)(r0 + r) * n + c0 + k] : make_double2(0.0, 0.0);
-  }
-}
-
-// acc[i][j] += sum_k A[i][k] conj(B[j][k]) over k < 64, for the 32 x 32 sub-tile of wave
+// acc[i][j] += sum_k A[i][k] conj(B[j][k]) over k < K, for the 32 x 32 sub-tile of wave
 // (wr, wc): 2 x 2 blocks of 16 x 16, lane (li, lk) of a block supplies row li, k = lk.
-__device__ __forceinline__ void cgemm_nt(const double2 (*A)[LP], const double2 (*B)[LP], int wr, int wc,
-                                         int li, int lk, d4 (&accR)[2][2], d4 (&accI)[2][2]) {
+template <int K, int P>
+__device__ __forceinline__ void cgemm_nt(const double2 (*A)[P], const double2 (*B)[P], int wr, int wc, int li,
+                                         int lk, d4 (&accR)[2][2], d4 (&accI)[2][2]) {
 #pragma unroll 4
-  for (int ks = 0; ks < NB / 4; ++ks) {
+  for (int ks = 0; ks < K / 4; ++ks) {
     double2 a[2], b[2];
 #pragma unroll
     for (int x = 0; x < 2; ++x) a[x] = A[wr * 32 + x * 16 + li][ks * 4 + lk];
@@ -100,113 +86,201 @@ __global__ __launch_bounds__(256) void chol_init_kernel(const double2 *W, int64_
   }
 }
 
-// Factor the diagonal block at column j0 of matrix b (pivots 1 + d, log1p of them into
-// logacc[b], the factor's inverse L11^-1 into linv); D and X are two NB x LP LDS arrays
-// of the calling kernel.  A failing pivot records its column in info[b].  Called by the
-// whole workgroup (every branch on the pivot is uniform).
-__device__ __forceinline__ void diag_block(double2 *W, int64_t stride, int n, int j0, int b, double *logacc,
-                                           int32_t *info, double2 *linv, double2 (*D)[LP], double2 (*X)[LP]) {
-  __shared__ double2 colbuf[2][NB];
-  __shared__ double ld[NB];
-  double2 *A = W + (int64_t)b * stride;
-  const int jb = min(NB, n - j0);
-  const int tid = threadIdx.x;
-  // Thread tid owns column s = tid % 64 and rows r = tid / 64 + 4 j (j < 16) of the block,
-  // kept in registers; only the current pivot column passes through LDS.
-  const int s = tid & 63, r0 = tid >> 6;
-  double2 v[16];
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const int r = r0 + 4 * j;
-    v[j] = (r < jb && s <= r) ? A[(int64_t)(j0 + r) * n + j0 + s] : make_double2(0.0, 0.0);
-  }
-  for (int e = tid; e < NB * NB; e += 256) X[e / NB][e % NB] = make_double2(0.0, 0.0);
-  // the pivots' d_c are kept in LDS; their square roots and log1p terms are taken after
-  // the loop, in parallel, so no transcendental sits between two barriers
-  __shared__ double dpiv[NB];
-  for (int c = 0; c < jb; ++c) {
-    double2 *cb = colbuf[c & 1];
-    if (s == c) {
-#pragma unroll
-      for (int j = 0; j < 16; ++j) cb[r0 + 4 * j] = v[j];   // column c is final
+// Order this wave's LDS writes before its later LDS reads of other lanes' data (one wave
+// issues its LDS instructions in order; the fences keep the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wave: acc += A[ra + i][ca + k] conj(B[rb + j][cb + k]) over k < K (nt) or
+// acc += A[ra + i][ca + k] B[rb + k][cb + j] (nn) for a 16 x 16 block; lane (li, lk)
+// holds output rows lk + 4 r of column li.
+template <bool NT>
+__device__ __forceinline__ void mm16(const double2 (*A)[LP], int ra, int ca, const double2 (*B)[LP], int rb, int cb,
+                                     int K, int li, int lk, d4 &accR, d4 &accI) {
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const double2 a = A[ra + li][ca + k0 + lk];
+    const double2 b = NT ? B[rb + li][cb + k0 + lk] : B[rb + k0 + lk][cb + li];
+    if (NT) {
+      // a conj(b) = (ar br + ai bi) + i (ai br - ar bi)
+      accR = mfma(a.x, b.x, accR);
+      accR = mfma(a.y, b.y, accR);
+      accI = mfma(a.y, b.x, accI);
+      accI = mfma(-a.x, b.y, accI);
+    } else {
+      // a b = (ar br - ai bi) + i (ar bi + ai br)
+      accR = mfma(a.x, b.x, accR);
+      accR = mfma(-a.y, b.y, accR);
+      accI = mfma(a.x, b.y, accI);
+      accI = mfma(a.y, b.x, accI);
     }
-    __syncthreads();
+  }
+}
+
+// Factor the 16 x 16 diagonal sub-block at (c0, c0) of D (already updated by the earlier
+// sub-panels) and invert it, by one wave with no workgroup barrier.  Lane (j, g) keeps
+// column j, rows g + 4 t (t < 4), of the block in v and of M in m, in registers; column c
+// of W and row c of M go through LDS at step c.  The inverse is built alongside the
+// factor (Gauss-Jordan): the elimination's row operations, applied to the identity, give
+// M = U^-1 for the unit lower factor U of I + W = U diag(piv) U^H, and L^-1 =
+// diag(piv)^-1/2 M.  On return D holds L there (l_c on the diagonal, zero above it), X
+// the inverse, dpiv the pivots' d_c and lpiv their l_c; *fail the first failing column.
+__device__ __forceinline__ void factor16(double2 (*D)[LP], double2 (*X)[LP], int c0, int lane, double *dpiv,
+                                         double *lpiv, double2 (*colbuf)[16], double2 (*rowbuf)[16], int *fail) {
+  const int j = lane & 15, g = lane >> 4;
+  double2 v[4], m[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int i = g + 4 * t;
+    v[t] = i >= j ? D[c0 + i][c0 + j] : make_double2(0.0, 0.0);
+    m[t] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    double2 *cb = colbuf[c & 1], *rb = rowbuf[c & 1];
+    if (j == c) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) cb[g + 4 * t] = v[t];   // column c of W is final
+    }
+    if (g == (c & 3)) rb[j] = m[c >> 2];                  // so is row c of M
+    wave_lds_sync();
     const double d = cb[c].x;
     const double piv = 1.0 + d;
     if (!(piv > 0.0) || !(piv < INFINITY)) {
-      if (tid == 0) info[b] = j0 + c;
-      return;   // uniform: every thread read the same pivot
+      if (lane == 0) *fail = c0 + c;
+      return;   // uniform: every lane read the same pivot
     }
-    if (tid == 0) dpiv[c] = d;
-    if (s > c && s < jb) {
-      // W[r][s] -= W[r][c] conj(W[s][c]) / piv for r >= s
-      const double2 ys = cb[s];
-      const double ip = 1.0 / piv;
-      const double yr = ys.x * ip, yi = ys.y * ip;
+    if (lane == 0) dpiv[c0 + c] = d;
+    const double ip = 1.0 / piv;
+    const double2 mc = rb[j];
+    const double2 ys = cb[j];
+    const double yr = ys.x * ip, yi = ys.y * ip;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const int r = r0 + 4 * j;
-        if (r >= s && r < jb) {
-          const double2 x = cb[r];
-          v[j].x -= x.x * yr + x.y * yi;
-          v[j].y -= x.y * yr - x.x * yi;
+    for (int t = 0; t < 4; ++t) {
+      const int i = g + 4 * t;
+      if (i > c) {
+        const double2 x = cb[i];
+        // M[i][j] -= (W[i][c] / piv) M[c][j]
+        const double ur = x.x * ip, ui = x.y * ip;
+        m[t].x -= ur * mc.x - ui * mc.y;
+        m[t].y -= ur * mc.y + ui * mc.x;
+        // W[i][j] -= W[i][c] conj(W[j][c]) / piv for i >= j > c
+        if (j > c && i >= j) {
+          v[t].x -= x.x * yr + x.y * yi;
+          v[t].y -= x.y * yr - x.x * yi;
         }
       }
     }
   }
-  __syncthreads();
-  if (tid < jb) {
-    ld[tid] = sqrt(1.0 + dpiv[tid]);
-    dpiv[tid] = log1p(dpiv[tid]);
+  if (lane < 16) lpiv[c0 + lane] = sqrt(1.0 + dpiv[c0 + lane]);
+  wave_lds_sync();
+  // L[i][j] = W[i][j] / l_j below the diagonal, l_j on it; X[i][j] = M[i][j] / l_i
+  const double lj = lpiv[c0 + j];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int i = g + 4 * t;
+    const double li = lpiv[c0 + i];
+    D[c0 + i][c0 + j] = i > j ? make_double2(v[t].x / lj, v[t].y / lj)
+                              : (i == j ? make_double2(lj, 0.0) : make_double2(0.0, 0.0));
+    X[c0 + i][c0 + j] = i >= j ? make_double2(m[t].x / li, m[t].y / li) : make_double2(0.0, 0.0);
   }
+}
+
+// Factor the diagonal block at column j0 of matrix b (pivots 1 + d, log1p of them into
+// logacc[b], the factor's inverse L11^-1 into linv); D and X are two NB x LP LDS arrays
+// of the calling kernel.  A failing pivot records its column in info[b].  Called by the
+// whole workgroup.
+//
+// The block is factored in four 16-column sub-panels p (right-looking, with its inverse
+// built alongside):  (a) one wave factors and inverts the 16 x 16 diagonal sub-block;
+// (b) the sub-panel below it, L_qp = W_qp X_pp^H, and T_pj = sum_{j<=k<p} L_pk X_kj for
+// the inverse's row p, as 16 x 16 complex MFMA products spread over the waves; (c) the
+// trailing update W_ab -= L_ap L_bp^H of the sub-blocks to the right, and the inverse's
+// row p, X_pj = -X_pp T_pj.  Three workgroup barriers per sub-panel.  Rows and columns at
+// and beyond jb hold zeros: their pivots are 1 and add log1p(0) = 0.
+__device__ __forceinline__ void diag_block(double2 *W, int64_t stride, int n, int j0, int b, double *logacc,
+                                           int32_t *info, double2 *linv, double2 (*D)[LP], double2 (*X)[LP]) {
+  __shared__ double2 colbuf[2][16], rowbuf[2][16];
+  __shared__ double dpiv[NB], lpiv[NB];
+  __shared__ int fail;
+  double2 *A = W + (int64_t)b * stride;
+  const int jb = min(NB, n - j0);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int r = e / NB, s = e % NB;
+    D[r][s] = (r < jb && s <= r) ? A[(int64_t)(j0 + r) * n + j0 + s] : make_double2(0.0, 0.0);
+    X[r][s] = make_double2(0.0, 0.0);
+  }
+  if (tid < NB) dpiv[tid] = 0.0;
+  if (tid == 0) fail = -1;
+  __syncthreads();
+  const int np = (jb + 15) / 16;
+  for (int p = 0; p < np; ++p) {
+    const int c0 = 16 * p;
+    // (a)
+    if (wave == 0) factor16(D, X, c0, lane, dpiv, lpiv, colbuf, rowbuf, &fail);
+    __syncthreads();
+    if (fail >= 0) {
+      if (tid == 0) info[b] = j0 + fail;
+      return;   // uniform
+    }
+    // (b) tasks: sub-panel blocks q = p+1..3, then T_pj for j = 0..p-1
+    {
+      const int npanel = 3 - p;
+      for (int task = wave; task < npanel + p; task += 4) {
+        d4 accR = {0.0, 0.0, 0.0, 0.0}, accI = {0.0, 0.0, 0.0, 0.0};
+        int r0, cc;
+        if (task < npanel) {
+          r0 = 16 * (p + 1 + task);
+          cc = c0;
+          mm16<true>(D, r0, c0, X, c0, c0, 16, li, lk, accR, accI);
+        } else {
+          const int jj = task - npanel;
+          r0 = c0;
+          cc = 16 * jj;
+          mm16<false>(D, c0, 16 * jj, X, 16 * jj, 16 * jj, 16 * (p - jj), li, lk, accR, accI);
+        }
+        double2 (*O)[LP] = task < npanel ? D : X;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) O[r0 + lk + 4 * r][cc + li] = make_double2(accR[r], accI[r]);
+      }
+    }
+    __syncthreads();
+    // (c) tasks: trailing blocks (a, b) with p < b <= a <= 3, then X_pj = -X_pp T_pj
+    {
+      const int m = 3 - p, ntrail = m * (m + 1) / 2;
+      for (int task = wave; task < ntrail + p; task += 4) {
+        d4 accR = {0.0, 0.0, 0.0, 0.0}, accI = {0.0, 0.0, 0.0, 0.0};
+        if (task < ntrail) {
+          int ta, tb;
+          tile_of(task, ta, tb);
+          const int ra = 16 * (p + 1 + ta), rb = 16 * (p + 1 + tb);
+          mm16<true>(D, ra, c0, D, rb, c0, 16, li, lk, accR, accI);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            double2 &w = D[ra + lk + 4 * r][rb + li];
+            w = make_double2(w.x - accR[r], w.y - accI[r]);
+          }
+        } else {
+          const int jj = task - ntrail;
+          mm16<false>(X, c0, c0, X, c0, 16 * jj, 16, li, lk, accR, accI);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) X[c0 + lk + 4 * r][16 * jj + li] = make_double2(-accR[r], -accI[r]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (tid < jb) dpiv[tid] = log1p(dpiv[tid]);
   __syncthreads();
   if (tid == 0) {
-    // summed in column order, once per block: a global read-modify-write per column would
-    // make every barrier wait for memory
+    // summed in column order, once per block
     double lsum = 0.0;
     for (int c = 0; c < jb; ++c) lsum += dpiv[c];
     logacc[b] += lsum;
-  }
-  // the factor L11 into D: L[r][s] = W[r][s] / l_s below the diagonal, l_s on it
-  {
-    const double ls = s < jb ? ld[s] : 1.0;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int r = r0 + 4 * j;
-      D[r][s] = (r < jb && s < r) ? make_double2(v[j].x / ls, v[j].y / ls)
-                                  : (r == s && r < jb ? make_double2(ls, 0.0) : make_double2(0.0, 0.0));
-    }
-  }
-  __syncthreads();
-  // X = L11^{-1}, row by row: X[i][j] = -(sum_{k<i} L[i][k] X[k][j]) / l_i for j < i,
-  // X[i][i] = 1 / l_i.  X is zero above its diagonal, so every lane can run over all
-  // k < i: L[i][k] is a broadcast read, X[k][j] a conflict-free row read.  The 256
-  // threads split k into four interleaved partitions summed in a fixed order; row i is
-  // finished by the thread of partition i % 4, the only one that reads X[i][j] later, so
-  // one barrier per row suffices (the partial sums alternate between two buffers).
-  {
-    __shared__ double2 part[2][4][NB];
-    const int j = tid & 63, g = tid >> 6;
-    if (tid < jb) X[tid][tid] = make_double2(1.0 / ld[tid], 0.0);
-    __syncthreads();
-    for (int i = 1; i < jb; ++i) {
-      double sr = 0.0, si = 0.0;
-      for (int k = g; k < i; k += 4) {
-        const double2 lv = D[i][k], xv = X[k][j];
-        sr += lv.x * xv.x - lv.y * xv.y;
-        si += lv.x * xv.y + lv.y * xv.x;
-      }
-      double2 (*pp)[NB] = part[i & 1];
-      pp[g][j] = make_double2(sr, si);
-      __syncthreads();
-      if (g == (i & 3) && j < i) {
-        const double il = X[i][i].x;   // 1 / l_i
-        const double r = (pp[0][j].x + pp[1][j].x) + (pp[2][j].x + pp[3][j].x);
-        const double m = (pp[0][j].y + pp[1][j].y) + (pp[2][j].y + pp[3][j].y);
-        X[i][j] = make_double2(-r * il, -m * il);
-      }
-    }
-    __syncthreads();
   }
   double2 *out = linv + (int64_t)b * NB * NB;
   for (int e = tid; e < NB * NB; e += 256) out[e] = X[e / NB][e % NB];
@@ -221,25 +295,72 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(double2 *W, int64_t stri
   diag_block(W, stride, n, j0, b, logacc, info, linv, D, X);
 }
 
+// The 64 x 64 tile products of the panel and update kernels stream their K = 64 columns
+// in chunks of KC = 16: each chunk of both operands goes HBM -> registers -> LDS one chunk
+// ahead of the MFMAs that use it (double-buffered), so the loads of a chunk overlap the
+// products of the previous one.  Thread t stages row t / 4 and four consecutive columns.
+constexpr int KC = 16;
+constexpr int LPC = KC + 1;
+typedef double2 Chunk[NB][LPC];
+
+struct ChunkStage {
+  double2 ra[4], rb[4];
+  // rows [ra0, ra0 + 64) of A and [rb0, rb0 + 64) of B (pitches lda, ldb), columns
+  // [ca0 + KC kc, ...) and [cb0 + KC kc, ...); zero outside rows < nra (A), < nrb (B) and
+  // columns < kw
+  __device__ __forceinline__ void fetch(const double2 *A, int64_t lda, int ra0, int ca0, int nra, const double2 *B,
+                                        int64_t ldb, int rb0, int cb0, int nrb, bool has_b, int kw, int kc) {
+    const int t = threadIdx.x, r = t >> 2, q = (t & 3) * 4;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = kc * KC + q + e;
+      ra[e] = (ra0 + r < nra && k < kw) ? A[(int64_t)(ra0 + r) * lda + ca0 + k] : make_double2(0.0, 0.0);
+      if (has_b) rb[e] = (rb0 + r < nrb && k < kw) ? B[(int64_t)(rb0 + r) * ldb + cb0 + k] : make_double2(0.0, 0.0);
+    }
+  }
+  __device__ __forceinline__ void put(Chunk &ca, Chunk &cb, bool has_b) {
+    const int t = threadIdx.x, r = t >> 2, q = (t & 3) * 4;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      ca[r][q + e] = ra[e];
+      if (has_b) cb[r][q + e] = rb[e];
+    }
+  }
+};
+
+// acc += A B^H over k < kw for a 64 x 64 tile, A and B as above (B = A when !has_b); the
+// chunk buffers ca[2], cb[2] are LDS of the caller.  Ends with a barrier.
+__device__ __forceinline__ void tile_product(const double2 *A, int64_t lda, int ra0, int ca0, int nra,
+                                             const double2 *B, int64_t ldb, int rb0, int cb0, int nrb, bool has_b,
+                                             int kw, Chunk *ca, Chunk *cb, d4 (&accR)[2][2], d4 (&accI)[2][2]) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
+  const int nk = (kw + KC - 1) / KC;
+  ChunkStage st;
+  st.fetch(A, lda, ra0, ca0, nra, B, ldb, rb0, cb0, nrb, has_b, kw, 0);
+  st.put(ca[0], cb[0], has_b);
+  __syncthreads();
+  for (int kc = 0; kc < nk; ++kc) {
+    const int cur = kc & 1;
+    if (kc + 1 < nk) st.fetch(A, lda, ra0, ca0, nra, B, ldb, rb0, cb0, nrb, has_b, kw, kc + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    cgemm_nt<KC, LPC>(ca[cur], has_b ? cb[cur] : ca[cur], wr, wc, li, lk, accR, accI);
+    __builtin_amdgcn_sched_barrier(0);
+    if (kc + 1 < nk) st.put(ca[cur ^ 1], cb[cur ^ 1], has_b);
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(256) void chol_panel_kernel(double2 *W, int64_t stride, int n, int j0,
                                                          const int32_t *info, const double2 *linv) {
-  __shared__ double2 Ab[NB][LP];
-  __shared__ double2 Bb[NB][LP];
+  __shared__ Chunk ca[2], cb[2];   // 70 KB: two workgroups per CU
   const int b = blockIdx.y;
   if (info[b] >= 0) return;
   const int jb = min(NB, n - j0);
   const int r0 = j0 + jb + (int)blockIdx.x * NB;
   if (r0 >= n) return;
   double2 *A = W + (int64_t)b * stride;
-  load_block(Ab, A, n, r0, j0, jb);
-  {
-    const double2 *L = linv + (int64_t)b * NB * NB;
-    const int t = threadIdx.x;
-    const int r = t >> 2, kq = (t & 3) * 16;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) Bb[r][kq + e] = L[r * NB + kq + e];
-  }
-  __syncthreads();
+  const double2 *L = linv + (int64_t)b * NB * NB;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
   d4 accR[2][2], accI[2][2];
@@ -247,7 +368,9 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(double2 *W, int64_t str
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) accR[x][y] = accI[x][y] = d4{0.0, 0.0, 0.0, 0.0};
-  cgemm_nt(Ab, Bb, wr, wc, li, lk, accR, accI);
+  // L21 = W21 (L11^-1)^H: rows of W21 against the 64 rows of L11^-1 (columns < jb; the
+  // inverse is zero beyond)
+  tile_product(A, n, r0, j0, n, L, NB, 0, 0, NB, true, jb, ca, cb, accR, accI);
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -276,17 +399,10 @@ __global__ __launch_bounds__(256) void chol_update_kernel(double2 *W, int64_t st
   const int R0 = j0 + jb + tr * NB, S0 = j0 + jb + tc * NB;
   if (R0 >= n) return;
   double2 *A = W + (int64_t)b * stride;
-  load_block(Ab, A, n, R0, j0, jb);
-  if (tr != tc) load_block(Bb, A, n, S0, j0, jb);
-  __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
-  d4 accR[2][2], accI[2][2];
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y) accR[x][y] = accI[x][y] = d4{0.0, 0.0, 0.0, 0.0};
-  cgemm_nt(Ab, tr != tc ? Bb : Ab, wr, wc, li, lk, accR, accI);
+  // the tile's current values, fetched now so that their latency hides behind the product
+  double2 old[2][2][4];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -295,11 +411,27 @@ __global__ __launch_bounds__(256) void chol_update_kernel(double2 *W, int64_t st
       for (int r = 0; r < 4; ++r) {
         const int row = R0 + wr * 32 + x * 16 + lk + 4 * r;
         const int col = S0 + wc * 32 + y * 16 + li;
-        if (row < n && col <= row) {
-          double2 *p = A + (int64_t)row * n + col;
-          const double2 v = *p;
-          *p = make_double2(v.x - accR[x][y][r], v.y - accI[x][y][r]);
-        }
+        old[x][y][r] = (row < n && col <= row) ? A[(int64_t)row * n + col] : make_double2(0.0, 0.0);
+      }
+  d4 accR[2][2], accI[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) accR[x][y] = accI[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+  // W22 -= L21 L21^H: the chunk buffers live in the diagonal factor's LDS arrays
+  Chunk *ca = reinterpret_cast<Chunk *>(&Ab[0][0]);
+  Chunk *cb = reinterpret_cast<Chunk *>(&Bb[0][0]);
+  tile_product(A, n, R0, j0, n, A, n, S0, j0, n, tr != tc, jb, ca, cb, accR, accI);
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = R0 + wr * 32 + x * 16 + lk + 4 * r;
+        const int col = S0 + wc * 32 + y * 16 + li;
+        if (row < n && col <= row)
+          A[(int64_t)row * n + col] = make_double2(old[x][y][r].x - accR[x][y][r], old[x][y][r].y - accI[x][y][r]);
       }
   if (blockIdx.y == 0) {
     // the updated next diagonal block is in global memory, written by this workgroup:

@@ -211,7 +211,7 @@ def test_trln_real_input(ctx):
     assert np.max(np.abs(ctx.trln(pis) - ref)) <= 1e-10 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("n,col", [(40, 17), (200, 130)])
+@pytest.mark.parametrize("n,col", [(40, 17), (200, 130), (20, 0), (70, 63), (100, 79), (130, 64)])
 def test_trln_not_positive_definite_is_an_error(ctx, n, col):
     from paper_2505_06021_amd import rpa
     say(f"trln not SPD n={n} col={col}")
