@@ -423,6 +423,11 @@ __global__ __launch_bounds__(256) void chi0_f64_w2_kernel(Chi0Launch L) {
   const int M = mlo + ms < (int)a.M ? mlo + ms : (int)a.M;
   const int P0 = tr * TN, Q0 = tc * TN;
   const bool diag = (tr == tc);
+  // an off-diagonal tile of the last tile row with at most 32 valid rows (N not a multiple
+  // of 64): its waves split by point instead of by row half, wave (wr, wc) contracting
+  // rows P0 .. P0 + 31 of its column half for point wr, so the tile takes half the MFMA
+  // time of a full one.  Every output element sees the same products in the same order.
+  const bool half = !diag && P0 + TN / 2 >= N;
 
   const int tid = threadIdx.x;
   const int lrow = tid >> 4;   // 0..15: one row of the K step per 16 lanes
@@ -528,12 +533,78 @@ __global__ __launch_bounds__(256) void chi0_f64_w2_kernel(Chi0Launch L) {
     }
   };
 
+  // one K step of a half tile: point wr only, rows 0 .. 31 of the tile
+  auto contract_half = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int ks = 0; ks < KT / 4; ++ks) {
+      const int r = ks * 4 + lk;
+      double2 av[2], bv[2], bw[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) av[x] = lds[buf][0][r][x * 16 + li];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bv[y] = lds[buf][1][r][wc * 32 + y * 16 + li];
+      const double w = lw[buf][wr][r];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bw[y] = make_double2(w * bv[y].x, w * bv[y].y);
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          accR[0][x][y] = mfma(av[x].x, bw[y].x, accR[0][x][y]);
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          accI[0][x][y] = mfma(av[x].x, bw[y].y, accI[0][x][y]);
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          accR[0][x][y] = mfma(av[x].y, bw[y].y, accR[0][x][y]);
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          accI[0][x][y] = mfma(-av[x].y, bw[y].x, accI[0][x][y]);
+    }
+  };
+
   const int nsteps = M > mlo ? (M - mlo + KT - 1) / KT : 1;
   double2 *base = split == 0 ? a.out : a.partial + (int64_t)(split - 1) * a.split_stride;
   load(mlo);
   store(0);
   __syncthreads();
-  if (!diag) {
+  if (half) {
+    // a single point's second pair of waves only keeps the loads and barriers going
+    const bool act = wr == 0 || two;
+    for (int s = 0; s + 1 < nsteps; ++s) {
+      const int cur = s & 1;
+      load(mlo + (s + 1) * KT);
+      __builtin_amdgcn_sched_barrier(0);
+      if (act) contract_half(cur);
+      __builtin_amdgcn_sched_barrier(0);
+      store(cur ^ 1);
+      __syncthreads();
+    }
+    if (act) {
+      contract_half((nsteps - 1) & 1);
+      double2 *out = base + (int64_t)(wr == 0 ? p0 : p1) * a.out_stride;
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int P = P0 + x * 16 + lk + 4 * r;
+            const int Q = Q0 + wc * 32 + y * 16 + li;
+            if (P >= N || Q >= N) continue;
+            const double re = accR[0][x][y][r];
+            const double im = accI[0][x][y][r];
+            out[(int64_t)P * N + Q] = make_double2(re, im);
+            out[(int64_t)Q * N + P] = make_double2(re, -im);
+          }
+    }
+  } else if (!diag) {
     for (int s = 0; s + 1 < nsteps; ++s) {
       const int cur = s & 1;
       load(mlo + (s + 1) * KT);
