@@ -14,6 +14,7 @@
 // panels go to a double-buffered LDS tile.  Four waves each own a 32 x 32 sub-tile (2 x 2 MFMA blocks, Re and Im
 // accumulators).  Off-diagonal tiles also store their conjugate transpose, so the full
 // Hermitian matrix is produced from the lower-triangle work only.
+#include <algorithm>
 #include <cmath>
 
 #include "common.hpp"
@@ -851,13 +852,17 @@ __global__ __launch_bounds__(256) void split_reduce_kernel(const double2 *partia
 
 int32_t chi0_pick_ksplit(int64_t work, int64_t slots, int64_t M, int32_t max_split) {
   // fraction of the last round of workgroups that is busy, for 1..max_split splits; a
-  // split must keep at least 512 rows and costs ~2% for its extra reduction traffic
+  // split must keep at least 512 rows.  Each further split costs its partial planes'
+  // traffic and their reduction: about 2% of the contraction at M = 16128 rows (the
+  // 3x3x1 slab at N_aux 384), a share that falls as 1/M since the contraction grows with
+  // M and the planes do not
+  const double pen = std::min(0.02, 0.02 * 16128.0 / (double)std::max<int64_t>(M, 1));
   int best = 1;
   double best_eff = 0.0;
   for (int s = 1; s <= max_split; ++s) {
     if (s > 1 && M / s < 512) break;
     const double rounds = (double)(work * s) / (double)slots;
-    const double eff = rounds / std::ceil(rounds) * (1.0 - 0.02 * (s - 1));
+    const double eff = rounds / std::ceil(rounds) * (1.0 - pen * (s - 1));
     if (eff > best_eff + 1e-9) {
       best_eff = eff;
       best = s;
