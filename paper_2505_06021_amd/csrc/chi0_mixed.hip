@@ -314,6 +314,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
   // diagonal quadrants skip their strictly upper 16 x 16 block (each block summed
   // exactly as before); bit 2x + y of `on` marks the blocks a wave computes.
   int on = 0xf;
+  // paired kernel, an off-diagonal tile of the last tile row with at most 32 valid rows:
+  // the waves split by point instead of by row half (wave (wr, wc) contracts rows
+  // P0 .. P0 + 31 of its column half for point hp = wr into accumulator set 0), so the tile
+  // takes half the MFMA time; every output element sees the same products, flushes and
+  // order as in a full tile
+  const bool half = NP == 2 && !is_diag && P0 + TN / 2 >= N;
+  const int hp = wr;
+  if (half) wr = 0;
   if (is_diag) {
     if (wr == 0 && wc == 1) {
       wr = 1;
@@ -433,6 +441,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
       }
     }
   };
+  // one K step of a half tile (NP = 2 only): point hp, rows 0 .. 31
+  auto contract_half = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int ks = 0; ks < KT / 4; ++ks) {
+      const int r = ks * 4 + lk;
+      float2 av[2], bv[2], bw[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) av[x] = lds[buf][0][r][x * 16 + li];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bv[y] = lds[buf][1][r][wc * 32 + y * 16 + li];
+      const float wp = lw[buf][NP == 2 ? hp : 0][r];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bw[y] = make_float2(wp * bv[y].x, wp * bv[y].y);
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) accR[0][x][y] = mfma32(av[x].x, bw[y].x, accR[0][x][y]);
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) accI[0][x][y] = mfma32(av[x].x, bw[y].y, accI[0][x][y]);
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) accR[0][x][y] = mfma32(av[x].y, bw[y].y, accR[0][x][y]);
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) accI[0][x][y] = mfma32(-av[x].y, bw[y].x, accI[0][x][y]);
+    }
+  };
   auto flush = [&]() __attribute__((always_inline)) {
 #pragma unroll
     for (int p = 0; p < NP; ++p)
@@ -525,7 +564,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
       return;
     }
   }
-  auto run = [&](auto masked) __attribute__((always_inline)) {
+  // a single point's second pair of waves in a half tile only keeps the loads and
+  // barriers going
+  const bool hact = !half || hp == 0 || (NP == 2 && pon[NP - 1]);
+  auto run = [&](auto masked, auto halfc) __attribute__((always_inline)) {
+    constexpr bool HALF = decltype(halfc)::value;
     load(mlo);
     store(0);
     __syncthreads();
@@ -533,25 +576,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
       const int cur = s & 1;
       load(mlo + (s + 1) * KT);
       __builtin_amdgcn_sched_barrier(0);
-      contract(cur, masked);
+      if (HALF) {
+        if (hact) contract_half(cur);
+      } else {
+        contract(cur, masked);
+      }
       __builtin_amdgcn_sched_barrier(0);
       if ((s + 1) % FLUSH_STEPS == 0) flush();
       store(cur ^ 1);
       __syncthreads();
     }
-    contract((nsteps - 1) & 1, masked);
+    if (HALF) {
+      if (hact) contract_half((nsteps - 1) & 1);
+    } else {
+      contract((nsteps - 1) & 1, masked);
+    }
     flush();
   };
-  if (is_diag) run(std::integral_constant<bool, true>{});
-  else run(std::integral_constant<bool, false>{});
+  if (is_diag) run(std::integral_constant<bool, true>{}, std::integral_constant<bool, false>{});
+  else if (NP == 2 && half) run(std::integral_constant<bool, false>{}, std::integral_constant<bool, true>{});
+  else run(std::integral_constant<bool, false>{}, std::integral_constant<bool, false>{});
 
   double2 *base = split == 0 ? a.out : a.partial + (int64_t)(split - 1) * a.split_stride;
   const bool first = split == 0;   // the exact diagonal enters once
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
-    if (!pon[p]) continue;
-    double2 *out = base + (int64_t)pidx[p] * a.out_stride;
-    const double *dg = diag + (int64_t)pidx[p] * N;
+    // a half tile keeps its one point's sums in set 0
+    if (half && p > 0) break;
+    const int pt = half ? hp : p;
+    if (!(pt == 0 ? pon[0] : pon[NP - 1])) continue;
+    const int pid = pt == 0 ? pidx[0] : pidx[NP - 1];
+    double2 *out = base + (int64_t)pid * a.out_stride;
+    const double *dg = diag + (int64_t)pid * N;
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
