@@ -19,7 +19,8 @@ Steps (the paper's notation; "the paper" is arXiv:2505.06021):
    psi*_a(k) psi_i(k+q) (Sec. 2.2); B is the complex conjugate of that coefficient,
    B^P_ia = conj(C^{ai}_P), so that conj(B^P) B^Q = C^{ai}_P conj(C^{ai}_Q) keeps the
    paper's index order.  For synthetic coefficients B is the input itself.
-4. Pi = V^(1/2) chi0 V^(1/2)   (working equation, Z = v^(1/2) P^(0) v^(1/2); Algorithm 1).
+4. Pi = V^(1/2) chi0 V^(1/2)   (the symmetrised response of the working equation;
+   Algorithm 1, sandwich step).
 5. eps(q, omega) = ln det(1 - Pi) + Re Tr Pi, with ln det from the Cholesky factor of the
    Hermitian positive definite 1 - Pi: ln det = 2 sum ln L_ii.  The sign follows Eq. 1
    (sum_n Z^n/n = -ln(1 - Z)); Algorithm 1 prints the term with the opposite sign, which
