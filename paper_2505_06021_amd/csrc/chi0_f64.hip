@@ -494,10 +494,27 @@ __global__ __launch_bounds__(256) void chi0_f64_w2_kernel(Chi0Launch L) {
       lw[buf][1][lrow] = mv ? sw1 : 0.0;
     }
   };
-  // one K step of an off-diagonal tile for both points
-  auto contract = [&](int buf) __attribute__((always_inline)) {
+  // one K step of an off-diagonal tile for both points; with LOADS, the next step's
+  // global loads are spread over the four sub-steps (column group ks before sub-step ks)
+  // instead of issued together, so that no wave waits long for the address unit while
+  // its MFMA pipe idles
+  auto contract = [&](int buf, auto loads_tag, int m0next) __attribute__((always_inline)) {
+    constexpr bool LOADS = decltype(loads_tag)::value;
+    int64_t rowoff = 0;
+    if (LOADS) {
+      const int m = m0next + lrow;
+      mv = m < M;
+      const int mc = mv ? m : 0;
+      sw0 = wrow0[mc];
+      sw1 = wrow1[mc];
+      rowoff = (int64_t)mc * N;
+    }
 #pragma unroll
     for (int ks = 0; ks < KT / 4; ++ks) {
+      if (LOADS) {
+        sa[ks] = load_b<CPLX_B>(bbase, rowoff + pcol[ks]);
+        sb[ks] = load_b<CPLX_B>(bbase, rowoff + qcol[ks]);
+      }
       const int r = ks * 4 + lk;
       double2 av[2], bv[2];
 #pragma unroll
@@ -608,14 +625,12 @@ __global__ __launch_bounds__(256) void chi0_f64_w2_kernel(Chi0Launch L) {
   } else if (!diag) {
     for (int s = 0; s + 1 < nsteps; ++s) {
       const int cur = s & 1;
-      load(mlo + (s + 1) * KT);
-      __builtin_amdgcn_sched_barrier(0);
-      contract(cur);
+      contract(cur, std::integral_constant<bool, true>{}, mlo + (s + 1) * KT);
       __builtin_amdgcn_sched_barrier(0);
       store(cur ^ 1);
       __syncthreads();
     }
-    contract((nsteps - 1) & 1);
+    contract((nsteps - 1) & 1, std::integral_constant<bool, false>{}, 0);
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       if (p == 1 && !two) break;
