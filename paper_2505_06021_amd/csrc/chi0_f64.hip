@@ -389,29 +389,38 @@ __global__ __launch_bounds__(256) void chi0_f64_w2_kernel(Chi0Launch L) {
       gbase = L.begin[k];
     }
 
-  // one-dimensional grid per group, off-diagonal tiles of every (pair, split) first and
-  // the shorter diagonal tiles last, so the last round of workgroups is made of short ones
+  // One-dimensional grid per group.  Work items run cluster by cluster, a cluster being
+  // one (tile, row split) and its members the launch's pairs, which all stage the same
+  // panel rows; the off-diagonal clusters of every split come first and the shorter
+  // diagonal ones last, so the last round of workgroups is made of short ones.  The
+  // hardware hands workgroup g to XCD g mod 8 (up to the group's base offset, the same for
+  // every workgroup of the group), so the items are dealt out in chunks of 8 consecutive
+  // ones: workgroups g = 64 j + x + 8 o (o = 0..7) take items 8 (8 j + x) + o, and the 8
+  // workgroups of a chunk run side by side on one XCD, where its L2 serves the panels
+  // they share; each XCD still gets every 8th chunk, hence the same mix of long and short
+  // tiles.  The last nw mod 64 items keep their own order.
   const int T = (a.N + TN - 1) / TN;
   const int noff = T * (T - 1) / 2;
-  const int64_t nunits = (int64_t)a.npairs * a.ksplit;
+  const int64_t np = a.npairs;
+  const int64_t ncl_off = (int64_t)noff * a.ksplit;   // off-diagonal clusters
+  const int64_t nw = (ncl_off + (int64_t)T * a.ksplit) * np;
   const int64_t g = (int64_t)blockIdx.x - gbase;
-  int tr, tc, pair, split;
-  if (g < (int64_t)noff * nunits) {
-    const int k = (int)(g % noff);               // strictly lower tile k: row r > column c
-    const int64_t u = g / noff;
+  const int64_t w = g < nw / 64 * 64 ? ((g >> 6) * 8 + (g & 7)) * 8 + ((g >> 3) & 7) : g;
+  const int64_t c = w / np;
+  const int pair = (int)(w % np);
+  int tr, tc, split;
+  if (c < ncl_off) {
+    const int k = (int)(c % noff);   // strictly lower tile k: row r > column c
     int r = (int)((1.0 + sqrt(1.0 + 8.0 * (double)k)) * 0.5);
     while (r * (r - 1) / 2 > k) --r;
     while ((r + 1) * r / 2 <= k) ++r;
     tr = r;
     tc = k - r * (r - 1) / 2;
-    pair = (int)(u % a.npairs);
-    split = (int)(u / a.npairs);
+    split = (int)(c / noff);
   } else {
-    const int64_t h = g - (int64_t)noff * nunits;
+    const int64_t h = c - ncl_off;
     tr = tc = (int)(h % T);
-    const int64_t u = h / T;
-    pair = (int)(u % a.npairs);
-    split = (int)(u / a.npairs);
+    split = (int)(h / T);
   }
   const int p0 = a.pairs[2 * pair];
   const int p1s = a.pairs[2 * pair + 1];

@@ -237,9 +237,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
   constexpr int RPI = 16;
   constexpr int NPASS = KT / RPI;
 
-  // NP = 1: grid (tile, point, split).  NP = 2: a one-dimensional grid with the
-  // off-diagonal tiles of every (pair, split) first and the shorter diagonal tiles last,
-  // so the last round of workgroups is made of short ones.
+  // NP = 1: grid (tile, point, split).  NP = 2: the one-dimensional grid of the paired
+  // FP64 kernel (clusters of the pairs of one (tile, split), off-diagonal ones first, dealt
+  // out to the XCDs in chunks of 8 items).
   int tr, tc, unit, split, nsplit;
   if constexpr (NP == 1) {
     tile_of((int)blockIdx.x, tr, tc);
@@ -249,24 +249,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
   } else {
     const int T = (a.N + TN - 1) / TN;
     const int noff = T * (T - 1) / 2;
-    const int64_t nunits = (int64_t)a.npairs * a.ksplit;
+    const int64_t np = a.npairs;
+    const int64_t ncl_off = (int64_t)noff * a.ksplit;   // off-diagonal (tile, split) clusters
+    const int64_t nw = (ncl_off + (int64_t)T * a.ksplit) * np;
     const int64_t g = (int64_t)blockIdx.x - gbase;
-    int64_t u;
-    if (g < (int64_t)noff * nunits) {
-      const int k = (int)(g % noff);   // strictly lower tile k: row r > column c
-      u = g / noff;
+    const int64_t w = g < nw / 64 * 64 ? ((g >> 6) * 8 + (g & 7)) * 8 + ((g >> 3) & 7) : g;
+    const int64_t c = w / np;
+    unit = (int)(w % np);
+    if (c < ncl_off) {
+      const int k = (int)(c % noff);   // strictly lower tile k: row r > column c
       int r = (int)((1.0 + sqrt(1.0 + 8.0 * (double)k)) * 0.5);
       while (r * (r - 1) / 2 > k) --r;
       while ((r + 1) * r / 2 <= k) ++r;
       tr = r;
       tc = k - r * (r - 1) / 2;
+      split = (int)(c / noff);
     } else {
-      const int64_t h = g - (int64_t)noff * nunits;
+      const int64_t h = c - ncl_off;
       tr = tc = (int)(h % T);
-      u = h / T;
+      split = (int)(h / T);
     }
-    unit = (int)(u % a.npairs);
-    split = (int)(u / a.npairs);
     nsplit = a.ksplit;
   }
   int pidx[NP];
