@@ -10,6 +10,12 @@ there; the full grids are checked the same way with every frequency of the q).
 FP64: |d eps| <= 1e-10 scale.  Reduced precision: |d eps| <= 1e-8 scale (FP32 and
 split-FP16) and 2e-7 scale (split-BF16); eps at these sizes is O(1e3 - 1e4) Ha at the
 lowest frequency.
+
+The largest auxiliary basis of the paper's basis-convergence study (Sec. 4, N_aux 4070: 64
+tile rows of 64 with a 38-row tail, Pi and the Cholesky at that size) is checked against
+the live oracle on a Gamma-only system with a short contraction (M = 128 rows), so that
+the oracle finishes in seconds: E and the eps grid in FP64, chi0 element by element, and
+the reduced precisions on the eps grid with the tolerances above.
 """
 import json
 import os
@@ -59,3 +65,31 @@ def test_sampled_points_full_size(ctx, name, make, prec):
     rel = np.abs(got - ref) / scale
     say(f"  eps {got}  err / scale {rel}")
     assert np.all(rel <= TOL[prec])
+
+
+def rel_rows(a, b):
+    """Element by element: max_PQ |a_PQ - b_PQ| / max_Q' |b_PQ'| (each row's own scale)."""
+    return float(np.max(np.abs(a - b).max(axis=1) / np.abs(b).max(axis=1)))
+
+
+@pytest.fixture(scope="module")
+def aux4070():
+    from oracle import rpa_oracle as orc
+    say("oracle at N_aux 4070")
+    s = inputs.make_system("aux4070", (1, 1, 1), 4, 32, 4070, 2, 4070, is_complex=True)
+    E_ref, g_ref = orc.energy(s)
+    chi_ref = orc.chi0(s, 0, s.omega[1])
+    return s, E_ref, g_ref, chi_ref
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
+def test_largest_paper_aux_basis(ctx, aux4070, prec):
+    s, E_ref, g_ref, chi_ref = aux4070
+    say(f"N_aux 4070 prec={prec}")
+    E, eps = ctx.energy(s, prec=prec)
+    scale = np.max(np.abs(g_ref))
+    assert np.max(np.abs(eps - g_ref)) <= TOL[prec] * scale
+    if prec == 0:
+        assert abs(E - E_ref) <= 1e-10 * abs(E_ref)
+        chi = ctx.chi0(s, 0, s.omega[1])
+        assert rel_rows(chi, chi_ref) <= 1e-12
