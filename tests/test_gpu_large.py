@@ -15,7 +15,10 @@ The largest auxiliary basis of the paper's basis-convergence study (Sec. 4, N_au
 tile rows of 64 with a 38-row tail, Pi and the Cholesky at that size) is checked against
 the live oracle on a Gamma-only system with a short contraction (M = 128 rows), so that
 the oracle finishes in seconds: E and the eps grid in FP64, chi0 element by element, and
-the reduced precisions on the eps grid with the tolerances above.
+the reduced precisions on the eps grid with the tolerances above.  The largest regular
+k-grid of the paper's studies (17 x 17, Sec. 4: 289 k- and q-points, so 289 slabs, 289 weight
+rows and k (+) q rows that wrap in both directions) is checked the same way with small
+bands and N_aux.
 """
 import json
 import os
@@ -93,3 +96,23 @@ def test_largest_paper_aux_basis(ctx, aux4070, prec):
         assert abs(E - E_ref) <= 1e-10 * abs(E_ref)
         chi = ctx.chi0(s, 0, s.omega[1])
         assert rel_rows(chi, chi_ref) <= 1e-12
+
+
+@pytest.fixture(scope="module")
+def grid17():
+    from oracle import rpa_oracle as orc
+    say("oracle on the 17x17x1 grid")
+    s = inputs.make_system("k17", (17, 17, 1), 2, 4, 40, 2, 1717, is_complex=True)
+    E_ref, g_ref = orc.energy(s)
+    return s, E_ref, g_ref
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_largest_paper_k_grid(ctx, grid17, prec):
+    s, E_ref, g_ref = grid17
+    say(f"17x17x1 grid prec={prec}")
+    E, eps = ctx.energy(s, prec=prec)
+    for q in range(s.nq):
+        assert np.max(np.abs(eps[q] - g_ref[q])) <= TOL[prec] * np.max(np.abs(g_ref[q])), q
+    if prec == 0:
+        assert abs(E - E_ref) <= 1e-10 * abs(E_ref)
